@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark: emulated FP64 GEMM on INT8 MFMA (MI355X), one GPU.
+
+A step is one emulated DGEMM C = A B over resident FP64 inputs: exponent
+scans and INT8 digit slicing of both operands, the s(s+1)/2 slice products
+on INT8 MFMA, and the fused FP64 recombination.  Default workload: the
+emulated-DGEMM sweep's largest square size m = n = k = 16384, entries
+a = u exp(phi g) with phi = 4, at the full slice count s = 9 (the count at
+which the normwise error against a double-double product is at most 1e-15
+for phi <= 4).  value = 2 m n k / (seconds per step) / 1e12 in FP64-equivalent
+TFLOP/s.
+
+Printed on one JSON line, beside value: the slice-product kernel's roofline
+(INT8 MFMA operations per launch over its event-timed duration, against the
+dense INT8 peak), the CPU oracle timed on a bounded sample of the same
+product (and the sampled block checked bit for bit), the normwise error of
+that block against a double-double reference, native FP64 DGEMM and LU
+(torch / ROCm libraries) on the same GPU, and the plain-method LU solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_INT8_OPS = 5.0e15     # MI355X dense INT8 MFMA, ops/s
+PEAK_HBM = 8.0e12          # MI355X HBM3E, bytes/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pairs(s, t):
+    return sum(1 for i in range(1, s + 1) for j in range(1, s + 1) if i + j <= t)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--s", type=int, default=9)
+    ap.add_argument("--phi", type=float, default=4.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sample-rows", type=int, default=256)
+    ap.add_argument("--sample-cols", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-native", action="store_true", help="skip native FP64")
+    ap.add_argument("--no-lu", action="store_true", help="skip the LU solve")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the emulated GEMM and LU run on a "
+              "single MI355X; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import matgen
+    import paper_2509_23565_amd as emu
+
+    torch.cuda.set_device(0)
+    n, s, phi = args.n, args.s, args.phi
+    t = s + 1
+    P = pairs(s, t)
+
+    log(f"generating A, B: {n}x{n}, phi={phi}, seed={args.seed}")
+    A = matgen.phi_matrix(n, n, phi, seed=args.seed, substream=0)
+    B = matgen.phi_matrix(n, n, phi, seed=args.seed, substream=1)
+    Ag = emu.colmajor(A)
+    Bg = emu.colmajor(B)
+    Cg = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    torch.cuda.synchronize()
+
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        emu.dgemm(Ag, Bg, Cg, nslices=s)
+    torch.cuda.synchronize()
+
+    log(f"timed x{args.steps}")
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    emu.emu_profile_start()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        emu.dgemm(Ag, Bg, Cg, nslices=s)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    emu.emu_profile_stop()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    gemm_ms, gemm_cnt = emu.profile_read(emu.PROF_GEMM)
+    slice_ms, slice_cnt = emu.profile_read(emu.PROF_SLICE)
+    gemm_avg = gemm_ms / max(gemm_cnt, 1)
+    slice_avg = slice_ms / max(slice_cnt, 1)
+    flops_equiv = 2.0 * n * n * n
+    value = flops_equiv / (ms_step * 1e-3) / 1e12
+    int8_ops = 2.0 * n * n * n * P
+    achieved = int8_ops / (gemm_avg * 1e-3) / 1e12
+    log(f"step {ms_step:.3f} ms -> {value:.1f} TFLOP/s-equiv; slice-GEMM kernel "
+        f"{gemm_avg:.3f} ms ({achieved:.0f} TOP/s INT8); slicing {slice_avg:.3f} ms")
+
+    result = {
+        "metric": "emulated-DGEMM TFLOP/s-equiv + LU solve time at <=1e-15 error vs native FP64",
+        "value": round(value, 3),
+        "unit": "TFLOP/s-equiv (FP64)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"emulated DGEMM m=n=k={n}, a=u*exp(phi*g) phi={phi}, "
+                        f"s={s} INT8 slices per operand, t=s+1 ({P} slice products)",
+            "m": n, "n": n, "k": n, "nslices": s, "t": t, "phi": phi,
+            "seed": args.seed, "alpha": 1.0, "beta": 0.0,
+        },
+        "roofline": {
+            "kernel": "k_slicegemm (INT8 MFMA slice products + FP64 recombination)",
+            "bound": "mfma",
+            "achieved": round(achieved, 2),
+            "peak": PEAK_INT8_OPS / 1e12,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / (PEAK_INT8_OPS / 1e12), 4),
+            "traffic": None,
+            "avg_ms": round(gemm_avg, 4),
+            "launches": gemm_cnt,
+            "algorithmic_ops_per_launch": int8_ops,
+        },
+        "slicing": {
+            "avg_ms": round(slice_avg, 4),
+            "algorithmic_bytes": 2 * n * n * (8 + s),
+            "GB_s": round(2 * n * n * (8 + s) / (slice_avg * 1e-3) / 1e9, 1),
+        },
+    }
+
+    # ---------------------------------------------------- sampled oracle leg
+    g = matgen.rng(args.seed, 99)
+    rows = np.sort(g.choice(n, size=min(args.sample_rows, n), replace=False))
+    cols = np.sort(g.choice(n, size=min(args.sample_cols, n), replace=False))
+    Cblock = Cg[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")]
+    Cblock = Cblock.cpu().numpy()
+    if not args.no_cpu:
+        import oracle
+        from threadpoolctl import threadpool_info
+        As = np.asfortranarray(A[rows, :])
+        Bs = np.asfortranarray(B[:, cols])
+        log(f"oracle on a {len(rows)}x{len(cols)} block of C ...")
+        t0 = time.perf_counter()
+        ref = oracle.dgemm_emu(As, Bs, s)
+        t_cpu = time.perf_counter() - t0
+        exact = bool(np.array_equal(np.ascontiguousarray(Cblock).view(np.int64),
+                                    np.ascontiguousarray(ref).view(np.int64)))
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
+        result["cpu_baseline"] = {
+            "value": round(2.0 * len(rows) * len(cols) * n / t_cpu / 1e12, 6),
+            "unit": "TFLOP/s-equiv (FP64)",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"C[{len(rows)} sampled rows, {len(cols)} sampled columns] of "
+                      f"the same product: oracle exponent scan and slicing of those "
+                      f"rows of A and columns of B, {P} slice products, "
+                      f"recombination; {t_cpu:.1f} s",
+            "seconds": round(t_cpu, 2),
+        }
+        # accuracy of a smaller block against the double-double product
+        r2 = rows[:16]
+        ref_dd = oracle.dgemm_dd(np.asfortranarray(A[r2, :]), Bs)
+        Cnat = (torch.as_tensor(A[r2, :], device="cuda") @ torch.as_tensor(Bs, device="cuda")).cpu().numpy()
+        result["parity"] = {
+            "sampled_block": f"{len(rows)}x{len(cols)}",
+            "bit_exact_vs_oracle": exact,
+            "eta_F_vs_dd": oracle.rel_err_fro(Cblock[:16], ref_dd),
+            "eta_F_native_fp64_vs_dd": oracle.rel_err_fro(Cnat, ref_dd),
+            "dd_block": f"{len(r2)}x{len(cols)}",
+        }
+        log(f"oracle block {t_cpu:.1f} s, bit-exact={exact}, "
+            f"eta_F={result['parity']['eta_F_vs_dd']:.2e}")
+        del As, Bs, ref
+
+    # ---------------------------------------------------------- native FP64
+    if not args.no_native:
+        Anat = Ag.contiguous()
+        Bnat = Bg.contiguous()
+        for _ in range(2):
+            Cn = Anat @ Bnat
+        torch.cuda.synchronize()
+        reps = 3
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            Cn = Anat @ Bnat
+        e1.record()
+        torch.cuda.synchronize()
+        nat_ms = e0.elapsed_time(e1) / reps
+        result["native_fp64"] = {
+            "dgemm_ms": round(nat_ms, 3),
+            "dgemm_tflops": round(flops_equiv / (nat_ms * 1e-3) / 1e12, 2),
+            "emulated_speedup": round(nat_ms / ms_step, 3),
+            "library": "torch.matmul float64 (ROCm BLAS)",
+        }
+        del Anat, Bnat, Cn
+        log(f"native FP64 DGEMM {nat_ms:.2f} ms")
+    del Ag, Bg, Cg
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------- plain-method LU solve
+    if not args.no_lu:
+        import oracle
+        nl = 1024
+        Al = matgen.uniform(nl, nl, seed=0, substream=0)
+        bl = matgen.uniform(nl, 1, seed=0, substream=1)
+        times = []
+        for rep in range(4):
+            Alg = emu.colmajor(Al)
+            xg = emu.colmajor(bl)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ipiv, info = emu.dgetrf(Alg, nb=64, nslices=7)
+            emu.dgetrs(Alg, ipiv, xg)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        x = xg.cpu().numpy()
+        eta = oracle.backward_error(Al, x, bl) if not args.no_cpu else None
+        # native FP64 LU on the same GPU
+        At = torch.as_tensor(Al, device="cuda")
+        bt = torch.as_tensor(bl, device="cuda")
+        nt = []
+        for rep in range(4):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            LUt, pv = torch.linalg.lu_factor(At)
+            xt = torch.linalg.lu_solve(LUt, pv, bt)
+            e1.record()
+            torch.cuda.synchronize()
+            nt.append(e0.elapsed_time(e1))
+        eta_nat = oracle.backward_error(Al, xt.cpu().numpy(), bl) if not args.no_cpu else None
+        result["lu_solve"] = {
+            "workload": "n=1024 U(-1,1), 1 RHS, nb=64, s=7, seed 0",
+            "emulated_ms": round(float(np.median(times[1:])), 3),
+            "eta_inf": eta,
+            "native_ms": round(float(np.median(nt[1:])), 3),
+            "native_eta_inf": eta_nat,
+            "native_library": "torch.linalg.lu_factor/lu_solve float64",
+        }
+        log(f"LU n=1024: emulated {result['lu_solve']['emulated_ms']} ms eta={eta}, "
+            f"native {result['lu_solve']['native_ms']} ms")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

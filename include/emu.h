@@ -1,0 +1,177 @@
+/*
+ * emu.h - FP64 matrix multiply emulated with INT8 slices on AMD MI355X
+ * (gfx950), and the partially pivoted LU solver whose Schur-complement update
+ * uses it.
+ *
+ * Method (arXiv 2509.23565, section "Emulation of FP64 and INT8 Splitting",
+ * eqns (1)-(2)): each operand is split into s slices, the product is the sum
+ * of the slice products A_i B_j, and products with i + j > t are dropped.
+ * Readings this library fixes where the paper is silent:
+ *   - a slice is an INT8 digit: 7 magnitude bits and the element's sign,
+ *     q in [-127, 127];
+ *   - A is scaled per row, B per column, by 2^-e where e is the frexp exponent
+ *     of the line's largest magnitude (0 for an all-zero line);
+ *   - digits are truncated toward zero: x 2^-e = sum_i q_i 128^-i + r,
+ *     |r| < 128^-s;
+ *   - t = s + 1 (s(s+1)/2 slice products) unless stated otherwise;
+ *   - slice products are exact: D_g = sum_{i+j=g} A_i B_j accumulated in
+ *     INT32 inside K-chunks short enough that no INT32 sum can overflow,
+ *     and in INT64 across chunks;
+ *   - recombination in one fixed order: S = 0; for g = t down to 2:
+ *     S = fl(S + D_g 2^-7g); X = S 2^(e_p + f_q); C = fma(alpha, X, beta C)
+ *     (beta = 0: fma(alpha, X, 0), C not read).  Results therefore do not
+ *     depend on tile shapes or launch configuration.
+ *   - a row of A or a column of B holding Inf or NaN makes the matching row
+ *     or column of C NaN and sets EMU_STATUS_NONFINITE in the status word.
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major FP64 in DEVICE memory with leading
+ *     dimensions; pivots and info are DEVICE int32; the caller owns every
+ *     buffer passed in, the library never frees or retains them;
+ *   - dimensions are int; all index arithmetic inside is 64-bit;
+ *   - calls are asynchronous on the calling thread's current stream (see
+ *     emu_set_stream) unless stated otherwise; the library's own scratch
+ *     memory (digit planes, exponents, partial sums) is allocated on first
+ *     use, grown when a larger problem arrives (after synchronizing the
+ *     stream) and released by emu_finalize;
+ *   - return value 0 on success; -i if argument i is invalid (LAPACK
+ *     xerbla style, counting from 1); a positive EMU_ERR_* code otherwise.
+ *     emu_last_error() describes the last failure of the calling thread.
+ */
+#ifndef EMU_H
+#define EMU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMU_SUCCESS            0
+#define EMU_ERR_HIP            1001  /* a HIP runtime call failed */
+#define EMU_ERR_WORKSPACE      1002  /* scratch allocation failed */
+#define EMU_ERR_UNSUPPORTED    1003  /* valid request this build cannot run */
+
+#define EMU_STATUS_NONFINITE   1     /* an emulated GEMM met Inf/NaN input */
+
+#define EMU_MAX_SLICES         9     /* GPU slice-count range is 1..9 */
+
+/* Library version as major*10000 + minor*100 + patch. */
+int emu_version(void);
+
+/* Initialise the HIP device state for the current device.  Optional: every
+ * entry point initialises on first use. */
+int emu_init(void);
+
+/* Release all scratch memory held by the library (all devices it touched).
+ * Synchronizes the library streams first. */
+int emu_finalize(void);
+
+/* Set the HIP stream (hipStream_t passed as void*) used by later calls from
+ * the calling thread; NULL selects the default (null) stream. */
+int emu_set_stream(void *hip_stream);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *emu_last_error(void);
+
+/* Synchronize the current stream and return, in *status, the OR of the
+ * EMU_STATUS_* bits raised since the previous call (then cleared). */
+int emu_status(int *status);
+
+/* Kernel-time profiling on the calling thread's stream.  emu_profile_start
+ * clears earlier records and makes every later call bracket its kernel
+ * groups with HIP events on the stream they run on; emu_profile_stop ends
+ * recording; emu_profile_read waits for the recorded events and returns the
+ * summed milliseconds and the number of launches of one group:
+ * EMU_PROF_SLICE (exponent scans and digit slicing of both operands) or
+ * EMU_PROF_GEMM (the slice-product GEMM with its recombination epilogue).
+ * Argument numbers: kind=1 total_ms=2 count=3. */
+#define EMU_PROF_SLICE 0
+#define EMU_PROF_GEMM  1
+int emu_profile_start(void);
+int emu_profile_stop(void);
+int emu_profile_read(int kind, double *total_ms, int *count);
+
+/*
+ * emu_dgemm: C <- alpha * A B + beta * C, A m x k (lda >= max(1,m)),
+ * B k x n (ldb >= max(1,k)), C m x n (ldc >= max(1,m)), no transposes,
+ * emulated with nslices INT8 slices per operand and threshold t = s + 1
+ * (paper: emulation section, eqns (1)-(2) and the truncation threshold).
+ * nslices must lie in 1..EMU_MAX_SLICES.
+ * Quick returns as in BLAS: m = 0 or n = 0 does nothing; k = 0 or
+ * alpha = 0 gives C <- beta C (C not read when beta = 0).
+ * Argument numbers for errors: m=1 n=2 k=3 alpha=4 A=5 lda=6 B=7 ldb=8
+ * beta=9 C=10 ldc=11 nslices=12.
+ */
+int emu_dgemm(int m, int n, int k, double alpha, const double *A, int lda,
+              const double *B, int ldb, double beta, double *C, int ldc,
+              int nslices);
+
+/*
+ * emu_dgemm_t: emu_dgemm with an explicit truncation threshold t (the
+ * paper's t: products A_i B_j with i + j > t are dropped).  Supported:
+ * t = s + 1 for s in 1..9 and t = 2s (all s^2 products) for s in 1..5.
+ * Argument 13 is t.
+ */
+int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
+                const double *B, int ldb, double beta, double *C, int ldc,
+                int nslices, int t);
+
+/*
+ * emu_dgetrf: PA = LU of the m x n matrix A (lda >= max(1,m)) in place,
+ * right-looking blocked with block size nb (nb <= 0 selects 64), partial
+ * pivoting (paper: solvers section, eqns (5)-(8)).  Per block column:
+ * FP64 panel factorization (first row of largest magnitude is the pivot;
+ * the column below is scaled by the reciprocal of the pivot, or divided
+ * when |pivot| < DBL_MIN); the panel's interchanges applied to the other
+ * columns; FP64 unit-lower triangular solve for U12; then the Schur update
+ * A22 <- A22 - L21 U12 as an emulated GEMM with nslices slices
+ * (nslices in 1..EMU_MAX_SLICES, threshold t = s + 1).
+ * ipiv (device, min(m,n) int32) receives 1-based row interchanges in
+ * LAPACK order.  *info (device int32) receives 0, or i > 0 when U(i,i) is
+ * exactly zero (the first such i); the factorization still completes.
+ * Argument numbers: m=1 n=2 A=3 lda=4 ipiv=5 info=6 nb=7 nslices=8.
+ */
+int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info,
+               int nb, int nslices);
+
+/*
+ * emu_dgetrs: solve A X = B (no transpose) with the factors of emu_dgetrf:
+ * row interchanges, forward substitution with unit L, back substitution
+ * with U, all FP64 (paper: eqn (5)).  LU n x n (lda >= max(1,n)), ipiv
+ * device int32[n], B n x nrhs (ldb >= max(1,n)) overwritten with X.
+ * Argument numbers: n=1 nrhs=2 LU=3 lda=4 ipiv=5 B=6 ldb=7.
+ */
+int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
+               double *B, int ldb);
+
+/*
+ * emu_debug_slices: expose the exponent scan and digit slicing of one
+ * operand, for bit-exact checks.  X is rows x cols column-major (ldx).
+ * by_rows = 1 scales per row (the A side), 0 per column (the B side).
+ * exps (device int32[by_rows ? rows : cols]) receives e (0 for zero or
+ * non-finite lines; non-finite lines also get flags bit 0 in nonfinite,
+ * device int32[same length], may be NULL).  digits (device int8) receives
+ * nslices planes, plane i (0-based) holding digit i+1 of every element in
+ * the same column-major rows x cols layout with leading dimension rows.
+ */
+int emu_debug_slices(int rows, int cols, const double *X, int ldx, int by_rows,
+                     int nslices, int *exps, int *nonfinite, int8_t *digits);
+
+/*
+ * emu_debug_products: the exact slice-product sums D_g, g = 2..t, of the
+ * emulated product of A (m x k) and B (k x n) with nslices slices and
+ * threshold t, computed by the same MFMA kernels as emu_dgemm_t.  D (device
+ * int64) receives t-1 planes, plane g-2 being D_g as an m x n column-major
+ * matrix with leading dimension m.
+ */
+int emu_debug_products(int m, int n, int k, const double *A, int lda,
+                       const double *B, int ldb, int nslices, int t,
+                       int64_t *D);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMU_H */

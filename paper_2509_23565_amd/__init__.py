@@ -1,0 +1,250 @@
+"""Python binding of libemu (include/emu.h): FP64 GEMM emulated with INT8
+slices on MI355X, and the LU solver that uses it for its Schur update.
+
+Two layers:
+
+* the raw C-ABI functions under their C names (``emu_dgemm``, ``emu_dgetrf``,
+  ``emu_dgetrs``, ...), which take integer device addresses and sizes and
+  return the library's status code;
+* thin torch conveniences (``dgemm``, ``dgetrf``, ``dgetrs``, ...), which only
+  marshal arguments: a matrix is a float64 CUDA tensor of shape (rows, cols)
+  with stride (1, ld) (column-major; ``colmajor`` builds one), and the call
+  runs on torch's current stream.
+
+Every computation runs in the HIP library.  There is no fallback: if
+libemu.so is missing or does not load, every call raises ``EmuError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "EmuError", "lib", "library_path", "EMU_MAX_SLICES",
+    "emu_version", "emu_init", "emu_finalize", "emu_set_stream", "emu_last_error",
+    "emu_status", "emu_dgemm", "emu_dgemm_t", "emu_dgetrf", "emu_dgetrs",
+    "emu_debug_slices", "emu_debug_products", "emu_profile_start",
+    "emu_profile_stop", "emu_profile_read", "profile_read", "PROF_SLICE", "PROF_GEMM",
+    "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
+    "status",
+]
+
+EMU_MAX_SLICES = 9
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libemu.so")
+
+
+class EmuError(RuntimeError):
+    pass
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+_SIGNATURES = {
+    "emu_version": ([], _I),
+    "emu_init": ([], _I),
+    "emu_finalize": ([], _I),
+    "emu_set_stream": ([_P], _I),
+    "emu_last_error": ([], ctypes.c_char_p),
+    "emu_status": ([ctypes.POINTER(_I)], _I),
+    "emu_dgemm": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
+    "emu_dgemm_t": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I, _I], _I),
+    "emu_dgetrf": ([_I, _I, _P, _I, _P, _P, _I, _I], _I),
+    "emu_dgetrs": ([_I, _I, _P, _I, _P, _P, _I], _I),
+    "emu_debug_slices": ([_I, _I, _P, _I, _I, _I, _P, _P, _P], _I),
+    "emu_debug_products": ([_I, _I, _I, _P, _I, _P, _I, _I, _I, _P], _I),
+    "emu_profile_start": ([], _I),
+    "emu_profile_stop": ([], _I),
+    "emu_profile_read": ([_I, ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libemu.so (raises EmuError when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise EmuError(f"{library_path} is not built; run "
+                           "`python -m paper_2509_23565_amd.build`")
+        try:
+            L = ctypes.CDLL(library_path)
+        except OSError as e:  # pragma: no cover - depends on the machine
+            raise EmuError(f"cannot load {library_path}: {e}") from e
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _raw(name):
+    def call(*args):
+        return getattr(lib(), name)(*args)
+    call.__name__ = name
+    return call
+
+
+emu_version = _raw("emu_version")
+emu_init = _raw("emu_init")
+emu_finalize = _raw("emu_finalize")
+emu_set_stream = _raw("emu_set_stream")
+emu_status = _raw("emu_status")
+emu_dgemm = _raw("emu_dgemm")
+emu_dgemm_t = _raw("emu_dgemm_t")
+emu_dgetrf = _raw("emu_dgetrf")
+emu_dgetrs = _raw("emu_dgetrs")
+emu_debug_slices = _raw("emu_debug_slices")
+emu_debug_products = _raw("emu_debug_products")
+emu_profile_start = _raw("emu_profile_start")
+emu_profile_stop = _raw("emu_profile_stop")
+emu_profile_read = _raw("emu_profile_read")
+
+PROF_SLICE = 0
+PROF_GEMM = 1
+
+
+def profile_read(kind: int):
+    """(total milliseconds, launches) of one profiled kernel group."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int(0)
+    _check(emu_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(cnt)),
+           "emu_profile_read")
+    return ms.value, cnt.value
+
+
+def emu_last_error() -> str:
+    v = lib().emu_last_error()
+    return v.decode() if v else ""
+
+
+def _check(rc: int, name: str) -> None:
+    if rc != 0:
+        raise EmuError(f"{name} returned {rc}: {emu_last_error()}")
+
+
+# ------------------------------------------------------------------ torch
+def _torch():
+    import torch
+    return torch
+
+
+def _bind_stream() -> None:
+    torch = _torch()
+    _check(emu_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "emu_set_stream")
+
+
+def colmajor(x, device="cuda"):
+    """float64 column-major device tensor (shape (rows, cols), stride (1, rows))
+    from a NumPy array or tensor."""
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.dim() == 1:
+        t = t[:, None]
+    out = torch.empty((t.shape[1], t.shape[0]), dtype=torch.float64, device=device).t()
+    out.copy_(t)
+    return out
+
+
+def _mat(t, name):
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2:
+        raise EmuError(f"{name}: expected a 2-D float64 CUDA tensor")
+    rows, cols = t.shape
+    if cols > 1 and rows > 0 and t.stride(0) != 1:
+        raise EmuError(f"{name}: must be column-major (stride(0) == 1)")
+    ld = t.stride(1) if cols > 1 else max(rows, 1)
+    return t.data_ptr(), max(ld, 1)
+
+
+def dgemm(A, B, C=None, alpha=1.0, beta=0.0, nslices=7, t=None):
+    """C <- alpha * emul(A @ B) + beta * C (column-major float64 tensors)."""
+    torch = _torch()
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise EmuError("dgemm: inner dimensions differ")
+    if C is None:
+        C = torch.empty((n, m), dtype=torch.float64, device=A.device).t()
+        if beta != 0.0:
+            raise EmuError("dgemm: beta != 0 needs C")
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    _bind_stream()
+    if t is None:
+        rc = emu_dgemm(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                       int(nslices))
+    else:
+        rc = emu_dgemm_t(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                         int(nslices), int(t))
+    _check(rc, "emu_dgemm")
+    return C
+
+
+def dgetrf(A, nb=64, nslices=7):
+    """In-place LU of A; returns (ipiv, info) as int32 device tensors."""
+    torch = _torch()
+    m, n = A.shape
+    pa, lda = _mat(A, "A")
+    ipiv = torch.zeros(max(min(m, n), 1), dtype=torch.int32, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _bind_stream()
+    _check(emu_dgetrf(m, n, pa, lda, ipiv.data_ptr(), info.data_ptr(), int(nb),
+                      int(nslices)), "emu_dgetrf")
+    return ipiv[:min(m, n)], info
+
+
+def dgetrs(LU, ipiv, B):
+    """Solve in place: B <- A^-1 B from dgetrf's factors."""
+    n = LU.shape[0]
+    nrhs = B.shape[1]
+    pl, lda = _mat(LU, "LU")
+    pb, ldb = _mat(B, "B")
+    _bind_stream()
+    _check(emu_dgetrs(n, nrhs, pl, lda, ipiv.data_ptr(), pb, ldb), "emu_dgetrs")
+    return B
+
+
+def debug_slices(X, by_rows, nslices):
+    """(exps, nonfinite, digits) of one operand; digits has shape
+    (nslices, rows, cols) in the operand's own column-major layout."""
+    torch = _torch()
+    rows, cols = X.shape
+    px, ldx = _mat(X, "X")
+    lines = rows if by_rows else cols
+    exps = torch.zeros(max(lines, 1), dtype=torch.int32, device=X.device)
+    bad = torch.zeros(max(lines, 1), dtype=torch.int32, device=X.device)
+    dig = torch.zeros((nslices, cols, rows), dtype=torch.int8, device=X.device)
+    _bind_stream()
+    _check(emu_debug_slices(rows, cols, px, ldx, 1 if by_rows else 0, int(nslices),
+                            exps.data_ptr(), bad.data_ptr(), dig.data_ptr()),
+           "emu_debug_slices")
+    return exps[:lines], bad[:lines], dig.transpose(1, 2)
+
+
+def debug_products(A, B, nslices, t=None):
+    """D_g for g = 2..t as an int64 tensor of shape (t-1, m, n)."""
+    torch = _torch()
+    m, k = A.shape
+    n = B.shape[1]
+    t = nslices + 1 if t is None else t
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    D = torch.zeros((t - 1, n, m), dtype=torch.int64, device=A.device)
+    _bind_stream()
+    _check(emu_debug_products(m, n, k, pa, lda, pb, ldb, int(nslices), int(t),
+                              D.data_ptr()), "emu_debug_products")
+    return D.transpose(1, 2)
+
+
+def status() -> int:
+    """Synchronize and return (then clear) the EMU_STATUS_* bits."""
+    v = ctypes.c_int(0)
+    _bind_stream()
+    _check(emu_status(ctypes.byref(v)), "emu_status")
+    return v.value

@@ -1,0 +1,122 @@
+// Internal declarations shared by the library's translation units.
+// Not installed; the public interface is include/emu.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <limits.h>
+
+#include "../../include/emu.h"
+
+namespace emu {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+int fail_hip(hipError_t e, const char *what);
+
+#define EMU_TRY_HIP(call)                                   \
+    do {                                                     \
+        hipError_t e__ = (call);                             \
+        if (e__ != hipSuccess) return ::emu::fail_hip(e__, #call); \
+    } while (0)
+
+#define EMU_TRY(call)                                       \
+    do {                                                     \
+        int r__ = (call);                                    \
+        if (r__ != 0) return r__;                            \
+    } while (0)
+
+// ------------------------------------------------------ device context
+struct Device {
+    int id = -1;
+    int *status = nullptr;        // device word: OR of EMU_STATUS_* bits
+    void *ws = nullptr;           // library scratch
+    size_t ws_bytes = 0;
+};
+
+// Current device's state (initialised on first use) and the thread's stream.
+int current(Device **dev, hipStream_t *stream);
+// Make sure dev->ws holds at least `bytes` (synchronizes `stream` to grow).
+int reserve(Device *dev, hipStream_t stream, size_t bytes);
+
+// ----------------------------------------------------------- geometry
+// Exponent codes kept per line during a scan: INT_MIN for a line of zeros
+// (finalised to exponent 0), INT_MAX for a line holding Inf/NaN, otherwise
+// the frexp exponent of the line's largest magnitude.
+constexpr int CODE_ZERO = INT_MIN;
+constexpr int CODE_NONFINITE = INT_MAX;
+
+// Digit planes are stored in MFMA fragment order.  A "line" is a row of A or
+// a column of B; lines are padded to LINE_PAD, K to K_BLOCK.  Block (lb, kb)
+// of plane d covers lines lb*32..+32 and k = kb*32..+32 and is 1024 bytes:
+// byte (kh*32 + line%32)*16 + k%16 with kh = (k%32)/16.  One wave loads a
+// block with one 16-byte load per lane; lane l receives line l%32 and the
+// k-half l/32, the operand layout of v_mfma_i32_32x32x32_i8 (the same k
+// assignment on the A and the B side is all the dot product needs).
+constexpr int LINE_PAD = 128;
+constexpr int K_BLOCK = 32;
+constexpr int FRAG_BYTES = 1024;
+
+struct Planes {
+    int lines = 0, k = 0;        // logical sizes
+    int LB = 0, KB = 0;          // 32-line blocks (padded), 32-k blocks
+    size_t plane_bytes = 0;      // bytes of one digit plane
+};
+
+inline Planes plane_geom(int lines, int k) {
+    Planes p;
+    p.lines = lines;
+    p.k = k;
+    int lp = (lines + LINE_PAD - 1) / LINE_PAD * LINE_PAD;
+    p.LB = lp / 32;
+    p.KB = (k + K_BLOCK - 1) / K_BLOCK;
+    p.plane_bytes = (size_t)p.LB * p.KB * FRAG_BYTES;
+    return p;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------- launchers
+// Exponent scan + slicing of one operand into packed planes.
+//   by_rows = 1: X is lines x k (rows of A are lines), element (l, kk) at
+//               X[l + kk*ldx];
+//   by_rows = 0: X is k x lines (columns of B are lines), element (kk, l) at
+//               X[kk + l*ldx].
+// code receives the per-line exponent codes (length >= lines); planes
+// receives s planes of geometry g; status gets EMU_STATUS_NONFINITE.
+int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
+                 int s, int *code, int8_t *planes, int *status,
+                 hipStream_t stream);
+
+// Unpack planes to plain column-major int8 (debug entry).
+int launch_unpack(const int8_t *planes, const Planes &g, int s, int by_rows,
+                  int8_t *out, hipStream_t stream);
+int launch_codes_to_exps(const int *code, int lines, int *exps, int *nonfinite,
+                         hipStream_t stream);
+
+// Slice-product GEMM with fused recombination (mode 0) or raw D_g output
+// (mode 1).  ws_chunk: int64 scratch for K-chunk partial sums (bytes from
+// gemm_chunk_bytes), may be null when gemm_chunk_bytes() == 0.
+size_t gemm_chunk_bytes(int m, int n, int k, int s, int t);
+int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
+                     const Planes &gb, const int *codeA, const int *codeB,
+                     int m, int n, int k, int s, int t, double alpha,
+                     double beta, double *C, long long ldc, int64_t *Dout,
+                     int64_t *ws_chunk, hipStream_t stream);
+bool gemm_supported(int s, int t);
+
+// FP64 LU pieces.
+int launch_fill_int(int *p, int v, int count, hipStream_t stream);
+int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
+                 int row0, int *info, hipStream_t stream);
+int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
+                 int ncols_right, const int *ipiv, int k1, int k2,
+                 hipStream_t stream);
+int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
+                     long long ldb, int ncols, hipStream_t stream);
+int launch_getrs(int n, int nrhs, const double *LU, long long lda,
+                 const int *ipiv, double *B, long long ldb, int *perm_ws,
+                 hipStream_t stream);
+
+}  // namespace emu

@@ -1,0 +1,265 @@
+// Exponent scan and INT8 digit slicing of one FP64 operand (gfx950).
+//
+// Paper: section "Emulation of FP64 and INT8 Splitting" (eqns (1)-(3)): the
+// operand is split into slices that fit the integer units; eqn (3) shows why
+// the scale must follow the magnitude of each row (of A) / column (of B).
+//
+// Pass 1 (k_scan_*): per-line exponent code = max over the line of the
+//   frexp exponent of each element (the exponent of the largest magnitude),
+//   with zeros ignored and Inf/NaN dominating; combined across workgroups
+//   with atomicMax, since the exponent of a maximum is the maximum of the
+//   exponents.
+// Pass 2 (k_slice_*): digits by exact integer arithmetic on the significand:
+//   with |x| = M 2^E (M the 53-bit significand), Z = floor(|x| 2^(7s - e))
+//   is M shifted by E - e + 7s bits (Z < 2^(7s) <= 2^63), and digit i
+//   (1-based) is bits 7(s-i)..7(s-i)+6 of Z with the sign of x.  This equals
+//   the truncated base-128 expansion of x 2^-e digit by digit.
+// Both passes read the operand once (8 bytes per element each); pass 2
+// writes s bytes per element in MFMA fragment order.
+#include "common.h"
+
+namespace emu {
+
+__device__ __forceinline__ int exp_code(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    int eb = (int)((b >> 52) & 0x7ff);
+    unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
+    if (eb == 0x7ff) return CODE_NONFINITE;
+    if (eb == 0) {
+        if (fr == 0) return CODE_ZERO;
+        return (63 - __clzll((long long)fr)) - 1073;   // subnormal
+    }
+    return eb - 1022;
+}
+
+__device__ __forceinline__ int code_to_exp(int c) {
+    return (c == CODE_ZERO || c == CODE_NONFINITE) ? 0 : c;
+}
+
+// Z = floor(|x| 2^(7s - e)), sign of x.
+__device__ __forceinline__ unsigned long long digits_word(double x, int e, int s,
+                                                         int *neg) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    *neg = (int)(b >> 63);
+    int eb = (int)((b >> 52) & 0x7ff);
+    unsigned long long M = b & 0xFFFFFFFFFFFFFull;
+    int E;
+    if (eb == 0) {
+        E = -1074;
+    } else {
+        M |= (1ull << 52);
+        E = eb - 1075;
+    }
+    if (M == 0) return 0;
+    int sh = E - e + 7 * s;
+    if (sh >= 0) return M << sh;       // value < 2^(7s) by choice of e
+    if (sh <= -64) return 0;
+    return M >> (-sh);
+}
+
+// ------------------------------------------------------------------ scans
+__global__ void k_fill_int(int *p, int v, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// Rows of X (lines x k, column-major): thread per row, k split over grid.y.
+__global__ __launch_bounds__(256) void k_scan_rows(const double *__restrict__ X,
+                                                   long long ldx, int lines, int k,
+                                                   int kper, int *code, int *status) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= lines) return;
+    int k0 = blockIdx.y * kper;
+    int k1 = min(k, k0 + kper);
+    int m = CODE_ZERO;
+    for (int c = k0; c < k1; ++c) m = max(m, exp_code(X[r + (long long)c * ldx]));
+    if (m != CODE_ZERO) atomicMax(&code[r], m);
+    if (m == CODE_NONFINITE) atomicOr(status, EMU_STATUS_NONFINITE);
+}
+
+// Columns of X (k x lines, column-major): one wave per (column, k-chunk).
+__global__ __launch_bounds__(256) void k_scan_cols(const double *__restrict__ X,
+                                                   long long ldx, int lines, int k,
+                                                   int kper, int *code, int *status) {
+    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    int col = wave;
+    if (col >= lines) return;
+    int k0 = blockIdx.y * kper;
+    int k1 = min(k, k0 + kper);
+    const double *x = X + (long long)col * ldx;
+    int m = CODE_ZERO;
+    for (int r = k0 + lane; r < k1; r += 64) m = max(m, exp_code(x[r]));
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    if (lane == 0) {
+        if (m != CODE_ZERO) atomicMax(&code[col], m);
+        if (m == CODE_NONFINITE) atomicOr(status, EMU_STATUS_NONFINITE);
+    }
+}
+
+// ---------------------------------------------------------------- slicing
+// One wave writes fragment block (lb, kb) of every plane.  Lane l handles
+// line lb*32 + l%32 and k = kb*32 + (l/32)*16 + 0..15.
+template <int S, bool ROWS>
+__global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
+                                               long long ldx, int lines, int k,
+                                               int LB, int KB,
+                                               const int *__restrict__ code,
+                                               int8_t *__restrict__ planes,
+                                               size_t plane_bytes) {
+    long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (wave >= (long long)LB * KB) return;
+    int lb = (int)(wave / KB);
+    int kb = (int)(wave % KB);
+    int line = lb * 32 + (lane & 31);
+    int kbase = kb * 32 + (lane >> 5) * 16;
+    int c = line < lines ? code[line] : CODE_ZERO;
+    bool ok = line < lines && c != CODE_NONFINITE;
+    int e = code_to_exp(c);
+
+    unsigned int w[S][4];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[d][q] = 0u;
+
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        int kx = kbase + kk;
+        double x = 0.0;
+        if (ok && kx < k) {
+            x = ROWS ? X[line + (long long)kx * ldx] : X[kx + (long long)line * ldx];
+        }
+        int neg;
+        unsigned long long Z = digits_word(x, e, S, &neg);
+#pragma unroll
+        for (int d = 0; d < S; ++d) {
+            int q = (int)((Z >> (7 * (S - 1 - d))) & 127ull);
+            if (neg) q = -q;
+            w[d][kk >> 2] |= ((unsigned int)(q & 0xff)) << (8 * (kk & 3));
+        }
+    }
+    size_t off = ((size_t)lb * KB + kb) * FRAG_BYTES + (size_t)lane * 16;
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+        uint4 v;
+        v.x = w[d][0];
+        v.y = w[d][1];
+        v.z = w[d][2];
+        v.w = w[d][3];
+        *reinterpret_cast<uint4 *>(planes + d * plane_bytes + off) = v;
+    }
+}
+
+template <int S>
+static void launch_slice_s(const double *X, long long ldx, int by_rows,
+                           const Planes &g, const int *code, int8_t *planes,
+                           hipStream_t stream) {
+    long long waves = (long long)g.LB * g.KB;
+    if (waves == 0) return;
+    dim3 grid((unsigned)((waves + 3) / 4));
+    if (by_rows)
+        hipLaunchKernelGGL((k_slice<S, true>), grid, dim3(256), 0, stream, X, ldx,
+                           g.lines, g.k, g.LB, g.KB, code, planes, g.plane_bytes);
+    else
+        hipLaunchKernelGGL((k_slice<S, false>), grid, dim3(256), 0, stream, X, ldx,
+                           g.lines, g.k, g.LB, g.KB, code, planes, g.plane_bytes);
+}
+
+int launch_fill_int(int *p, int v, int count, hipStream_t stream) {
+    if (count <= 0) return 0;
+    hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, stream,
+                       p, v, count);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
+                 int s, int *code, int8_t *planes, int *status,
+                 hipStream_t stream) {
+    EMU_TRY(launch_fill_int(code, CODE_ZERO, g.lines, stream));
+    if (g.k > 0 && g.lines > 0) {
+        if (by_rows) {
+            int kper = 256;
+            dim3 grid((g.lines + 255) / 256, (g.k + kper - 1) / kper);
+            hipLaunchKernelGGL(k_scan_rows, grid, dim3(256), 0, stream, X, ldx,
+                               g.lines, g.k, kper, code, status);
+        } else {
+            int kper = 2048;
+            dim3 grid((g.lines + 3) / 4, (g.k + kper - 1) / kper);
+            hipLaunchKernelGGL(k_scan_cols, grid, dim3(256), 0, stream, X, ldx,
+                               g.lines, g.k, kper, code, status);
+        }
+        EMU_TRY_HIP(hipGetLastError());
+    }
+    switch (s) {
+        case 1: launch_slice_s<1>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 2: launch_slice_s<2>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 3: launch_slice_s<3>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 4: launch_slice_s<4>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 5: launch_slice_s<5>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 6: launch_slice_s<6>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 7: launch_slice_s<7>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 8: launch_slice_s<8>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 9: launch_slice_s<9>(X, ldx, by_rows, g, code, planes, stream); break;
+        default:
+            set_error("slice count %d outside 1..%d", s, EMU_MAX_SLICES);
+            return EMU_ERR_UNSUPPORTED;
+    }
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+// ------------------------------------------------------------ debug views
+__global__ void k_unpack(const int8_t *__restrict__ planes, int lines, int k, int LB,
+                         int KB, size_t plane_bytes, int s, int by_rows,
+                         int8_t *__restrict__ out) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)lines * k;
+    if (idx >= total) return;
+    // output is column-major in the operand's own orientation
+    int line, kk;
+    if (by_rows) {
+        line = (int)(idx % lines);
+        kk = (int)(idx / lines);
+    } else {
+        kk = (int)(idx % k);
+        line = (int)(idx / k);
+    }
+    int lb = line / 32, kb = kk / 32;
+    int kh = (kk % 32) / 16;
+    size_t off = ((size_t)lb * KB + kb) * FRAG_BYTES +
+                 (size_t)(kh * 32 + line % 32) * 16 + (kk % 16);
+    for (int d = 0; d < s; ++d) out[d * total + idx] = planes[d * plane_bytes + off];
+}
+
+__global__ void k_codes_to_exps(const int *code, int lines, int *exps, int *nonfinite) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= lines) return;
+    int c = code[i];
+    exps[i] = code_to_exp(c);
+    if (nonfinite) nonfinite[i] = (c == CODE_NONFINITE) ? 1 : 0;
+}
+
+int launch_unpack(const int8_t *planes, const Planes &g, int s, int by_rows,
+                  int8_t *out, hipStream_t stream) {
+    long long total = (long long)g.lines * g.k;
+    if (total == 0) return 0;
+    hipLaunchKernelGGL(k_unpack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       stream, planes, g.lines, g.k, g.LB, g.KB, g.plane_bytes, s,
+                       by_rows, out);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_codes_to_exps(const int *code, int lines, int *exps, int *nonfinite,
+                         hipStream_t stream) {
+    if (lines <= 0) return 0;
+    hipLaunchKernelGGL(k_codes_to_exps, dim3((lines + 255) / 256), dim3(256), 0,
+                       stream, code, lines, exps, nonfinite);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+}  // namespace emu

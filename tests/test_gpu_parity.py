@@ -1,0 +1,256 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Integer work (exponents, digits, slice-product sums) must match bit for bit.
+Because the recombination and every FP64 step of the LU follow one fixed
+order on both sides, the emulated GEMM, the LU factors, the pivots and the
+solutions must match bit for bit as well; the tolerance-based checks
+(normwise error against the double-double reference, backward error) are
+reported on top.
+"""
+import numpy as np
+import pytest
+import torch
+
+import matgen
+import oracle as O
+import paper_2509_23565_amd as emu
+
+pytestmark = pytest.mark.gpu
+
+
+def _same_bits(a, b):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    return a.shape == b.shape and np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _special_rows(A):
+    A = np.array(A, order="F", copy=True)
+    A[1, :] = 0.0
+    A[2, :] *= 2.0 ** -1060          # subnormal-range row
+    A[3, :] = 0.0
+    A[3, 0] = 2.0 ** 40              # exact power of two
+    A[4, :] *= 1e290
+    return A
+
+
+# ----------------------------------------------------------------- slicing
+
+@pytest.mark.parametrize("s", [1, 3, 7, 9])
+@pytest.mark.parametrize("phi", [0.0, 4.0, 12.0])
+def test_slices_bit_exact(s, phi):
+    X = _special_rows(matgen.phi_matrix(203, 141, phi, seed=1))
+    Xt = np.asfortranarray(X.T)
+    for by_rows, M in ((True, X), (False, Xt)):
+        e_g, bad_g, q_g = emu.debug_slices(emu.colmajor(M), by_rows, s)
+        axis = 1 if by_rows else 0
+        e_o, bad_o = O.line_exponents(M, axis)
+        q_o = O.slice_digits(M, e_o, bad_o, s, axis)
+        assert np.array_equal(_host(e_g), e_o)
+        assert not _host(bad_g).any()
+        assert np.array_equal(_host(q_g).astype(np.int64), q_o.astype(np.int64))
+
+
+def test_slices_flag_nonfinite_lines():
+    X = np.array(matgen.uniform(70, 40, seed=2), order="F")
+    X[5, 3] = np.inf
+    X[9, 0] = np.nan
+    e_g, bad_g, q_g = emu.debug_slices(emu.colmajor(X), True, 4)
+    e_o, bad_o = O.line_exponents(X, 1)
+    assert np.array_equal(_host(bad_g).astype(bool), bad_o)
+    assert np.array_equal(_host(e_g), e_o)
+    assert np.array_equal(_host(q_g), O.slice_digits(X, e_o, bad_o, 4, 1))
+
+
+# ---------------------------------------------------------- slice products
+
+@pytest.mark.parametrize("s,t", [(1, 2), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7),
+                                 (7, 8), (8, 9), (9, 10), (2, 4), (3, 6), (4, 8),
+                                 (5, 10)])
+def test_slice_products_bit_exact(s, t):
+    A = matgen.phi_matrix(161, 237, 3.0, seed=3, substream=0)
+    B = matgen.phi_matrix(237, 99, 3.0, seed=3, substream=1)
+    D_g = _host(emu.debug_products(emu.colmajor(A), emu.colmajor(B), s, t))
+    _, parts = O.dgemm_emu(A, B, s, t=t, return_parts=True)
+    for g in range(2, t + 1):
+        assert np.array_equal(D_g[g - 2], parts["D"][g].astype(np.int64)), g
+
+
+def test_slice_products_across_exactness_chunks():
+    # s = 9: one INT32 chunk holds at most 14784 K values (the bound assumes
+    # 9 pairs of 127 * 127 per k); with every digit 1..7 equal to 127
+    # (x = 1 - 2^-53) and k = 20000 the true sums exceed 2^31.
+    k = 20000
+    x = 1.0 - 2.0 ** -53
+    A = np.full((70, k), x, order="F")
+    A[::2, :] *= -1.0
+    B = np.full((k, 40), x, order="F")
+    B[:, 1::3] *= -1.0
+    D_g = _host(emu.debug_products(emu.colmajor(A), emu.colmajor(B), 9))
+    _, parts = O.dgemm_emu(A, B, 9, return_parts=True)
+    for g in range(2, 11):
+        assert np.array_equal(D_g[g - 2], parts["D"][g].astype(np.int64)), g
+    assert np.abs(D_g).max() > 2 ** 31           # the INT64 fold was needed
+
+
+# ------------------------------------------------------------ emulated GEMM
+
+@pytest.mark.parametrize("s", list(range(1, 10)))
+def test_dgemm_bit_exact(s):
+    m, n, k = 190, 133, 301
+    A = matgen.phi_matrix(m, k, 4.0, seed=5, substream=0)
+    B = matgen.phi_matrix(k, n, 4.0, seed=5, substream=1)
+    C0 = matgen.uniform(m, n, seed=5, substream=2)
+    for alpha, beta in ((1.0, 0.0), (-0.7, 1.3), (2.5, -1.0)):
+        Cg = emu.colmajor(C0)
+        emu.dgemm(emu.colmajor(A), emu.colmajor(B), Cg, alpha=alpha, beta=beta, nslices=s)
+        ref = O.dgemm_emu(A, B, s, alpha=alpha, beta=beta, C=C0)
+        assert _same_bits(_host(Cg), ref), (alpha, beta)
+
+
+@pytest.mark.parametrize("s,t", [(2, 4), (3, 6), (5, 10)])
+def test_dgemm_full_threshold_bit_exact(s, t):
+    A = matgen.int_matrix(64, 96, 21, seed=6, substream=0)
+    B = matgen.int_matrix(96, 80, 14, seed=6, substream=1)
+    Cg = emu.dgemm(emu.colmajor(A), emu.colmajor(B), nslices=s, t=t)
+    ref = O.dgemm_emu(A, B, s, t=t)
+    assert _same_bits(_host(Cg), ref)
+    if s == 3:   # 21-bit x 14-bit integers are exact with all pairs (s = 3)
+        assert np.array_equal(ref, A @ B)
+
+
+def test_dgemm_submatrix_views_and_beta_zero_ignores_nan():
+    big = matgen.phi_matrix(300, 300, 1.0, seed=7)
+    Ag = emu.colmajor(big)
+    A = big[10:150, 20:220]
+    B = big[50:250, 100:190]
+    C = np.full((140, 90), np.nan)
+    Cbig = emu.colmajor(np.full((200, 120), np.nan))
+    Cg = Cbig[5:145, 7:97]
+    emu.dgemm(Ag[10:150, 20:220], Ag[50:250, 100:190], Cg, alpha=1.0, beta=0.0, nslices=6)
+    ref = O.dgemm_emu(A, B, 6, alpha=1.0, beta=0.0, C=C)
+    assert _same_bits(_host(Cg), ref)
+    assert np.isnan(_host(Cbig)[:5]).all()       # outside the view untouched
+
+
+def test_dgemm_nonfinite_rows_cols_and_status():
+    A = np.array(matgen.uniform(100, 64, seed=8), order="F")
+    B = np.array(matgen.uniform(64, 70, seed=9), order="F")
+    A[7, 3] = np.inf
+    B[5, 66] = np.nan
+    emu.status()
+    Cg = emu.dgemm(emu.colmajor(A), emu.colmajor(B), nslices=5)
+    ref = O.dgemm_emu(A, B, 5)
+    got = _host(Cg)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    assert _same_bits(got[~np.isnan(ref)], ref[~np.isnan(ref)])
+    assert emu.status() & 1
+    assert emu.status() == 0
+
+
+def test_dgemm_quick_returns():
+    C0 = matgen.uniform(50, 40, seed=10)
+    Cg = emu.colmajor(C0)
+    Ag = torch.empty((0, 50), dtype=torch.float64, device="cuda").t()
+    Bg = torch.empty((40, 0), dtype=torch.float64, device="cuda").t()
+    emu.dgemm(Ag, Bg, Cg, alpha=1.0, beta=0.5, nslices=3)
+    assert np.array_equal(_host(Cg), 0.5 * C0)
+    A = matgen.uniform(50, 30, seed=11)
+    B = matgen.uniform(30, 40, seed=12)
+    Cg = emu.colmajor(np.full((50, 40), np.nan))
+    emu.dgemm(emu.colmajor(A), emu.colmajor(B), Cg, alpha=0.0, beta=0.0, nslices=3)
+    assert np.array_equal(_host(Cg), np.zeros((50, 40)))
+
+
+@pytest.mark.parametrize("phi", [0.0, 1.0, 4.0])
+def test_full_slice_count_normwise_error(phi):
+    A = matgen.phi_matrix(512, 512, phi, seed=0, substream=0)
+    B = matgen.phi_matrix(512, 512, phi, seed=0, substream=1)
+    ref = O.dgemm_dd(A, B)
+    Cg = _host(emu.dgemm(emu.colmajor(A), emu.colmajor(B), nslices=9))
+    err = O.rel_err_fro(Cg, ref)
+    native = O.rel_err_fro(A @ B, ref)
+    print(f"phi={phi}: eta_F s=9 {err:.3e}  native FP64 {native:.3e}")
+    assert err <= 1e-15
+
+
+# ---------------------------------------------------------------------- LU
+
+@pytest.mark.parametrize("m,n,nb,s", [(256, 256, 64, 7), (300, 300, 64, 5),
+                                      (300, 200, 64, 7), (200, 300, 32, 9),
+                                      (257, 257, 128, 3)])
+def test_getrf_bit_exact(m, n, nb, s):
+    A = matgen.phi_matrix(m, n, 1.0, seed=13)
+    Ag = emu.colmajor(A)
+    ipiv, info = emu.dgetrf(Ag, nb=nb, nslices=s)
+    LU, piv, inf = O.getrf(A, nb=nb, s=s)
+    assert int(_host(info)[0]) == inf
+    assert np.array_equal(_host(ipiv), piv)
+    assert _same_bits(_host(Ag), LU)
+
+
+def test_lu_solve_small_config_bit_exact_and_backward_error():
+    # plain method, small: n = 1024, U(-1,1), block 64, 7 slices, seed 0
+    n = 1024
+    A = matgen.uniform(n, n, seed=0, substream=0)
+    b = matgen.uniform(n, 1, seed=0, substream=1)
+    Ag = emu.colmajor(A)
+    ipiv, info = emu.dgetrf(Ag, nb=64, nslices=7)
+    xg = emu.colmajor(b)
+    emu.dgetrs(Ag, ipiv, xg)
+    LU, piv, inf = O.getrf(A, nb=64, s=7)
+    x = O.getrs(LU, piv, b)
+    assert np.array_equal(_host(ipiv), piv) and int(_host(info)[0]) == inf == 0
+    assert _same_bits(_host(Ag), LU)
+    assert _same_bits(_host(xg), x)
+    eta = O.backward_error(A, _host(xg), b)
+    print(f"n=1024 s=7 nb=64: eta {eta:.3e}, scaled residual {eta / (n * O.EPS):.3f}")
+    assert eta < 1e-12
+
+
+@pytest.mark.parametrize("n,nrhs", [(300, 1), (300, 3), (64, 2), (65, 1)])
+def test_getrs_bit_exact(n, nrhs):
+    A = matgen.phi_matrix(n, n, 2.0, seed=14)
+    B = matgen.uniform(n, nrhs, seed=15)
+    LU, piv, _ = O.getrf(A, nb=32, s=None)
+    x = O.getrs(LU, piv, B)
+    Lg = emu.colmajor(LU)
+    Bg = emu.colmajor(B)
+    emu.dgetrs(Lg, torch.as_tensor(piv.astype(np.int32), device="cuda"), Bg)
+    assert _same_bits(_host(Bg), x)
+
+
+def test_getrf_singular_reports_info():
+    A = np.array(matgen.uniform(150, 150, seed=16), order="F")
+    A[:, 77] = 0.0
+    Ag = emu.colmajor(A)
+    ipiv, info = emu.dgetrf(Ag, nb=32, nslices=6)
+    LU, piv, inf = O.getrf(A, nb=32, s=6)
+    assert inf == 78 and int(_host(info)[0]) == 78
+    assert _same_bits(_host(Ag), LU)
+
+
+@pytest.mark.parametrize("s", [1, 4, 5])
+def test_turing_and_wilkinson_closed_forms(s):
+    n = 160
+    T = matgen.turing(n)
+    Tg = emu.colmajor(T)
+    ipiv, info = emu.dgetrf(Tg, nb=32, nslices=s)
+    assert np.array_equal(_host(ipiv), np.arange(1, n + 1))
+    e1 = np.zeros((n, 1))
+    e1[0] = 1.0
+    xg = emu.colmajor(e1)
+    emu.dgetrs(Tg, ipiv, xg)
+    expect = np.array([1.0] + [2.0 ** (i - 1) for i in range(1, n)])
+    assert np.array_equal(_host(xg)[:, 0], expect)
+    W = matgen.wilkinson(n)
+    Wg = emu.colmajor(W)
+    emu.dgetrf(Wg, nb=32, nslices=s)
+    last = _host(Wg)[:, n - 1]
+    exact = np.array_equal(last, 2.0 ** np.arange(n))
+    assert exact == (s >= 5)          # 7 s bits must cover a 32-row block's 2^31 spread

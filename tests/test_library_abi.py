@@ -1,0 +1,72 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/emu.h declares, and rejects invalid arguments with LAPACK-style codes
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2509_23565_amd as emu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "emu.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|int)\s*(emu_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("emu_dgemm", "emu_dgetrf", "emu_dgetrs"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = emu.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert emu.emu_version() >= 100
+
+
+def _p(v=0x1000):
+    return ctypes.c_void_p(v)   # never dereferenced: argument checks come first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7), -1),
+    ((4, -1, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7), -2),
+    ((4, 4, -1, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7), -3),
+    ((4, 4, 4, 1.0, None, 4, _p(), 4, 0.0, _p(), 4, 7), -5),
+    ((4, 4, 4, 1.0, _p(), 3, _p(), 4, 0.0, _p(), 4, 7), -6),
+    ((4, 4, 4, 1.0, _p(), 4, None, 4, 0.0, _p(), 4, 7), -7),
+    ((4, 4, 5, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7), -8),
+    ((4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, None, 4, 7), -10),
+    ((4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 3, 7), -11),
+    ((4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 0), -12),
+    ((4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 17), -12),
+])
+def test_dgemm_argument_errors(args, code):
+    assert emu.emu_dgemm(*args) == code
+    assert "argument" in emu.emu_last_error()
+
+
+def test_dgemm_unsupported_slice_count():
+    assert emu.emu_dgemm(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 12) == 1003
+    assert emu.emu_dgemm_t(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7, 14) == 1003
+    assert emu.emu_dgemm_t(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 3, 7) == -13
+
+
+def test_lu_argument_errors():
+    assert emu.emu_dgetrf(-1, 4, _p(), 4, _p(), _p(), 64, 7) == -1
+    assert emu.emu_dgetrf(4, 4, _p(), 3, _p(), _p(), 64, 7) == -4
+    assert emu.emu_dgetrf(4, 4, _p(), 4, None, _p(), 64, 7) == -5
+    assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), None, 64, 7) == -6
+    assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 2048, 7) == -7
+    assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 64, 0) == -8
+    assert emu.emu_dgetrs(4, 1, _p(), 3, _p(), _p(), 4) == -4
+    assert emu.emu_dgetrs(4, -1, _p(), 4, _p(), _p(), 4) == -2
+    assert emu.emu_dgetrs(4, 1, _p(), 4, _p(), _p(), 2) == -7
+    assert emu.emu_status(None) == -1
