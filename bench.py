@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-native", action="store_true", help="skip native FP64")
     ap.add_argument("--no-lu", action="store_true", help="skip the LU solve")
+    ap.add_argument("--sweep-s", type=str, default="",
+                    help="comma-separated slice counts to time on the same inputs "
+                         "(adds a 'sweep' list to the JSON line)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
@@ -159,6 +162,37 @@ def main():
             "GB_s": round(2 * n * n * (8 + s) / (slice_avg * 1e-3) / 1e9, 1),
         },
     }
+
+    # ------------------------------------------------- slice-count sweep
+    if args.sweep_s:
+        sweep = []
+        for s2 in [int(v) for v in args.sweep_s.split(",") if v]:
+            P2 = pairs(s2, s2 + 1)
+            emu.dgemm(Ag, Bg, Cg, nslices=s2)
+            torch.cuda.synchronize()
+            emu.emu_profile_start()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            reps = 3
+            for _ in range(reps):
+                emu.dgemm(Ag, Bg, Cg, nslices=s2)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            emu.emu_profile_stop()
+            step2 = e0.elapsed_time(e1) / reps
+            gm, gc = emu.profile_read(emu.PROF_GEMM)
+            gavg = gm / max(gc, 1)
+            ach = 2.0 * n * n * n * P2 / (gavg * 1e-3) / 1e12
+            sweep.append({"s": s2, "products": P2, "ms_per_step": round(step2, 3),
+                          "tflops_equiv": round(flops_equiv / (step2 * 1e-3) / 1e12, 2),
+                          "gemm_ms": round(gavg, 3), "int8_tops": round(ach, 1),
+                          "int8_frac": round(ach / (PEAK_INT8_OPS / 1e12), 4)})
+            log(f"sweep s={s2}: step {step2:.2f} ms, kernel {gavg:.2f} ms, "
+                f"{ach:.0f} TOP/s ({ach / 5000:.1%})")
+        result["sweep"] = sweep
+        emu.dgemm(Ag, Bg, Cg, nslices=s)
+        torch.cuda.synchronize()
 
     # ---------------------------------------------------- sampled oracle leg
     g = matgen.rng(args.seed, 99)

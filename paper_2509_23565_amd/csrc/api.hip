@@ -106,7 +106,8 @@ struct GemmScratch {
     size_t off_codeA, off_codeB, off_pa, off_pb, off_chunk, total;
 };
 
-static GemmScratch gemm_scratch(int m, int n, int k, int s, int t) {
+static GemmScratch gemm_scratch(int m, int n, int k, int s, int t,
+                                bool raw_sums = false) {
     GemmScratch g;
     g.ga = plane_geom(m, k);
     g.gb = plane_geom(n, k);
@@ -120,7 +121,7 @@ static GemmScratch gemm_scratch(int m, int n, int k, int s, int t) {
     g.off_pb = off;
     off += align256((size_t)s * g.gb.plane_bytes);
     g.off_chunk = off;
-    off += align256(gemm_chunk_bytes(m, n, k, s, t));
+    off += align256(gemm_chunk_bytes(m, n, k, s, t, raw_sums));
     g.total = off;
     return g;
 }
@@ -172,8 +173,8 @@ static int gemm_core(Device *dev, hipStream_t stream, const GemmScratch &g, int 
     int *codeB = reinterpret_cast<int *>(ws + g.off_codeB);
     int8_t *pa = reinterpret_cast<int8_t *>(ws + g.off_pa);
     int8_t *pb = reinterpret_cast<int8_t *>(ws + g.off_pb);
-    int64_t *chunk = gemm_chunk_bytes(m, n, k, s, t)
-                         ? reinterpret_cast<int64_t *>(ws + g.off_chunk)
+    int32_t *chunk = gemm_chunk_bytes(m, n, k, s, t, Dout != nullptr)
+                         ? reinterpret_cast<int32_t *>(ws + g.off_chunk)
                          : nullptr;
     ProfScope ps(EMU_PROF_SLICE, stream);
     EMU_TRY(launch_slice(A, lda, 1, g.ga, s, codeA, pa, dev->status, stream));
@@ -316,7 +317,7 @@ static int dgemm_impl(int m, int n, int k, double alpha, const double *A, int ld
         }
         return scale_c(C, ldc, m, n, beta, st);
     }
-    GemmScratch g = gemm_scratch(m, n, k, s, t);
+    GemmScratch g = gemm_scratch(m, n, k, s, t, Dout != nullptr);
     EMU_TRY(reserve(dev, st, g.total));
     return gemm_core(dev, st, g, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, t,
                      Dout);

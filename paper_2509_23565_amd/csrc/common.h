@@ -95,15 +95,16 @@ int launch_unpack(const int8_t *planes, const Planes &g, int s, int by_rows,
 int launch_codes_to_exps(const int *code, int lines, int *exps, int *nonfinite,
                          hipStream_t stream);
 
-// Slice-product GEMM with fused recombination (mode 0) or raw D_g output
-// (mode 1).  ws_chunk: int64 scratch for K-chunk partial sums (bytes from
-// gemm_chunk_bytes), may be null when gemm_chunk_bytes() == 0.
-size_t gemm_chunk_bytes(int m, int n, int k, int s, int t);
+// Slice-product GEMM with fused recombination, or the raw diagonal sums
+// D_g (Dout != null, int64 [t-1][n][m]).  ws_part: INT32 scratch for K-chunk
+// partial sums of gemm_chunk_bytes(..., raw_sums = Dout != null) bytes; may
+// be null when that is 0.
+size_t gemm_chunk_bytes(int m, int n, int k, int s, int t, bool raw_sums);
 int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
                      const Planes &gb, const int *codeA, const int *codeB,
                      int m, int n, int k, int s, int t, double alpha,
                      double beta, double *C, long long ldc, int64_t *Dout,
-                     int64_t *ws_chunk, hipStream_t stream);
+                     int32_t *ws_part, hipStream_t stream);
 bool gemm_supported(int s, int t);
 
 // FP64 LU pieces.

@@ -4,16 +4,29 @@
 // Paper: section "Emulation of FP64 and INT8 Splitting", eqn (2) and the
 // truncation threshold t; the Schur update of eqn (8) is the call site in
 // the LU.  For every output element the kernel forms the exact diagonal sums
-// D_g = sum_{i+j=g} A_i B_j, g = 2..t, with one INT32 accumulator tile per
-// diagonal, loading each digit fragment once per K step and reusing it for
-// every pair on every diagonal it takes part in.
+// D_g = sum_{i+j=g} A_i B_j, g = 2..t, in INT32 accumulator tiles, one per
+// diagonal ("slot"), loading each digit fragment once per K step and reusing
+// it for every pair on every diagonal it takes part in.
 //
-// Exactness: |D_g| over a K-range of length L is at most pairs(g) L 127^2.
-// The host picks a chunk length (a multiple of 32) that keeps this below
-// 2^31 for the diagonal with the most pairs; longer K are split into chunks
-// whose INT32 sums are folded into an INT64 scratch tile owned by the
-// workgroup.  Chunking depends on (s, t, k) only, so tile shapes never
-// change a bit of the result.
+// Data path per workgroup (8 waves, two per SIMD):
+//   - the digit planes are stored in MFMA fragment order (1 KB per 32 lines
+//     x 32 k), so a K step of the workgroup tile is a list of whole
+//     fragments; they are copied global -> LDS with 16-byte direct-to-LDS
+//     loads (no VGPR staging), double buffered, one barrier per K step;
+//   - each wave reads its own A and B fragments of every digit from LDS and
+//     issues all pairs (i, j) with i + j <= t on 32x32x32 INT8 MFMA;
+//   - workgroups are numbered so that each of the 8 XCDs receives one
+//     contiguous range of output tiles, walked in groups of 8 tile rows, so
+//     the concurrently running tiles of an XCD share A and B panels in its L2.
+//
+// Exactness: a slot holding p pairs over a K range of length L is bounded by
+// p L 127^2, which must stay below 2^31.  The longest diagonal (t = s + 1
+// has s pairs) can be split over two slots ("split" variant) so that no slot
+// holds more than s - 1 pairs; K up to 16640 then needs no chunking for any
+// s <= 9.  Longer K is cut into chunks of the exact-INT32 length; each chunk
+// writes its INT32 diagonal sums to scratch and a combine pass adds them in
+// INT64 before recombining.  The cuts depend on (s, t, k) only, so tile
+// shapes never change a bit of the result.
 //
 // Epilogue (fixed order): S = 0; for g = t..2: S = fl(S + D_g 2^-7g);
 // X = ldexp(S, e_p + f_q); C = fma(alpha, X, beta C) (beta = 0: fma(alpha,
@@ -31,135 +44,282 @@ namespace emu {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-template <int S, int T>
-struct Diag {
-    static constexpr int NACC = T - 1;                       // diagonals 2..T
-    static constexpr int pairs(int g) {
-        int lo = g - S > 1 ? g - S : 1;
-        int hi = g - 1 < S ? g - 1 : S;
-        return hi >= lo ? hi - lo + 1 : 0;
+// s_waitcnt immediate for gfx9: vmcnt(0), expcnt/lgkmcnt unconstrained.
+constexpr int WAIT_VMCNT0 = 0x0F70;
+
+// ------------------------------------------------------------- diagonals
+__host__ __device__ constexpr int diag_pairs(int s, int g) {
+    int lo = g - s > 1 ? g - s : 1;
+    int hi = g - 1 < s ? g - 1 : s;
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// Pairs per slot at most: s (plain), s - 1 (split longest diagonal).
+static int max_slot_pairs(int s, int t, bool split) {
+    int m = 0;
+    for (int g = 2; g <= t; ++g) {
+        int p = diag_pairs(s, g);
+        if (split && g == t) p = (p + 1) / 2;
+        if (p > m) m = p;
     }
-    static constexpr int max_pairs() {
-        int m = 0;
-        for (int g = 2; g <= T; ++g) m = pairs(g) > m ? pairs(g) : m;
-        return m;
+    return m;
+}
+
+// K-length (multiple of 32) whose INT32 slot sums cannot overflow.
+static long long exact_len(int pairs) {
+    long long L = 2147483647LL / ((long long)pairs * 127 * 127);
+    return L / K_BLOCK * K_BLOCK;
+}
+
+template <int S, int T, bool SPLIT>
+struct Cfg {
+    static constexpr int NSLOT = (T - 1) + (SPLIT ? 1 : 0);
+    // wave tile WM x WN blocks of 32x32; workgroup WAVES_M x WAVES_N waves.
+    // Two 32x32 blocks per wave while the accumulators fit two waves per
+    // SIMD (16 NSLOT VGPRs per block), else one.
+    static constexpr int WM = 1;
+    static constexpr int WN = (NSLOT <= 5) ? 2 : 1;
+    static constexpr int WAVES_M = (WN == 2) ? 4 : 2;
+    static constexpr int WAVES_N = (WN == 2) ? 2 : 4;
+    static constexpr int NW = WAVES_M * WAVES_N;
+    static constexpr int THREADS = 64 * NW;
+    static constexpr int TM = WAVES_M * WM;     // 32-row blocks per tile
+    static constexpr int TN = WAVES_N * WN;     // 32-column blocks per tile
+    static constexpr int FRA = S * TM;
+    static constexpr int FRB = S * TN;
+    static constexpr int FR = FRA + FRB;        // fragments per K step
+    // slot of pair (i, j): diagonal g = i + j -> g - 2; with SPLIT the
+    // upper half of the longest diagonal goes to the extra slot.
+    static constexpr int slot(int i, int j) {
+        return (SPLIT && i + j == T && i > (S + 1) / 2) ? T - 1 : i + j - 2;
     }
 };
 
-// Largest multiple of 32 such that max_pairs * L * 127^2 <= 2^31 - 1.
-static int chunk_len(int s, int t) {
-    int lo_pairs = 0;
-    for (int g = 2; g <= t; ++g) {
-        int lo = g - s > 1 ? g - s : 1;
-        int hi = g - 1 < s ? g - 1 : s;
-        if (hi - lo + 1 > lo_pairs) lo_pairs = hi - lo + 1;
-    }
-    long long L = 2147483647LL / ((long long)lo_pairs * 127 * 127);
-    return (int)(L / 32 * 32);
+struct GemmArgs {
+    const int8_t *Ap;
+    const int8_t *Bp;
+    size_t a_plane, b_plane;
+    const int *codeA;
+    const int *codeB;
+    int M, N, KB;         // logical sizes, K in 32-blocks
+    int chunk_kb;         // K-blocks per chunk (chunked partial mode)
+    int tiles_m, tiles_n;
+    double alpha, beta;
+    double *C;
+    long long ldc;
+    int32_t *part;        // chunk partials [chunk][g-2][n][m]
+};
+
+// XCD-aware tile order: consecutive workgroups go to different XCDs
+// (round-robin dispatch), so give XCD x the contiguous range of tile ids
+// x*per.., then walk tiles in groups of GROUP_M tile rows.
+__device__ __forceinline__ void tile_of(int L, int tiles_m, int tiles_n, int *tm,
+                                        int *tn) {
+    constexpr int NXCD = 8, GROUP_M = 8;
+    const int num = tiles_m * tiles_n;
+    const int xcd = L % NXCD, q = L / NXCD;
+    const int per = num / NXCD, rem = num % NXCD;
+    const int pid = xcd < rem ? xcd * (per + 1) + q
+                              : rem * (per + 1) + (xcd - rem) * per + q;
+    const int group_size = GROUP_M * tiles_n;
+    const int first_m = (pid / group_size) * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int in = pid % group_size;
+    *tm = first_m + in % gm;
+    *tn = in / gm;
 }
 
-constexpr int WG_M = 64;   // workgroup tile: 64 rows x 64 columns of C
-constexpr int WG_N = 64;
+// MODE 0: recombine into C.  MODE 2: write chunk partial INT32 D_g.
+template <int S, int T, bool SPLIT, int MODE>
+__global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
+    using CF = Cfg<S, T, SPLIT>;
+    static_assert(CF::THREADS == 512, "launch bounds assume 8 waves");
+    constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
+    constexpr int NSLOT = CF::NSLOT;
+    __shared__ __attribute__((aligned(1024))) int8_t lds0[FR * FRAG_BYTES];
+    __shared__ __attribute__((aligned(1024))) int8_t lds1[FR * FRAG_BYTES];
 
-// MODE 0: recombine into C.  MODE 1: write D_g (int64) to Dout.
-// CHUNKED: K is longer than one exactness chunk (separate instantiation so
-// that the common case carries no INT64 bookkeeping in its registers).
-template <int S, int T, int MODE, bool CHUNKED>
-__global__ __launch_bounds__(256) void k_slicegemm(
-    const int8_t *__restrict__ Ap, size_t a_plane, int a_KB,
-    const int8_t *__restrict__ Bp, size_t b_plane, int b_KB,
-    const int *__restrict__ codeA, const int *__restrict__ codeB, int M, int N,
-    int KB, int chunk_blocks, double alpha, double beta, double *__restrict__ C,
-    long long ldc, int64_t *__restrict__ Dout, int64_t *__restrict__ ws) {
-    constexpr int NACC = Diag<S, T>::NACC;
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int mb = blockIdx.x * 2 + (w & 1);    // 32-row block of C / A lines
-    const int nbk = blockIdx.y * 2 + (w >> 1);  // 32-column block of C / B lines
+    // wave index as a uniform (scalar) value, so per-wave addresses live in SGPRs
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int tm, tn;
+    tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
+    const int mb0 = tm * TM, nb0 = tn * TN;
+    const int wm = w % CF::WAVES_M, wn = w / CF::WAVES_M;
 
-    v16i acc[NACC];
-#pragma unroll
-    for (int g = 0; g < NACC; ++g)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[g][r] = 0;
-
-    const int8_t *pa = Ap + (size_t)mb * a_KB * FRAG_BYTES + (size_t)lane * 16;
-    const int8_t *pb = Bp + (size_t)nbk * b_KB * FRAG_BYTES + (size_t)lane * 16;
-    constexpr bool chunked = CHUNKED;
-    int64_t *wsp = nullptr;
-    if (chunked) {
-        size_t tile = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        wsp = ws + ((tile * 4 + w) * NACC) * 16 * 64 + lane;
+    int kb0 = 0, kb1 = p.KB;
+    if (MODE == 2) {
+        kb0 = blockIdx.y * p.chunk_kb;
+        kb1 = min(p.KB, kb0 + p.chunk_kb);
     }
 
-    for (int kb = 0; kb < KB; ++kb) {
-        v4i a[S], b[S];
+    // fragment sources of this wave for one K step (uniform per wave)
+    const int8_t *src[(FR + NW - 1) / NW];
 #pragma unroll
-        for (int d = 0; d < S; ++d)
-            a[d] = *reinterpret_cast<const v4i *>(pa + d * a_plane + (size_t)kb * FRAG_BYTES);
+    for (int q = 0; q < (FR + NW - 1) / NW; ++q) {
+        const int f = q * NW + w;
+        const int8_t *s_ = nullptr;
+        if (f < FRA) {
+            const int d = f / TM, i = f % TM;
+            s_ = p.Ap + d * p.a_plane + (size_t)(mb0 + i) * p.KB * FRAG_BYTES;
+        } else if (f < FR) {
+            const int g = f - FRA;
+            const int d = g / TN, j = g % TN;
+            s_ = p.Bp + d * p.b_plane + (size_t)(nb0 + j) * p.KB * FRAG_BYTES;
+        }
+        src[q] = s_ ? s_ + lane * 16 : nullptr;
+    }
+    auto issue = [&](int8_t *buf, int kb) {
 #pragma unroll
-        for (int d = 0; d < S; ++d)
-            b[d] = *reinterpret_cast<const v4i *>(pb + d * b_plane + (size_t)kb * FRAG_BYTES);
+        for (int q = 0; q < (FR + NW - 1) / NW; ++q) {
+            const int f = q * NW + w;
+            if (f < FR)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(src[q] + (size_t)kb * FRAG_BYTES),
+                    (void *)(buf + f * FRAG_BYTES), 16, 0, 0);
+        }
+    };
+
+    v16i acc[CF::WM][CF::WN][NSLOT];
 #pragma unroll
-        for (int i = 1; i <= S; ++i)
+    for (int i = 0; i < CF::WM; ++i)
 #pragma unroll
-            for (int j = 1; j <= S; ++j)
-                if (i + j <= T)
-                    acc[i + j - 2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                        b[j - 1], a[i - 1], acc[i + j - 2], 0, 0, 0);
-        if (chunked && (kb % chunk_blocks) == chunk_blocks - 1 && kb != KB - 1) {
-            const bool first = kb == chunk_blocks - 1;
+        for (int j = 0; j < CF::WN; ++j)
 #pragma unroll
-            for (int g = 0; g < NACC; ++g)
+            for (int g = 0; g < NSLOT; ++g)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    int64_t *p = wsp + (g * 16 + r) * 64;
-                    *p = (first ? 0 : *p) + (int64_t)acc[g][r];
-                    acc[g][r] = 0;
+                for (int r = 0; r < 16; ++r) acc[i][j][g][r] = 0;
+
+    if (kb0 < kb1) issue(lds0, kb0);
+    for (int kb = kb0; kb < kb1; ++kb) {
+        const int it = kb - kb0;
+        __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+        __syncthreads();
+        const int8_t *cur = (it & 1) ? lds1 : lds0;
+        if (kb + 1 < kb1) issue((it & 1) ? lds0 : lds1, kb + 1);
+#pragma unroll
+        for (int i = 0; i < CF::WM; ++i) {
+#pragma unroll
+            for (int j = 0; j < CF::WN; ++j) {
+                // all B digits of this block stay in registers; A digits are
+                // streamed, most-used first (digit ii pairs with T - ii
+                // B digits), so each LDS read is covered by the MFMAs of the
+                // digit before it
+                v4i b[S];
+#pragma unroll
+                for (int d = 0; d < S; ++d)
+                    b[d] = *reinterpret_cast<const v4i *>(
+                        cur + (FRA + d * TN + wn * CF::WN + j) * FRAG_BYTES + lane * 16);
+                const int8_t *pa = cur + (wm * CF::WM + i) * FRAG_BYTES + lane * 16;
+                v4i a = *reinterpret_cast<const v4i *>(pa);
+                // schedule: the B reads and the first A read, then for each A
+                // digit the read of the next one ahead of this digit's MFMAs
+                __builtin_amdgcn_sched_group_barrier(0x100, S + 1, 0);
+#pragma unroll
+                for (int ii = 1; ii <= S; ++ii) {
+                    v4i an = a;
+                    if (ii < S) {
+                        an = *reinterpret_cast<const v4i *>(pa + ii * TM * FRAG_BYTES);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
+#pragma unroll
+                    for (int jj = 1; jj <= S; ++jj)
+                        if (ii + jj <= T) {
+                            const int sl = CF::slot(ii, jj);
+                            acc[i][j][sl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                b[jj - 1], a, acc[i][j][sl], 0, 0, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        }
+                    a = an;
                 }
+            }
         }
     }
 
-    const int m = mb * 32 + (lane & 31);
-    if (m >= M) return;
-    int ca = codeA[m];
-    const bool badA = ca == CODE_NONFINITE;
-    const int ea = (ca == CODE_ZERO || badA) ? 0 : ca;
+    // ---------------------------------------------------------- epilogue
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int n = nbk * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (n >= N) continue;
-        int64_t D[NACC];
+    for (int i = 0; i < CF::WM; ++i) {
+        const int m = (mb0 + wm * CF::WM + i) * 32 + (lane & 31);
+        if (m >= p.M) continue;
+        const int ca = p.codeA[m];
+        const bool badA = ca == CODE_NONFINITE;
+        const int ea = (ca == CODE_ZERO || badA) ? 0 : ca;
 #pragma unroll
-        for (int g = 0; g < NACC; ++g) {
-            D[g] = (int64_t)acc[g][r];
-            if (chunked) D[g] += wsp[(g * 16 + r) * 64];
-        }
-        if (MODE == 1) {
+        for (int j = 0; j < CF::WN; ++j) {
+            const int nbase = (nb0 + wn * CF::WN + j) * 32 + 4 * (lane >> 5);
 #pragma unroll
-            for (int g = 0; g < NACC; ++g)
-                Dout[((size_t)g * N + n) * M + m] = D[g];
-        } else {
-            const int cb = codeB[n];
-            const bool badB = cb == CODE_NONFINITE;
-            const int eb = (cb == CODE_ZERO || badB) ? 0 : cb;
-            double Ssum = 0.0;
+            for (int r = 0; r < 16; ++r) {
+                const int n = nbase + 8 * (r >> 2) + (r & 3);
+                if (n >= p.N) continue;
+                if (MODE == 2) {
 #pragma unroll
-            for (int g = NACC - 1; g >= 0; --g) {
-                // weight 2^-7(g+2), exact power of two
-                const double wgt = __longlong_as_double(
-                    (long long)(1023 - 7 * (g + 2)) << 52);
-                Ssum = Ssum + (double)D[g] * wgt;
+                    for (int g = 0; g < T - 1; ++g)
+                        p.part[(((size_t)blockIdx.y * (T - 1) + g) * p.N + n) * p.M + m] =
+                            acc[i][j][g][r];
+                } else {
+                    const int cb = p.codeB[n];
+                    const bool badB = cb == CODE_NONFINITE;
+                    const int eb = (cb == CODE_ZERO || badB) ? 0 : cb;
+                    double Ssum = 0.0;
+#pragma unroll
+                    for (int g = T - 2; g >= 0; --g) {
+                        long long D = acc[i][j][g][r];
+                        if (SPLIT && g == T - 2) D += acc[i][j][T - 1][r];
+                        // weight 2^-7(g+2), an exact power of two
+                        const double wgt =
+                            __longlong_as_double((long long)(1023 - 7 * (g + 2)) << 52);
+                        Ssum = Ssum + (double)D * wgt;
+                    }
+                    const double X = ldexp(Ssum, ea + eb);
+                    double *pc = p.C + (size_t)n * p.ldc + m;
+                    double out = (p.beta == 0.0) ? fma(p.alpha, X, 0.0)
+                                                 : fma(p.alpha, X, p.beta * *pc);
+                    if (badA || badB) out = __builtin_nan("");
+                    *pc = out;
+                }
             }
-            const double X = ldexp(Ssum, ea + eb);
-            double *pc = C + (size_t)n * ldc + m;
-            double out = (beta == 0.0) ? fma(alpha, X, 0.0) : fma(alpha, X, beta * *pc);
-            if (badA || badB) out = __builtin_nan("");
-            *pc = out;
         }
     }
 }
 
+// Chunk combine: D_g = sum over chunks (INT64), then either the raw sums
+// (debug, Dout != null) or the recombination into C.
+template <int T>
+__global__ __launch_bounds__(256) void k_combine(GemmArgs p, int nchunks, int64_t *Dout) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long MN = (long long)p.M * p.N;
+    if (idx >= MN) return;
+    const int m = (int)(idx % p.M), n = (int)(idx / p.M);
+    long long D[T - 1];
+#pragma unroll
+    for (int g = 0; g < T - 1; ++g) {
+        long long acc = 0;
+        for (int c = 0; c < nchunks; ++c) acc += p.part[((size_t)c * (T - 1) + g) * MN + idx];
+        D[g] = acc;
+    }
+    if (Dout) {
+#pragma unroll
+        for (int g = 0; g < T - 1; ++g) Dout[(size_t)g * MN + idx] = D[g];
+        return;
+    }
+    const int ca = p.codeA[m], cb = p.codeB[n];
+    const bool bad = ca == CODE_NONFINITE || cb == CODE_NONFINITE;
+    const int ea = (ca == CODE_ZERO || ca == CODE_NONFINITE) ? 0 : ca;
+    const int eb = (cb == CODE_ZERO || cb == CODE_NONFINITE) ? 0 : cb;
+    double Ssum = 0.0;
+#pragma unroll
+    for (int g = T - 2; g >= 0; --g) {
+        const double wgt = __longlong_as_double((long long)(1023 - 7 * (g + 2)) << 52);
+        Ssum = Ssum + (double)D[g] * wgt;
+    }
+    const double X = ldexp(Ssum, ea + eb);
+    double *pc = p.C + (size_t)n * p.ldc + m;
+    double out = (p.beta == 0.0) ? fma(p.alpha, X, 0.0) : fma(p.alpha, X, p.beta * *pc);
+    if (bad) out = __builtin_nan("");
+    *pc = out;
+}
+
+// ---------------------------------------------------------------- host
 bool gemm_supported(int s, int t) {
     if (s < 1 || s > EMU_MAX_SLICES) return false;
     if (t == s + 1) return true;
@@ -167,64 +327,115 @@ bool gemm_supported(int s, int t) {
     return false;
 }
 
-size_t gemm_chunk_bytes(int m, int n, int k, int s, int t) {
-    int L = chunk_len(s, t);
-    int KB = (k + K_BLOCK - 1) / K_BLOCK;
-    if (KB <= L / K_BLOCK) return 0;
-    size_t tiles = (size_t)((m + WG_M - 1) / WG_M) * ((n + WG_N - 1) / WG_N);
-    return tiles * 4 * (size_t)(t - 1) * 16 * 64 * sizeof(int64_t);
+static bool split_available(int s, int t) { return t == s + 1 && s >= 3; }
+
+// How a product of depth k is cut: 0 chunks = one pass (split tells the
+// variant); otherwise nchunks partial passes of chunk_kb K-blocks.
+struct Plan {
+    bool split = false;
+    int nchunks = 0;
+    int chunk_kb = 0;
+    int plain_kb = 0;     // longest exact K (in blocks) of one plain pass
+};
+
+static Plan plan_for(int k, int s, int t) {
+    Plan pl;
+    const long long KB = (k + K_BLOCK - 1) / K_BLOCK;
+    const long long plain = exact_len(max_slot_pairs(s, t, false)) / K_BLOCK;
+    pl.plain_kb = (int)plain;
+    if (KB <= plain) return pl;
+    if (split_available(s, t)) {
+        const long long sp = exact_len(max_slot_pairs(s, t, true)) / K_BLOCK;
+        if (KB <= sp) {
+            pl.split = true;
+            return pl;
+        }
+    }
+    pl.chunk_kb = (int)plain;
+    pl.nchunks = (int)((KB + plain - 1) / plain);
+    return pl;
+}
+
+size_t gemm_chunk_bytes(int m, int n, int k, int s, int t, bool raw_sums) {
+    Plan pl = plan_for(k, s, t);
+    if (pl.nchunks == 0 && !raw_sums) return 0;
+    const int KB = (k + K_BLOCK - 1) / K_BLOCK;
+    const int nchunks = (KB + pl.plain_kb - 1) / pl.plain_kb;
+    return (size_t)nchunks * (t - 1) * (size_t)m * n * sizeof(int32_t);
+}
+
+template <int S, int T, bool SPLIT, int MODE>
+static int launch_cfg(const GemmArgs &a0, int nchunks, hipStream_t stream) {
+    using CF = Cfg<S, T, SPLIT>;
+    GemmArgs a = a0;
+    a.tiles_m = (a.M + CF::TM * 32 - 1) / (CF::TM * 32);
+    a.tiles_n = (a.N + CF::TN * 32 - 1) / (CF::TN * 32);
+    dim3 grid((unsigned)(a.tiles_m * a.tiles_n), MODE == 2 ? nchunks : 1);
+    hipLaunchKernelGGL((k_slicegemm<S, T, SPLIT, MODE>), grid, dim3(CF::THREADS), 0,
+                       stream, a);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
 }
 
 template <int S, int T>
-static void launch_st(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
-                      const Planes &gb, const int *codeA, const int *codeB, int m,
-                      int n, int KB, int chunk_blocks, double alpha, double beta,
-                      double *C, long long ldc, int64_t *Dout, int64_t *ws,
-                      hipStream_t stream) {
-    dim3 grid((m + WG_M - 1) / WG_M, (n + WG_N - 1) / WG_N);
-    const bool chunked = chunk_blocks < KB;
-#define EMU_LAUNCH(MODE_, CH_)                                                      \
-    hipLaunchKernelGGL((k_slicegemm<S, T, MODE_, CH_>), grid, dim3(256), 0, stream, Ap, \
-                       ga.plane_bytes, ga.KB, Bp, gb.plane_bytes, gb.KB, codeA, codeB, \
-                       m, n, KB, chunk_blocks, alpha, beta, C, ldc, Dout, ws)
-    if (Dout) {
-        if (chunked) EMU_LAUNCH(1, true); else EMU_LAUNCH(1, false);
-    } else {
-        if (chunked) EMU_LAUNCH(0, true); else EMU_LAUNCH(0, false);
+static int launch_st(const GemmArgs &a, const Plan &pl, int64_t *Dout,
+                     hipStream_t stream) {
+    if (pl.nchunks == 0 && Dout == nullptr) {
+        if constexpr (T == S + 1 && S >= 3) {
+            if (pl.split) return launch_cfg<S, T, true, 0>(a, 0, stream);
+        }
+        return launch_cfg<S, T, false, 0>(a, 0, stream);
     }
-#undef EMU_LAUNCH
+    // chunked partial passes of exact INT32 length (also the raw-sum debug
+    // path, which always lands in the combine kernel)
+    GemmArgs b = a;
+    b.chunk_kb = pl.plain_kb;
+    const int nchunks = (a.KB + pl.plain_kb - 1) / pl.plain_kb;
+    EMU_TRY((launch_cfg<S, T, false, 2>(b, nchunks, stream)));
+    const long long MN = (long long)a.M * a.N;
+    hipLaunchKernelGGL(k_combine<T>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0,
+                       stream, b, nchunks, Dout);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
 }
 
 int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
                      const Planes &gb, const int *codeA, const int *codeB, int m,
                      int n, int k, int s, int t, double alpha, double beta,
-                     double *C, long long ldc, int64_t *Dout, int64_t *ws_chunk,
+                     double *C, long long ldc, int64_t *Dout, int32_t *ws_part,
                      hipStream_t stream) {
     if (!gemm_supported(s, t)) {
         set_error("unsupported slice count / threshold (s=%d, t=%d)", s, t);
         return EMU_ERR_UNSUPPORTED;
     }
-    const int KB = (k + K_BLOCK - 1) / K_BLOCK;
-    const int chunk_blocks = chunk_len(s, t) / K_BLOCK;
-    if (chunk_blocks < KB && ws_chunk == nullptr) {
-        set_error("K-chunk scratch missing");
+    Plan pl = plan_for(k, s, t);
+    if ((pl.nchunks > 0 || Dout) && ws_part == nullptr) {
+        set_error("chunk scratch missing");
         return EMU_ERR_WORKSPACE;
     }
-#define EMU_CASE(S_, T_)                                                          \
-    if (s == S_ && t == T_) {                                                     \
-        launch_st<S_, T_>(Ap, ga, Bp, gb, codeA, codeB, m, n, KB, chunk_blocks,    \
-                          alpha, beta, C, ldc, Dout, ws_chunk, stream);           \
-    } else
+    GemmArgs a{};
+    a.Ap = Ap;
+    a.Bp = Bp;
+    a.a_plane = ga.plane_bytes;
+    a.b_plane = gb.plane_bytes;
+    a.codeA = codeA;
+    a.codeB = codeB;
+    a.M = m;
+    a.N = n;
+    a.KB = ga.KB;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.C = C;
+    a.ldc = ldc;
+    a.part = ws_part;
+#define EMU_CASE(S_, T_) \
+    if (s == S_ && t == T_) return launch_st<S_, T_>(a, pl, Dout, stream);
     EMU_CASE(1, 2) EMU_CASE(2, 3) EMU_CASE(3, 4) EMU_CASE(4, 5) EMU_CASE(5, 6)
     EMU_CASE(6, 7) EMU_CASE(7, 8) EMU_CASE(8, 9) EMU_CASE(9, 10)
     EMU_CASE(2, 4) EMU_CASE(3, 6) EMU_CASE(4, 8) EMU_CASE(5, 10)
-    {
-        set_error("no kernel for s=%d t=%d", s, t);
-        return EMU_ERR_UNSUPPORTED;
-    }
 #undef EMU_CASE
-    EMU_TRY_HIP(hipGetLastError());
-    return 0;
+    set_error("no kernel for s=%d t=%d", s, t);
+    return EMU_ERR_UNSUPPORTED;
 }
 
 }  // namespace emu
