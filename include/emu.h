@@ -52,6 +52,8 @@ extern "C" {
 #define EMU_ERR_HIP            1001  /* a HIP runtime call failed */
 #define EMU_ERR_WORKSPACE      1002  /* scratch allocation failed */
 #define EMU_ERR_UNSUPPORTED    1003  /* valid request this build cannot run */
+#define EMU_ERR_NOT_CONVERGED  1004  /* refinement missed its tolerance at the
+                                        largest slice count */
 
 #define EMU_STATUS_NONFINITE   1     /* an emulated GEMM met Inf/NaN input */
 
@@ -145,6 +147,43 @@ int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info,
  */
 int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
                double *B, int ldb);
+
+/*
+ * emu_set_param: library knobs (thread-local).  Keys:
+ *   "ir_force_fail" (value >= 0): the next `value` convergence checks of
+ *   emu_dgesv_ir on this thread count as failed, which exercises the
+ *   fallback to more slices (a test hook; the checks still run).
+ * Returns -1 for an unknown key, -2 for an invalid value.
+ */
+int emu_set_param(const char *key, long long value);
+
+/*
+ * emu_dgesv_ir: solve A X = B to a backward-error tolerance with the
+ * precision form: emulated LU with a reduced slice count, FP64 solves and
+ * FP64 iterative refinement, falling back to more slices when refinement
+ * stalls (this form is not in the paper; the stopping quantity is eqn (9)'s
+ * scaled residual without its n eps factor).
+ *   1. LU of a copy of A (A itself is not modified) with `nslices` slices and
+ *      block size nb (nb <= 0: 64); X = getrs(B).
+ *   2. Repeat: R = B - A X in FP64; eta = max over columns of
+ *      ||R||_inf / (||A||_inf ||X||_inf + ||B||_inf).  Stop when eta <= tol.
+ *      Otherwise, if eta did not fall below half its previous value, or
+ *      `maxiter` corrections were applied, or eta is NaN: fall back (step 3);
+ *      else X += getrs(R).
+ *   3. Fallback: refactor with s = min(s + 2, EMU_MAX_SLICES) and restart at
+ *      step 1's solve; if s was already EMU_MAX_SLICES return
+ *      EMU_ERR_NOT_CONVERGED.
+ * A n x n (lda >= max(1,n)), B and X n x nrhs (ldb, ldx >= max(1,n)), all
+ * device; outputs on the HOST: *iters = corrections applied (all
+ * factorizations), *berr = last eta, *s_final = slice count of the last
+ * factorization, *info = its LAPACK info (> 0: exactly singular U, X not
+ * refined).  Synchronizes the stream once per refinement step.
+ * Argument numbers: n=1 nrhs=2 A=3 lda=4 B=5 ldb=6 X=7 ldx=8 nb=9
+ * nslices=10 tol=11 maxiter=12 iters=13 berr=14 s_final=15 info=16.
+ */
+int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int ldb,
+                 double *X, int ldx, int nb, int nslices, double tol, int maxiter,
+                 int *iters, double *berr, int *s_final, int *info);
 
 /*
  * emu_debug_slices: expose the exponent scan and digit slicing of one

@@ -18,10 +18,13 @@ Parity status of each function (what pins it, in tests/test_oracle_pins.py):
                                   (eqns (10)-(12)), PA = LU, LAPACK-style
                                   info on singular input
   backward_error/scaled_residual - eqn (9) identity, exact rational residual
+  gesv_ir                       - the delivered solution's double-double
+                                  backward error meets the tolerance; forced
+                                  failures take the fallback
 """
 from .emu import (  # noqa: F401
     DIGIT_BITS, EPS, line_exponents, slice_digits, slice_products, recombine,
     dgemm_emu, dgemm_dd, rel_err_fro, getf2, trsm_unit_lower, laswp, getrf,
-    getrs, residual_dd, backward_error, scaled_residual, pa_minus_lu,
+    getrs, residual_dd, backward_error, scaled_residual, pa_minus_lu, gesv_ir,
 )
 from ._clib import build_oracle  # noqa: F401

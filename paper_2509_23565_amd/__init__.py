@@ -25,6 +25,7 @@ __all__ = [
     "emu_status", "emu_dgemm", "emu_dgemm_t", "emu_dgetrf", "emu_dgetrs",
     "emu_debug_slices", "emu_debug_products", "emu_profile_start",
     "emu_profile_stop", "emu_profile_read", "profile_read", "PROF_SLICE", "PROF_GEMM",
+    "emu_set_param", "emu_dgesv_ir", "set_param", "dgesv_ir",
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status",
 ]
@@ -56,6 +57,10 @@ _SIGNATURES = {
     "emu_dgetrs": ([_I, _I, _P, _I, _P, _P, _I], _I),
     "emu_debug_slices": ([_I, _I, _P, _I, _I, _I, _P, _P, _P], _I),
     "emu_debug_products": ([_I, _I, _I, _P, _I, _P, _I, _I, _I, _P], _I),
+    "emu_set_param": ([ctypes.c_char_p, ctypes.c_longlong], _I),
+    "emu_dgesv_ir": ([_I, _I, _P, _I, _P, _I, _P, _I, _I, _I, _D, _I,
+                      ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_I),
+                      ctypes.POINTER(_I)], _I),
     "emu_profile_start": ([], _I),
     "emu_profile_stop": ([], _I),
     "emu_profile_read": ([_I, ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
@@ -99,6 +104,8 @@ emu_dgetrf = _raw("emu_dgetrf")
 emu_dgetrs = _raw("emu_dgetrs")
 emu_debug_slices = _raw("emu_debug_slices")
 emu_debug_products = _raw("emu_debug_products")
+emu_set_param = _raw("emu_set_param")
+emu_dgesv_ir = _raw("emu_dgesv_ir")
 emu_profile_start = _raw("emu_profile_start")
 emu_profile_stop = _raw("emu_profile_stop")
 emu_profile_read = _raw("emu_profile_read")
@@ -208,6 +215,36 @@ def dgetrs(LU, ipiv, B):
     _bind_stream()
     _check(emu_dgetrs(n, nrhs, pl, lda, ipiv.data_ptr(), pb, ldb), "emu_dgetrs")
     return B
+
+
+def set_param(key: str, value: int) -> None:
+    _check(emu_set_param(key.encode(), int(value)), "emu_set_param")
+
+
+def dgesv_ir(A, B, X=None, nb=64, nslices=3, tol=1e-15, maxiter=10):
+    """Precision-form solve; returns (X, dict(iters, berr, s_final, info, rc)).
+
+    rc is 0 on convergence or EMU_ERR_NOT_CONVERGED (1004); other codes raise.
+    """
+    torch = _torch()
+    n = A.shape[0]
+    nrhs = B.shape[1]
+    if X is None:
+        X = torch.empty((nrhs, n), dtype=torch.float64, device=A.device).t()
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    px, ldx = _mat(X, "X")
+    it = ctypes.c_int(0)
+    be = ctypes.c_double(0.0)
+    sf = ctypes.c_int(0)
+    inf = ctypes.c_int(0)
+    _bind_stream()
+    rc = emu_dgesv_ir(n, nrhs, pa, lda, pb, ldb, px, ldx, int(nb), int(nslices),
+                      float(tol), int(maxiter), ctypes.byref(it), ctypes.byref(be),
+                      ctypes.byref(sf), ctypes.byref(inf))
+    if rc not in (0, 1004):
+        _check(rc, "emu_dgesv_ir")
+    return X, dict(iters=it.value, berr=be.value, s_final=sf.value, info=inf.value, rc=rc)
 
 
 def debug_slices(X, by_rows, nslices):

@@ -163,12 +163,11 @@ struct ProfScope {
     }
 };
 
-// Emulated GEMM on reserved scratch (m, n, k > 0, alpha != 0).
-static int gemm_core(Device *dev, hipStream_t stream, const GemmScratch &g, int m,
-                     int n, int k, double alpha, const double *A, long long lda,
+// Emulated GEMM on reserved scratch at `ws` (m, n, k > 0, alpha != 0).
+static int gemm_core(Device *dev, char *ws, hipStream_t stream, const GemmScratch &g,
+                     int m, int n, int k, double alpha, const double *A, long long lda,
                      const double *B, long long ldb, double beta, double *C,
                      long long ldc, int s, int t, int64_t *Dout) {
-    char *ws = static_cast<char *>(dev->ws);
     int *codeA = reinterpret_cast<int *>(ws + g.off_codeA);
     int *codeB = reinterpret_cast<int *>(ws + g.off_codeB);
     int8_t *pa = reinterpret_cast<int8_t *>(ws + g.off_pa);
@@ -187,6 +186,49 @@ static int gemm_core(Device *dev, hipStream_t stream, const GemmScratch &g, int 
 }
 
 static inline int imax1(int a) { return a > 1 ? a : 1; }
+
+static thread_local int g_ir_force_fail = 0;
+
+// Scratch of one blocked LU: the largest trailing update's GEMM scratch
+// (the first update; later ones are smaller).
+static size_t getrf_scratch_bytes(int m, int n, int nb, int s) {
+    const int mn = m < n ? m : n;
+    if (nb <= 0) nb = 64;
+    const int jb0 = nb < mn ? nb : mn;
+    if (jb0 <= 0) return 256;
+    return gemm_scratch(m - jb0 > 0 ? m - jb0 : 1, n - jb0 > 0 ? n - jb0 : 1, jb0, s, s + 1)
+        .total;
+}
+
+static size_t getrs_scratch_bytes(int n, int nrhs) {
+    return align256((size_t)n * sizeof(int)) + align256((size_t)n * nrhs * sizeof(double));
+}
+
+// Right-looking blocked LU on reserved scratch `ws` (getrf_scratch_bytes).
+static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, double *A,
+                      long long ld, int *ipiv, int *info, int nb, int s) {
+    EMU_TRY(launch_fill_int(info, 0, 1, st));
+    const int mn = m < n ? m : n;
+    const int t = s + 1;
+    for (int j0 = 0; j0 < mn; j0 += nb) {
+        const int jb = nb < mn - j0 ? nb : mn - j0;
+        const int j1 = j0 + jb;
+        double *Ajj = A + j0 + (long long)j0 * ld;
+        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, st));
+        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, st));
+        if (j1 < n) {
+            double *U12 = A + j0 + (long long)j1 * ld;
+            EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));
+            if (j1 < m) {
+                GemmScratch gs = gemm_scratch(m - j1, n - j1, jb, s, t);
+                EMU_TRY(gemm_core(dev, ws, st, gs, m - j1, n - j1, jb, -1.0,
+                                  A + j1 + (long long)j0 * ld, ld, U12, ld, 1.0,
+                                  A + j1 + (long long)j1 * ld, ld, s, t, nullptr));
+            }
+        }
+    }
+    return 0;
+}
 
 }  // namespace emu
 
@@ -319,8 +361,8 @@ static int dgemm_impl(int m, int n, int k, double alpha, const double *A, int ld
     }
     GemmScratch g = gemm_scratch(m, n, k, s, t, Dout != nullptr);
     EMU_TRY(reserve(dev, st, g.total));
-    return gemm_core(dev, st, g, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, t,
-                     Dout);
+    return gemm_core(dev, static_cast<char *>(dev->ws), st, g, m, n, k, alpha, A, lda, B,
+                     ldb, beta, C, ldc, s, t, Dout);
 }
 
 int emu_dgemm(int m, int n, int k, double alpha, const double *A, int lda,
@@ -394,33 +436,9 @@ int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info, int nb,
     Device *dev;
     hipStream_t st;
     EMU_TRY(current(&dev, &st));
-    EMU_TRY(launch_fill_int(info, 0, 1, st));
-    if (mn == 0) return 0;
-    const int s = nslices, t = nslices + 1;
-    // the first trailing update is the largest
-    int jb0 = nb < mn ? nb : mn;
-    GemmScratch g = gemm_scratch(m - jb0 > 0 ? m - jb0 : 1, n - jb0 > 0 ? n - jb0 : 1,
-                                 jb0, s, t);
-    EMU_TRY(reserve(dev, st, g.total));
-    const long long ld = lda;
-    for (int j0 = 0; j0 < mn; j0 += nb) {
-        const int jb = nb < mn - j0 ? nb : mn - j0;
-        const int j1 = j0 + jb;
-        double *Ajj = A + j0 + (long long)j0 * ld;
-        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, st));
-        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, st));
-        if (j1 < n) {
-            double *U12 = A + j0 + (long long)j1 * ld;
-            EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));
-            if (j1 < m) {
-                GemmScratch gs = gemm_scratch(m - j1, n - j1, jb, s, t);
-                EMU_TRY(gemm_core(dev, st, gs, m - j1, n - j1, jb, -1.0,
-                                  A + j1 + (long long)j0 * ld, ld, U12, ld, 1.0,
-                                  A + j1 + (long long)j1 * ld, ld, s, t, nullptr));
-            }
-        }
-    }
-    return 0;
+    EMU_TRY(reserve(dev, st, getrf_scratch_bytes(m, n, nb, nslices)));
+    return getrf_impl(dev, static_cast<char *>(dev->ws), st, m, n, A, lda, ipiv, info, nb,
+                      nslices);
 }
 
 int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv, double *B,
@@ -440,9 +458,143 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv, doub
     Device *dev;
     hipStream_t st;
     EMU_TRY(current(&dev, &st));
-    size_t bytes = align256((size_t)n * sizeof(int)) + align256((size_t)n * nrhs * sizeof(double));
-    EMU_TRY(reserve(dev, st, bytes));
+    EMU_TRY(reserve(dev, st, getrs_scratch_bytes(n, nrhs)));
     return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, static_cast<int *>(dev->ws), st);
+}
+
+int emu_set_param(const char *key, long long value) {
+    if (!key) return -1;
+    if (std::strcmp(key, "ir_force_fail") == 0) {
+        if (value < 0) return -2;
+        g_ir_force_fail = (int)value;
+        return 0;
+    }
+    set_error("emu_set_param: unknown key \"%s\"", key);
+    return -1;
+}
+
+int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int ldb,
+                 double *X, int ldx, int nb, int nslices, double tol, int maxiter,
+                 int *iters, double *berr, int *s_final, int *info) {
+    if (n < 0) return -1;
+    if (nrhs < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < imax1(n)) return -4;
+    if (n > 0 && nrhs > 0 && !B) return -5;
+    if (ldb < imax1(n)) return -6;
+    if (n > 0 && nrhs > 0 && !X) return -7;
+    if (ldx < imax1(n)) return -8;
+    if (nb > 1024) return -9;
+    if (nslices < 1 || nslices > EMU_MAX_SLICES) return -10;
+    if (!(tol > 0.0)) return -11;
+    if (maxiter < 0) return -12;
+    if (!iters) return -13;
+    if (!berr) return -14;
+    if (!s_final) return -15;
+    if (!info) return -16;
+    if (nb <= 0) nb = 64;
+    *iters = 0;
+    *berr = 0.0;
+    *s_final = nslices;
+    *info = 0;
+    if (n == 0 || nrhs == 0) return 0;
+    if (nrhs > 65535) {
+        set_error("emu_dgesv_ir: nrhs above 65535");
+        return EMU_ERR_UNSUPPORTED;
+    }
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    // scratch: LU copy | ipiv | info | R | partials | norm + stats | LU/solve scratch
+    size_t off = 0;
+    const size_t o_lu = off;
+    off += align256((size_t)n * n * sizeof(double));
+    const size_t o_ipiv = off;
+    off += align256((size_t)n * sizeof(int));
+    const size_t o_info = off;
+    off += align256(sizeof(int));
+    const size_t o_r = off;
+    off += align256((size_t)n * nrhs * sizeof(double));
+    const size_t o_part = off;
+    off += align256(refine_partial_bytes(n, nrhs));
+    const size_t o_stats = off;
+    off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
+    const size_t o_sub = off;
+    size_t sub = getrf_scratch_bytes(n, n, nb, EMU_MAX_SLICES);
+    const size_t sub2 = getrs_scratch_bytes(n, nrhs);
+    if (sub2 > sub) sub = sub2;
+    off += sub;
+    EMU_TRY(reserve(dev, st, off));
+    char *ws = static_cast<char *>(dev->ws);
+    double *LU = reinterpret_cast<double *>(ws + o_lu);
+    int *ipiv = reinterpret_cast<int *>(ws + o_ipiv);
+    int *dinfo = reinterpret_cast<int *>(ws + o_info);
+    double *R = reinterpret_cast<double *>(ws + o_r);
+    double *part = reinterpret_cast<double *>(ws + o_part);
+    double *normA = reinterpret_cast<double *>(ws + o_stats);
+    double *stats = normA + 1;
+    char *subws = ws + o_sub;
+
+    EMU_TRY(launch_norm_inf(A, lda, n, part, normA, st));
+    double hnorm = 0.0;
+    std::vector<double> hstats(3 * (size_t)nrhs);
+    int force = g_ir_force_fail;
+    int s = nslices;
+    int total_iters = 0;
+    for (;;) {
+        // factor a copy of A with s slices and solve
+        EMU_TRY(launch_copy_mat(A, lda, LU, n, n, n, st));
+        EMU_TRY(getrf_impl(dev, subws, st, n, n, LU, n, ipiv, dinfo, nb, s));
+        int hinfo = 0;
+        EMU_TRY_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, st));
+        EMU_TRY_HIP(hipStreamSynchronize(st));
+        *info = hinfo;
+        *s_final = s;
+        if (hinfo > 0) return 0;       // exactly singular U: nothing to refine
+        EMU_TRY(launch_copy_mat(B, ldb, X, ldx, n, nrhs, st));
+        EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, X, ldx, reinterpret_cast<int *>(subws), st));
+        double prev = -1.0;
+        bool fallback = false;
+        for (int it = 0;; ++it) {
+            EMU_TRY(launch_residual(A, lda, n, X, ldx, B, ldb, nrhs, R, n, part, stats, st));
+            EMU_TRY_HIP(hipMemcpyAsync(hstats.data(), stats, hstats.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, st));
+            EMU_TRY_HIP(hipMemcpyAsync(&hnorm, normA, sizeof(double), hipMemcpyDeviceToHost, st));
+            EMU_TRY_HIP(hipStreamSynchronize(st));
+            double eta = 0.0;
+            for (int r = 0; r < nrhs; ++r) {
+                const double den = hnorm * hstats[3 * r + 1] + hstats[3 * r + 2];
+                const double e = den > 0.0 ? hstats[3 * r] / den : hstats[3 * r];
+                if (!(e <= eta)) eta = e;     // NaN propagates
+            }
+            *berr = eta;
+            *iters = total_iters;
+            bool forced = false;
+            if (force > 0) {
+                --force;
+                forced = true;
+            }
+            if (!forced && eta <= tol) return 0;
+            // stagnation (less than a halving), the step budget, or a forced
+            // failure: refactor with more slices
+            if (forced || it >= maxiter || (prev >= 0.0 && !(eta <= 0.5 * prev)) || eta != eta) {
+                fallback = true;
+                break;
+            }
+            prev = eta;
+            EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, R, n, reinterpret_cast<int *>(subws), st));
+            EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
+            ++total_iters;
+        }
+        if (fallback) {
+            if (s >= EMU_MAX_SLICES) {
+                set_error("emu_dgesv_ir: no convergence to %g at %d slices (eta %g)", tol, s,
+                          *berr);
+                return EMU_ERR_NOT_CONVERGED;
+            }
+            s = s + 2 < EMU_MAX_SLICES ? s + 2 : EMU_MAX_SLICES;
+        }
+    }
 }
 
 }  // extern "C"

@@ -120,4 +120,16 @@ int launch_getrs(int n, int nrhs, const double *LU, long long lda,
                  const int *ipiv, double *B, long long ldb, int *perm_ws,
                  hipStream_t stream);
 
+// Precision form (refine.hip).
+size_t refine_partial_bytes(int n, int nrhs);
+int launch_norm_inf(const double *A, long long lda, int n, double *partial, double *out,
+                    hipStream_t stream);
+int launch_residual(const double *A, long long lda, int n, const double *X, long long ldx,
+                    const double *B, long long ldb, int nrhs, double *R, long long ldr,
+                    double *partial, double *stats, hipStream_t stream);
+int launch_add_cols(double *X, long long ldx, const double *D, long long ldd, int n,
+                    int nrhs, hipStream_t stream);
+int launch_copy_mat(const double *src, long long lds_, double *dst, long long ldd, int n,
+                    int cols, hipStream_t stream);
+
 }  // namespace emu

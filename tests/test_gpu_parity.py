@@ -263,3 +263,48 @@ def test_turing_and_wilkinson_closed_forms(s):
     last = _host(Wg)[:, n - 1]
     exact = np.array_equal(last, 2.0 ** np.arange(n))
     assert exact == (s >= 5)          # 7 s bits must cover a 32-row block's 2^31 spread
+
+
+# ----------------------------------------------------------- precision form
+
+@pytest.mark.parametrize("n,phi,s,nrhs", [(512, 1.0, 3, 1), (700, 0.0, 4, 3),
+                                          (1024, 1.0, 5, 1), (1500, 2.0, 3, 2)])
+def test_refinement_reaches_1e15(n, phi, s, nrhs):
+    A = matgen.phi_matrix(n, n, phi, seed=21)
+    B = matgen.uniform(n, nrhs, seed=22)
+    Xg, inf = emu.dgesv_ir(emu.colmajor(A), emu.colmajor(B), nb=64, nslices=s, tol=1e-15)
+    Xo, info_o = O.gesv_ir(A, B, nb=64, s=s, tol=1e-15)
+    X = _host(Xg)
+    eta = O.backward_error(A, X, B)          # double-double residual
+    print(f"n={n} phi={phi} s={s}: GPU iters {inf['iters']} berr {inf['berr']:.2e} "
+          f"(dd {eta:.2e}); oracle iters {info_o['iters']}")
+    assert inf["rc"] == 0 and inf["info"] == 0 and inf["s_final"] == s
+    assert eta <= 1e-15
+    assert info_o["converged"] and abs(inf["iters"] - info_o["iters"]) <= 1
+    # both solutions solve the same system to ~1e-15 backward error
+    assert np.abs(X - Xo).max() <= 1e-12 * np.abs(Xo).max()
+
+
+def test_refinement_fallback_paths_match_oracle():
+    A = matgen.phi_matrix(400, 400, 1.0, seed=23)
+    B = matgen.uniform(400, 1, seed=24)
+    Ag, Bg = emu.colmajor(A), emu.colmajor(B)
+    try:
+        emu.set_param("ir_force_fail", 1)
+        _, inf = emu.dgesv_ir(Ag, Bg, nb=64, nslices=3)
+        assert inf["rc"] == 0 and inf["s_final"] == 5
+        emu.set_param("ir_force_fail", 2)
+        _, inf = emu.dgesv_ir(Ag, Bg, nb=64, nslices=8)
+        assert inf["rc"] == 1004 and inf["s_final"] == 9
+    finally:
+        emu.set_param("ir_force_fail", 0)
+    _, io = O.gesv_ir(A, B, nb=64, s=3, force_fail=1)
+    assert io["s_final"] == 5
+
+
+def test_refinement_singular_reports_info():
+    A = np.array(matgen.uniform(200, 200, seed=25), order="F")
+    A[:, 50] = 0.0
+    B = matgen.uniform(200, 1, seed=26)
+    _, inf = emu.dgesv_ir(emu.colmajor(A), emu.colmajor(B), nb=64, nslices=5)
+    assert inf["info"] == 51 and inf["rc"] == 0

@@ -330,3 +330,28 @@ def test_scaled_residual_matches_eqn9():
            + max(abs(Fraction(float(v))) for v in b[:, 0])) * 30 * Fraction(U)
     assert abs(O.scaled_residual(A, x, b) - float(r / den)) <= 1e-12 * float(r / den)
     assert O.scaled_residual(A, x, b) < 16.0
+
+
+# ------------------------------------------------------- precision form
+
+@pytest.mark.parametrize("s", [3, 4, 5])
+def test_refinement_reaches_tolerance_in_double_double(s):
+    A = matgen.phi_matrix(300, 300, 1.0, seed=17)
+    b = matgen.uniform(300, 2, seed=18)
+    X, inf = O.gesv_ir(A, b, nb=32, s=s, tol=1e-15)
+    assert inf["converged"] and inf["s_final"] == s
+    # judged by the independent double-double residual, not the FP64 one
+    assert O.backward_error(A, X, b) <= 1e-15
+    assert inf["iters"] >= 1
+
+
+def test_refinement_fallback_on_forced_failure_and_give_up():
+    A = matgen.phi_matrix(200, 200, 1.0, seed=19)
+    b = matgen.uniform(200, 1, seed=20)
+    X, inf = O.gesv_ir(A, b, nb=32, s=3, tol=1e-15, force_fail=1)
+    assert inf["converged"] and inf["s_final"] == 5
+    X, inf = O.gesv_ir(A, b, nb=32, s=8, tol=1e-15, force_fail=1)
+    assert inf["converged"] and inf["s_final"] == 9
+    # a failure at the largest slice count gives up
+    X, inf = O.gesv_ir(A, b, nb=32, s=8, tol=1e-15, force_fail=2)
+    assert not inf["converged"] and inf["s_final"] == 9
