@@ -190,14 +190,18 @@ static inline int imax1(int a) { return a > 1 ? a : 1; }
 static thread_local int g_ir_force_fail = 0;
 
 // Scratch of one blocked LU: the largest trailing update's GEMM scratch
-// (the first update; later ones are smaller).
-static size_t getrf_scratch_bytes(int m, int n, int nb, int s) {
+// (the first update; later ones are smaller), then the panel's buffers.
+static size_t getrf_gemm_bytes(int m, int n, int nb, int s) {
     const int mn = m < n ? m : n;
-    if (nb <= 0) nb = 64;
     const int jb0 = nb < mn ? nb : mn;
     if (jb0 <= 0) return 256;
-    return gemm_scratch(m - jb0 > 0 ? m - jb0 : 1, n - jb0 > 0 ? n - jb0 : 1, jb0, s, s + 1)
-        .total;
+    return align256(gemm_scratch(m - jb0 > 0 ? m - jb0 : 1, n - jb0 > 0 ? n - jb0 : 1, jb0,
+                                 s, s + 1).total);
+}
+
+static size_t getrf_scratch_bytes(int m, int n, int nb, int s) {
+    if (nb <= 0) nb = 64;
+    return getrf_gemm_bytes(m, n, nb, s) + panel_scratch_bytes(m);
 }
 
 static size_t getrs_scratch_bytes(int n, int nrhs) {
@@ -208,14 +212,15 @@ static size_t getrs_scratch_bytes(int n, int nrhs) {
 static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, double *A,
                       long long ld, int *ipiv, int *info, int nb, int s) {
     EMU_TRY(launch_fill_int(info, 0, 1, st));
+    char *pws = ws + getrf_gemm_bytes(m, n, nb, s);
     const int mn = m < n ? m : n;
     const int t = s + 1;
     for (int j0 = 0; j0 < mn; j0 += nb) {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
         double *Ajj = A + j0 + (long long)j0 * ld;
-        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, st));
-        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, st));
+        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, st));
+        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, st));
         if (j1 < n) {
             double *U12 = A + j0 + (long long)j1 * ld;
             EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));

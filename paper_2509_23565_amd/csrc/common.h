@@ -109,10 +109,13 @@ bool gemm_supported(int s, int t);
 
 // FP64 LU pieces.
 int launch_fill_int(int *p, int v, int count, hipStream_t stream);
+// Panel factorization (recursive, see panel.hip) of the rows x jb block at
+// A (global row/column row0); ws: panel_scratch_bytes(rows) bytes.
+size_t panel_scratch_bytes(int rows);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
-                 int row0, int *info, hipStream_t stream);
+                 int row0, int *info, char *ws, hipStream_t stream);
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
-                 int ncols_right, const int *ipiv, int k1, int k2,
+                 int ncols_right, const int *ipiv, int k1, int k2, int row0,
                  hipStream_t stream);
 int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
                      long long ldb, int ncols, hipStream_t stream);

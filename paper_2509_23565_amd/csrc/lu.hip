@@ -1,217 +1,128 @@
-// FP64 parts of the blocked LU with partial pivoting and of the solve
-// (paper: section "Dense Numerical Solvers Using FP64 Emulation", eqns
-// (5)-(8): the panel, where the pivots are chosen and U11^-1 reaches A21,
-// stays in FP64 "custom code"; only the Schur update is emulated).
+// Row interchanges and the triangular solves of getrs (paper: eqn (5), the
+// solve that follows the factorization; the panel and the trailing TRSM are
+// in panel.hip).
 //
 // Every FP64 update here is one rounded product followed by one rounded
-// subtraction (this file is compiled with -ffp-contract=off), applied to each
-// element in increasing elimination order, so the factors and solutions are
-// identical bit for bit to a column-by-column right-looking elimination with
-// the same pivots.
+// subtraction (this library is compiled with -ffp-contract=off), applied to
+// each element in increasing elimination order, so the solutions are
+// identical bit for bit to plain column-oriented substitution.
 #include "common.h"
-
-#include <float.h>
 
 namespace emu {
 
-// ---------------------------------------------------------------- panel
-// Pivot order: NaN ranks above every number; otherwise larger magnitude
-// wins; ties go to the smaller row index.
-__device__ __forceinline__ bool better(double va, int ia, double vb, int ib) {
-    bool na = va != va, nb = vb != vb;
-    if (na || nb) {
-        if (na && nb) return ia < ib;
-        return na;
-    }
-    if (va != vb) return va > vb;
-    return ia < ib;
-}
-
-constexpr int PANEL_THREADS = 1024;
-constexpr int PANEL_MAX_NB = 1024;
-
-// One workgroup factors the panel A[0:rows, 0:jb] (global row offset row0)
-// column by column.  Data stay in global memory (the panel is re-read from
-// L2); all waves of the workgroup share one L1, so barriers order them.
-__global__ __launch_bounds__(PANEL_THREADS) void k_panel(double *__restrict__ A,
-                                                         long long lda, int rows,
-                                                         int jb, int *ipiv,
-                                                         int row0, int *info) {
-    __shared__ double prow[PANEL_MAX_NB];
-    __shared__ double red_v[PANEL_THREADS / 64];
-    __shared__ int red_i[PANEL_THREADS / 64];
-    __shared__ int s_p;
-    __shared__ double s_piv;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wid = tid >> 6;
-    const int ncol = rows < jb ? rows : jb;
-
-    for (int c = 0; c < ncol; ++c) {
-        double *colc = A + (long long)c * lda;
-        // 1. pivot search over rows c..rows-1
-        double bv = -1.0;
-        int bi = INT_MAX;
-        for (int i = c + tid; i < rows; i += PANEL_THREADS) {
-            double v = fabs(colc[i]);
-            if (better(v, i, bv, bi)) { bv = v; bi = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            double ov = __shfl_xor(bv, off, 64);
-            int oi = __shfl_xor(bi, off, 64);
-            if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-            for (int q = 1; q < PANEL_THREADS / 64; ++q)
-                if (better(red_v[q], red_i[q], bv, bi)) { bv = red_v[q]; bi = red_i[q]; }
-            double piv = colc[bi];
-            ipiv[c] = row0 + bi + 1;
-            if (piv == 0.0 && *info == 0) *info = row0 + c + 1;
-            s_p = bi;
-            s_piv = piv;
-        }
-        __syncthreads();
-        const int p = s_p;
-        const double piv = s_piv;
-        if (piv != 0.0) {
-            // 2. interchange rows c and p across the panel
-            if (p != c) {
-                for (int j = tid; j < jb; j += PANEL_THREADS) {
-                    double *a = A + (long long)j * lda;
-                    double t0 = a[c];
-                    a[c] = a[p];
-                    a[p] = t0;
-                }
-            }
-            __syncthreads();
-            // 3. scale the column below the pivot
-            if (fabs(piv) >= DBL_MIN) {
-                const double rp = 1.0 / piv;
-                for (int i = c + 1 + tid; i < rows; i += PANEL_THREADS) colc[i] = colc[i] * rp;
-            } else {
-                for (int i = c + 1 + tid; i < rows; i += PANEL_THREADS) colc[i] = colc[i] / piv;
-            }
-        }
-        // 4. rank-1 update of the trailing panel columns
-        for (int j = c + 1 + tid; j < jb; j += PANEL_THREADS) prow[j] = A[c + (long long)j * lda];
-        __syncthreads();
-        for (int i = c + 1 + tid; i < rows; i += PANEL_THREADS) {
-            const double l = colc[i];
-            for (int j = c + 1; j < jb; ++j) {
-                double *a = A + i + (long long)j * lda;
-                *a = *a - l * prow[j];
-            }
-        }
-        __syncthreads();
-    }
-}
-
-int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0,
-                 int *info, hipStream_t stream) {
-    if (jb > PANEL_MAX_NB) {
-        set_error("panel width %d above %d", jb, PANEL_MAX_NB);
-        return EMU_ERR_UNSUPPORTED;
-    }
-    hipLaunchKernelGGL(k_panel, dim3(1), dim3(PANEL_THREADS), 0, stream, A, lda, rows,
-                       jb, ipiv, row0, info);
-    EMU_TRY_HIP(hipGetLastError());
-    return 0;
-}
-
 // ---------------------------------------------------------------- laswp
-// Thread per column: columns [0, ncols_left) and [col_right, col_right +
-// ncols_right); interchanges ipiv[k1..k2) applied in order.
-__global__ void k_laswp(double *__restrict__ A, long long lda, int nrows,
-                        int ncols_left, int col_right, int ncols_right,
-                        const int *__restrict__ ipiv, int k1, int k2) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncols_left + ncols_right) return;
-    int col = t < ncols_left ? t : col_right + (t - ncols_left);
-    double *a = A + (long long)col * lda;
-    for (int c = k1; c < k2; ++c) {
-        int p = ipiv[c] - 1;
-        if (p > c && p < nrows) {
-            double t0 = a[c];
-            a[c] = a[p];
-            a[p] = t0;
+// The interchanges ipiv[k1..k2) (1-based global rows; A's first row is global
+// row row0) are composed into one permutation of the rows they touch (at
+// most 2 (k2 - k1) rows), then applied to columns [0, ncols_left) and
+// [col_right, col_right + ncols_right): every workgroup reads its columns'
+// touched rows into LDS and writes them back permuted, so the sequential
+// chain of swaps costs no memory round trips.
+constexpr int SW_MAX = 1024;          // interchanges per call
+constexpr int SW_TILE = 8192;         // doubles of LDS for the row tile
+
+__global__ __launch_bounds__(256) void k_laswp_perm(double *__restrict__ A, long long lda,
+                                                    int nrows, int ncols_left, int col_right,
+                                                    int ncols_right,
+                                                    const int *__restrict__ ipiv, int k1,
+                                                    int k2, int row0) {
+    __shared__ int pr[SW_MAX];            // target row of interchange c (local)
+    __shared__ int pslot[SW_MAX];         // slot of that row
+    __shared__ int first[SW_MAX];         // 1 if the row first appears here (outside [k1,k2))
+    __shared__ int srow[2 * SW_MAX];      // row of each slot
+    __shared__ int content[2 * SW_MAX];   // source row of each slot after all swaps
+    __shared__ double tile[SW_TILE];
+    __shared__ int s_nslot;
+    const int t = threadIdx.x;
+    const int J = k2 - k1;
+    for (int c = t; c < J; c += blockDim.x) {
+        int pv = ipiv[k1 + c] - 1 - row0;
+        if (pv < k1 + c || pv >= nrows) pv = k1 + c;       // invalid: no interchange
+        pr[c] = pv;
+    }
+    __syncthreads();
+    // first appearance of each target row outside [k1, k2)
+    for (int c = t; c < J; c += blockDim.x) {
+        const int pv = pr[c];
+        int f = (pv >= k2) ? 1 : 0;
+        if (f)
+            for (int c2 = 0; c2 < c; ++c2)
+                if (pr[c2] == pv) {
+                    f = 0;
+                    break;
+                }
+        first[c] = f;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int nx = 0;
+        for (int c = 0; c < J; ++c) {
+            srow[c] = k1 + c;
+            content[c] = k1 + c;
         }
+        for (int c = 0; c < J; ++c) {
+            const int pv = pr[c];
+            if (pv < k2) {
+                pslot[c] = pv - k1;
+            } else if (first[c]) {
+                pslot[c] = J + nx;
+                srow[J + nx] = pv;
+                content[J + nx] = pv;
+                ++nx;
+            } else {
+                for (int c2 = 0; c2 < c; ++c2)
+                    if (pr[c2] == pv) {
+                        pslot[c] = pslot[c2];
+                        break;
+                    }
+            }
+        }
+        for (int c = 0; c < J; ++c) {        // the interchanges, in order
+            const int a = c, b = pslot[c];
+            const int x = content[a];
+            content[a] = content[b];
+            content[b] = x;
+        }
+        s_nslot = J + nx;
+    }
+    __syncthreads();
+    const int nslot = s_nslot;
+    const int CW = max(1, SW_TILE / nslot);                   // columns per pass
+    const int ncols = ncols_left + ncols_right;
+    for (int cb = blockIdx.x * CW; cb < ncols; cb += gridDim.x * CW) {
+        const int cw = min(CW, ncols - cb);
+        for (int e = t; e < nslot * cw; e += blockDim.x) {
+            const int sl = e / cw, jj = e % cw;
+            const int cidx = cb + jj;
+            const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
+            tile[e] = A[content[sl] + (long long)col * lda];
+        }
+        __syncthreads();
+        for (int e = t; e < nslot * cw; e += blockDim.x) {
+            const int sl = e / cw, jj = e % cw;
+            if (content[sl] == srow[sl]) continue;
+            const int cidx = cb + jj;
+            const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
+            A[srow[sl] + (long long)col * lda] = tile[e];
+        }
+        __syncthreads();
     }
 }
 
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
-                 int ncols_right, const int *ipiv, int k1, int k2,
+                 int ncols_right, const int *ipiv, int k1, int k2, int row0,
                  hipStream_t stream) {
-    int total = ncols_left + ncols_right;
+    const int total = ncols_left + ncols_right;
     if (total <= 0 || k2 <= k1) return 0;
-    hipLaunchKernelGGL(k_laswp, dim3((total + 255) / 256), dim3(256), 0, stream, A,
-                       lda, nrows, ncols_left, col_right, ncols_right, ipiv, k1, k2);
-    EMU_TRY_HIP(hipGetLastError());
-    return 0;
-}
-
-// ----------------------------------------------------------------- trsm
-// B (jb x ncols) <- L^-1 B, L unit lower (jb x jb).  Thread per column;
-// for k increasing, b_i = b_i - l_ik b_k (i > k).  NB >= jb: the column
-// lives in registers and L in LDS.
-template <int NB>
-__global__ __launch_bounds__(256) void k_trsm_reg(const double *__restrict__ L,
-                                                  long long ldl, int jb,
-                                                  double *__restrict__ B,
-                                                  long long ldb, int ncols) {
-    __shared__ double Ls[NB * NB];
-    for (int idx = threadIdx.x; idx < jb * jb; idx += blockDim.x) {
-        int i = idx % jb, k = idx / jb;
-        Ls[k * NB + i] = L[i + (long long)k * ldl];
+    if (k2 - k1 > SW_MAX) {
+        set_error("more than %d interchanges in one call", SW_MAX);
+        return EMU_ERR_UNSUPPORTED;
     }
-    __syncthreads();
-    int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncols) return;
-    double *bcol = B + (long long)col * ldb;
-    double b[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) b[i] = i < jb ? bcol[i] : 0.0;
-#pragma unroll
-    for (int k = 0; k < NB - 1; ++k) {
-        if (k < jb - 1) {
-            const double bk = b[k];
-#pragma unroll
-            for (int i = k + 1; i < NB; ++i)
-                if (i < jb) b[i] = b[i] - Ls[k * NB + i] * bk;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        if (i < jb) bcol[i] = b[i];
-}
-
-__global__ __launch_bounds__(256) void k_trsm_gen(const double *__restrict__ L,
-                                                  long long ldl, int jb,
-                                                  double *__restrict__ B,
-                                                  long long ldb, int ncols) {
-    int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncols) return;
-    double *bcol = B + (long long)col * ldb;
-    for (int k = 0; k < jb - 1; ++k) {
-        const double bk = bcol[k];
-        const double *lk = L + (long long)k * ldl;
-        for (int i = k + 1; i < jb; ++i) bcol[i] = bcol[i] - lk[i] * bk;
-    }
-}
-
-int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B, long long ldb,
-                     int ncols, hipStream_t stream) {
-    if (ncols <= 0 || jb <= 1) return 0;
-    dim3 grid((ncols + 255) / 256);
-    if (jb <= 32)
-        hipLaunchKernelGGL(k_trsm_reg<32>, grid, dim3(256), 0, stream, L, ldl, jb, B,
-                           ldb, ncols);
-    else if (jb <= 64)
-        hipLaunchKernelGGL(k_trsm_reg<64>, grid, dim3(256), 0, stream, L, ldl, jb, B,
-                           ldb, ncols);
-    else
-        hipLaunchKernelGGL(k_trsm_gen, grid, dim3(256), 0, stream, L, ldl, jb, B, ldb,
-                           ncols);
+    const int nslot_max = 2 * (k2 - k1);
+    const int cw = nslot_max < SW_TILE ? SW_TILE / nslot_max : 1;
+    int blocks = (total + cw - 1) / cw;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_laswp_perm, dim3(blocks), dim3(256), 0, stream, A, lda, nrows,
+                       ncols_left, col_right, ncols_right, ipiv, k1, k2, row0);
     EMU_TRY_HIP(hipGetLastError());
     return 0;
 }

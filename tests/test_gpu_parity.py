@@ -192,7 +192,9 @@ def test_full_slice_count_normwise_error(phi):
 
 @pytest.mark.parametrize("m,n,nb,s", [(256, 256, 64, 7), (300, 300, 64, 5),
                                       (300, 200, 64, 7), (200, 300, 32, 9),
-                                      (257, 257, 128, 3)])
+                                      (257, 257, 128, 3), (2600, 300, 64, 5),
+                                      (2300, 2300, 128, 4), (4100, 96, 96, 3),
+                                      (700, 700, 200, 6)])
 def test_getrf_bit_exact(m, n, nb, s):
     A = matgen.phi_matrix(m, n, 1.0, seed=13)
     Ag = emu.colmajor(A)
