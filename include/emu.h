@@ -186,6 +186,46 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
                  int *iters, double *berr, int *s_final, int *info);
 
 /*
+ * Batched grouped form (not in the paper; every system is the paper's LU):
+ * `count` independent systems i with n[i] in 1..1024 (host array), A[i]
+ * (host array of DEVICE pointers, lda[i] >= n[i]), ipiv[i] (host array of
+ * DEVICE int32[n[i]]), info (DEVICE int32[count]).  Per block step one
+ * launch per phase covers every active system (panel, interchanges, TRSM,
+ * slicing) and one persistent grouped launch runs all slice-pair GEMMs of
+ * that step's updates; the sequence is captured once per batch shape into a
+ * hipGraph and replayed (descriptors refreshed per call; the call
+ * synchronizes the stream once to upload them).  nb in 1..32 (0: the
+ * autotuned value for this batch shape, else 32); nslices in 1..9.  Each
+ * system's factors and pivots equal emu_dgetrf's with the same nb.
+ * Argument numbers: count=1 n=2 A=3 lda=4 ipiv=5 info=6 nb=7 nslices=8.
+ */
+int emu_dgetrf_batched(int count, const int *n, double *const *A, const int *lda,
+                       int *const *ipiv, int *info, int nb, int nslices);
+
+/*
+ * emu_dgesv_batched: emu_dgetrf_batched followed by the solve of each
+ * system with its nrhs[i] in 1..8 right-hand sides B[i] (host array of
+ * DEVICE pointers, ldb[i] >= n[i]), overwritten with the solutions; same
+ * solve order as emu_dgetrs.  Argument numbers: count=1 n=2 nrhs=3 A=4
+ * lda=5 ipiv=6 info=7 B/ldb=8 nb=9 nslices=10.
+ */
+int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A,
+                      const int *lda, int *const *ipiv, int *info, double *const *B,
+                      const int *ldb, int nb, int nslices);
+
+/*
+ * emu_autotune_batched: time the batched solve of this batch on private
+ * copies (inputs untouched) for block sizes {16, 32} and grouped-GEMM grid
+ * sizes {1, 2} x (CUs x resident workgroups), record the fastest for the
+ * batch shape (count, largest n, nslices) — used when nb = 0 — and return
+ * it (host outputs).  With EMU_AUTOTUNE_CACHE set the table is read from
+ * and written to that file.  Allocates and frees device memory.
+ */
+int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const *A,
+                         const int *lda, double *const *B, const int *ldb, int nslices,
+                         int *best_nb, int *best_mult, double *best_ms);
+
+/*
  * emu_debug_slices: expose the exponent scan and digit slicing of one
  * operand, for bit-exact checks.  X is rows x cols column-major (ldx).
  * by_rows = 1 scales per row (the A side), 0 per column (the B side).

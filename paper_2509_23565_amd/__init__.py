@@ -26,6 +26,8 @@ __all__ = [
     "emu_debug_slices", "emu_debug_products", "emu_profile_start",
     "emu_profile_stop", "emu_profile_read", "profile_read", "PROF_SLICE", "PROF_GEMM",
     "emu_set_param", "emu_dgesv_ir", "set_param", "dgesv_ir",
+    "emu_dgetrf_batched", "emu_dgesv_batched", "emu_autotune_batched",
+    "dgetrf_batched", "dgesv_batched", "autotune_batched",
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status",
 ]
@@ -61,6 +63,10 @@ _SIGNATURES = {
     "emu_dgesv_ir": ([_I, _I, _P, _I, _P, _I, _P, _I, _I, _I, _D, _I,
                       ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_I),
                       ctypes.POINTER(_I)], _I),
+    "emu_dgetrf_batched": ([_I, _P, _P, _P, _P, _P, _I, _I], _I),
+    "emu_dgesv_batched": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I], _I),
+    "emu_autotune_batched": ([_I, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_I),
+                              ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "emu_profile_start": ([], _I),
     "emu_profile_stop": ([], _I),
     "emu_profile_read": ([_I, ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
@@ -106,6 +112,9 @@ emu_debug_slices = _raw("emu_debug_slices")
 emu_debug_products = _raw("emu_debug_products")
 emu_set_param = _raw("emu_set_param")
 emu_dgesv_ir = _raw("emu_dgesv_ir")
+emu_dgetrf_batched = _raw("emu_dgetrf_batched")
+emu_dgesv_batched = _raw("emu_dgesv_batched")
+emu_autotune_batched = _raw("emu_autotune_batched")
 emu_profile_start = _raw("emu_profile_start")
 emu_profile_stop = _raw("emu_profile_stop")
 emu_profile_read = _raw("emu_profile_read")
@@ -245,6 +254,72 @@ def dgesv_ir(A, B, X=None, nb=64, nslices=3, tol=1e-15, maxiter=10):
     if rc not in (0, 1004):
         _check(rc, "emu_dgesv_ir")
     return X, dict(iters=it.value, berr=be.value, s_final=sf.value, info=inf.value, rc=rc)
+
+
+class _Batch:
+    """Host arrays (sizes, device pointers) of a list of column-major tensors."""
+
+    def __init__(self, mats, name):
+        n = len(mats)
+        self.ptr = (ctypes.c_void_p * n)()
+        self.ld = (ctypes.c_int * n)()
+        for i, t in enumerate(mats):
+            p, ld = _mat(t, f"{name}[{i}]")
+            self.ptr[i] = p
+            self.ld[i] = ld
+
+
+def dgesv_batched(As, Bs, nb=32, nslices=5):
+    """Factor and solve a batch in place (A_i -> LU_i, B_i -> X_i).
+
+    Returns (ipivs, info) with info an int32 device tensor of length count.
+    nb = 0 uses the autotuned block size for this batch shape.
+    """
+    torch = _torch()
+    count = len(As)
+    dev = As[0].device
+    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
+    nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
+    ipivs = [torch.zeros(int(a.shape[0]), dtype=torch.int32, device=dev) for a in As]
+    pp = (ctypes.c_void_p * count)(*[p.data_ptr() for p in ipivs])
+    info = torch.zeros(count, dtype=torch.int32, device=dev)
+    a = _Batch(As, "A")
+    b = _Batch(Bs, "B")
+    _bind_stream()
+    _check(emu_dgesv_batched(count, n, nrhs, a.ptr, a.ld, pp, info.data_ptr(), b.ptr, b.ld,
+                             int(nb), int(nslices)), "emu_dgesv_batched")
+    return ipivs, info
+
+
+def dgetrf_batched(As, nb=32, nslices=5):
+    """Factor a batch in place; returns (ipivs, info)."""
+    torch = _torch()
+    count = len(As)
+    dev = As[0].device
+    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
+    ipivs = [torch.zeros(int(a.shape[0]), dtype=torch.int32, device=dev) for a in As]
+    pp = (ctypes.c_void_p * count)(*[p.data_ptr() for p in ipivs])
+    info = torch.zeros(count, dtype=torch.int32, device=dev)
+    a = _Batch(As, "A")
+    _bind_stream()
+    _check(emu_dgetrf_batched(count, n, a.ptr, a.ld, pp, info.data_ptr(), int(nb),
+                              int(nslices)), "emu_dgetrf_batched")
+    return ipivs, info
+
+
+def autotune_batched(As, Bs, nslices=5):
+    """Tune (nb, grid multiplier) for this batch shape; returns (nb, mult, ms)."""
+    count = len(As)
+    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
+    nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
+    a = _Batch(As, "A")
+    b = _Batch(Bs, "B")
+    bnb, bm, bms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    _bind_stream()
+    _check(emu_autotune_batched(count, n, nrhs, a.ptr, a.ld, b.ptr, b.ld, int(nslices),
+                                ctypes.byref(bnb), ctypes.byref(bm), ctypes.byref(bms)),
+           "emu_autotune_batched")
+    return bnb.value, bm.value, bms.value
 
 
 def debug_slices(X, by_rows, nslices):

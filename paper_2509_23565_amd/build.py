@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libemu.so")
 ARCH = "gfx950"
-SOURCES = ["api.hip", "slice.hip", "slicegemm.hip", "lu.hip", "panel.hip", "refine.hip"]
+SOURCES = ["api.hip", "slice.hip", "slicegemm.hip", "lu.hip", "panel.hip", "refine.hip",
+           "batched.hip"]
 
 
 def _hipcc() -> str:

@@ -1,0 +1,755 @@
+// Batched grouped form: many independent LU systems of uneven size solved
+// together (this form is not in the paper; each system is the paper's LU with
+// the emulated Schur update of eqn (8)).
+//
+// Systems are sorted by size, so the systems still active at block step j
+// (n_i > j nb) are a prefix of the list.  Each step issues one launch per
+// phase for all active systems: panel (one workgroup per system, the panel in
+// registers), interchanges, triangular solve, slicing of every L21 and U12
+// (one pass each: K = nb <= 32 is a single fragment block), and one
+// persistent grouped slice-product GEMM over the concatenated tile lists of
+// all systems.  The whole sequence (and the solves) is captured once per
+// batch shape into a hipGraph and replayed; per call only the descriptor
+// tables are refreshed.  Every FP64 step follows the single-system order, so
+// each system's factors are bit-identical to emu_dgetrf with the same nb.
+//
+// An autotuner times the candidate block sizes and grouped-GEMM grid sizes
+// on a copy of a batch and records the fastest per batch shape.
+#include "common.h"
+#include "devutil.h"
+
+#include <float.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace emu {
+
+constexpr int BMAX_N = 1024;       // grouped path: systems up to this size
+constexpr int BMAX_NB = 32;        // panel width held in registers
+constexpr int BMAX_RHS = 8;
+
+struct BSys {
+    double *A;
+    long long lda;
+    int n;
+    int nrhs;
+    int *ipiv;
+    int *info;
+    double *B;
+    long long ldb;
+};
+
+// ------------------------------------------------------------------ panel
+// One workgroup per active system: column-by-column over the rows x jb
+// panel at (j0, j0), one row per thread, the row's jb <= 32 values in
+// registers (same operations and order as the single-system panel).
+__global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, int j0, int nb) {
+    __shared__ double urow[BMAX_NB], xrow[BMAX_NB];
+    __shared__ double red_v[16 + 1];
+    __shared__ int red_i[16 + 1];
+    const BSys S = sys[blockIdx.x];
+    const int rows = S.n - j0;
+    if (rows <= 0) return;
+    const int w = nb < rows ? nb : rows;
+    double *P = S.A + j0 + (long long)j0 * S.lda;
+    const int t = threadIdx.x;
+    double v[BMAX_NB];
+#pragma unroll
+    for (int j = 0; j < BMAX_NB; ++j)
+        v[j] = (t < rows && j < w) ? P[t + (long long)j * S.lda] : 0.0;
+#pragma unroll 1
+    for (int c = 0; c < w; ++c) {
+        double vc = 0.0;
+#pragma unroll
+        for (int j = 0; j < BMAX_NB; ++j)
+            if (j == c) vc = v[j];
+        double bv = -1.0;
+        int bi = INT_MAX;
+        if (t >= c && t < rows) {
+            bv = fabs(vc);
+            bi = t;
+        }
+        block_best<16>(bv, bi, red_v, red_i);
+        const int p = bi;
+        if (t == p)
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) urow[j] = v[j];
+        if (t == c)
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) xrow[j] = v[j];
+        __syncthreads();
+        const double piv = urow[c];
+        if (t == 0) {
+            S.ipiv[j0 + c] = j0 + p + 1;
+            if (piv == 0.0 && *S.info == 0) *S.info = j0 + c + 1;
+        }
+        const bool swap = piv != 0.0 && p != c;
+        const double *ur = (piv != 0.0) ? urow : xrow;
+        if (swap && t == c) {
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) v[j] = urow[j];
+        } else if (swap && t == p) {
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) v[j] = xrow[j];
+        }
+        if (t > c && t < rows) {
+            double l = 0.0;
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j)
+                if (j == c) l = v[j];
+            if (piv != 0.0) l = (fabs(piv) >= DBL_MIN) ? l * (1.0 / piv) : l / piv;
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) {
+                if (j == c) v[j] = l;
+                if (j > c) v[j] = v[j] - l * ur[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (t < rows)
+#pragma unroll
+        for (int j = 0; j < BMAX_NB; ++j)
+            if (j < w) P[t + (long long)j * S.lda] = v[j];
+}
+
+// Interchanges of step j0 on the columns outside the panel: thread per
+// column, the jb <= 32 swaps in order.
+__global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, int j0, int nb) {
+    const BSys S = sys[blockIdx.y];
+    const int rows = S.n - j0;
+    if (rows <= 0) return;
+    const int w = nb < rows ? nb : rows;
+    const int ncols = S.n - w;                       // [0, j0) and [j0 + w, n)
+    const int tcol = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tcol >= ncols) return;
+    const int col = tcol < j0 ? tcol : tcol + w;
+    double *a = S.A + (long long)col * S.lda;
+    for (int c = j0; c < j0 + w; ++c) {
+        const int p = S.ipiv[c] - 1;
+        if (p > c && p < S.n) {
+            const double t0 = a[c];
+            a[c] = a[p];
+            a[p] = t0;
+        }
+    }
+}
+
+// U12 = L11^-1 A12 for every active system: thread per column, the column
+// in registers, L11 (jb <= 32) in LDS.
+__global__ __launch_bounds__(256) void k_btrsm(const BSys *__restrict__ sys, int j0, int nb) {
+    __shared__ double Ls[BMAX_NB * BMAX_NB];
+    const BSys S = sys[blockIdx.y];
+    const int rows = S.n - j0;
+    if (rows <= 0) return;
+    const int w = nb < rows ? nb : rows;
+    const int ncols = S.n - j0 - w;
+    if (ncols <= 0 || (int)(blockIdx.x * blockDim.x) >= ncols) return;
+    const double *L = S.A + j0 + (long long)j0 * S.lda;
+    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+        const int i = idx % w, k = idx / w;
+        Ls[k * BMAX_NB + i] = L[i + (long long)k * S.lda];
+    }
+    __syncthreads();
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncols) return;
+    double *bcol = S.A + j0 + (long long)(j0 + w + col) * S.lda;
+    double b[BMAX_NB];
+#pragma unroll
+    for (int i = 0; i < BMAX_NB; ++i) b[i] = i < w ? bcol[i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < BMAX_NB - 1; ++k) {
+        if (k < w - 1) {
+            const double bk = b[k];
+#pragma unroll
+            for (int i = k + 1; i < BMAX_NB; ++i)
+                if (i < w) b[i] = b[i] - Ls[k * BMAX_NB + i] * bk;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BMAX_NB; ++i)
+        if (i < w) bcol[i] = b[i];
+}
+
+// ------------------------------------------------------------------ solve
+// One workgroup per system: interchanges (one thread per right-hand side),
+// then forward and back substitution in 64-row blocks (a wave resolves the
+// diagonal block with shuffles, all threads update the other rows), in the
+// same per-element order as the single-system solve.  B lives in LDS.
+__global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
+    __shared__ double X[BMAX_N * BMAX_RHS];
+    const BSys S = sys[blockIdx.x];
+    const int n = S.n, nr = S.nrhs;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    for (int e = t; e < n * nr; e += blockDim.x) {
+        const int i = e % n, r = e / n;
+        X[r * BMAX_N + i] = S.B[i + (long long)r * S.ldb];
+    }
+    __syncthreads();
+    if (t < nr) {
+        double *x = X + t * BMAX_N;
+        for (int c = 0; c < n; ++c) {
+            const int p = S.ipiv[c] - 1;
+            if (p > c && p < n) {
+                const double q = x[c];
+                x[c] = x[p];
+                x[p] = q;
+            }
+        }
+    }
+    __syncthreads();
+    const double *LU = S.A;
+    const long long lda = S.lda;
+    for (int k0 = 0; k0 < n; k0 += 64) {
+        const int kb = n - k0 < 64 ? n - k0 : 64;
+        if (wid < nr) {                               // diagonal block, wave per rhs
+            double *x = X + wid * BMAX_N;
+            const int i = k0 + lane;
+            double b = lane < kb ? x[i] : 0.0;
+            for (int k = 0; k < kb - 1; ++k) {
+                const double xk = __shfl(b, k, 64);
+                if (lane > k && lane < kb) b = b - LU[i + (long long)(k0 + k) * lda] * xk;
+            }
+            if (lane < kb) x[i] = b;
+        }
+        __syncthreads();
+        for (int e = t; e < (n - k0 - kb) * nr; e += blockDim.x) {
+            const int i = k0 + kb + e % (n - k0 - kb), r = e / (n - k0 - kb);
+            double *x = X + r * BMAX_N;
+            double b = x[i];
+            for (int k = 0; k < kb; ++k) b = b - LU[i + (long long)(k0 + k) * lda] * x[k0 + k];
+            x[i] = b;
+        }
+        __syncthreads();
+    }
+    const int last0 = (n - 1) / 64 * 64;
+    for (int k0 = last0; k0 >= 0; k0 -= 64) {
+        const int kb = n - k0 < 64 ? n - k0 : 64;
+        if (wid < nr) {
+            double *x = X + wid * BMAX_N;
+            const int i = k0 + lane;
+            double b = lane < kb ? x[i] : 0.0;
+            for (int k = kb - 1; k >= 0; --k) {
+                if (lane == k) b = b / LU[i + (long long)i * lda];
+                const double xk = __shfl(b, k, 64);
+                if (lane < k) b = b - LU[i + (long long)(k0 + k) * lda] * xk;
+            }
+            if (lane < kb) x[i] = b;
+        }
+        __syncthreads();
+        for (int e = t; e < k0 * nr; e += blockDim.x) {
+            const int i = e % k0, r = e / k0;
+            double *x = X + r * BMAX_N;
+            double b = x[i];
+            for (int k = kb - 1; k >= 0; --k) b = b - LU[i + (long long)(k0 + k) * lda] * x[k0 + k];
+            x[i] = b;
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < n * nr; e += blockDim.x) {
+        const int i = e % n, r = e / n;
+        S.B[i + (long long)r * S.ldb] = X[r * BMAX_N + i];
+    }
+}
+
+__global__ void k_binfo_clear(const BSys *__restrict__ sys, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) *sys[i].info = 0;
+}
+
+// ------------------------------------------------------------------ plans
+struct BatchPlan {
+    int count = 0, nb = 0, s = 0, steps = 0, grid_mult = 1, nmax = 0;
+    bool solve = false;
+    std::vector<int> order;            // system index of sorted slot q
+    std::vector<int> nact;             // active systems per step
+    std::vector<int> g_off, g_cnt, g_tiles, j_off, j_cnt, j_waves;
+    std::vector<GemmArgs> gemm;        // all steps
+    std::vector<int> gprefix;          // per step: g_cnt + 1 entries, concatenated
+    std::vector<int> gp_off;
+    std::vector<SliceJob> jobs;
+    std::vector<int> jprefix;
+    std::vector<int> jp_off;
+    std::vector<BSys> sys;             // sorted
+    // scratch offsets
+    size_t o_sys = 0, o_gemm = 0, o_gpre = 0, o_jobs = 0, o_jpre = 0, o_planes = 0, total = 0;
+    std::vector<size_t> sys_planes;    // per sorted slot: offset of its plane region
+};
+
+static size_t region_bytes(int n, int nb, int s) {
+    const int k = nb < n ? nb : n;
+    const int lines = n - k > 0 ? n - k : 1;
+    const Planes g = plane_geom(lines, k);
+    return 2 * (align256((size_t)g.LB * 32 * sizeof(int)) + align256((size_t)s * g.plane_bytes));
+}
+
+// Shapes only: offsets, counts and scratch size.
+static void plan_shape(BatchPlan &pl, int count, const int *n, const int *nrhs, int nb, int s,
+                       bool solve) {
+    pl.count = count;
+    pl.nb = nb;
+    pl.s = s;
+    pl.solve = solve;
+    pl.order.resize(count);
+    std::iota(pl.order.begin(), pl.order.end(), 0);
+    std::stable_sort(pl.order.begin(), pl.order.end(),
+                     [&](int a, int b) { return n[a] > n[b]; });
+    pl.nmax = count ? n[pl.order[0]] : 0;
+    pl.steps = (pl.nmax + nb - 1) / nb;
+    (void)nrhs;
+    size_t off = 0;
+    pl.o_sys = off;
+    off += align256((size_t)count * sizeof(BSys));
+    // count problems/jobs per step
+    pl.nact.assign(pl.steps, 0);
+    pl.g_off.assign(pl.steps, 0);
+    pl.g_cnt.assign(pl.steps, 0);
+    pl.g_tiles.assign(pl.steps, 0);
+    pl.j_off.assign(pl.steps, 0);
+    pl.j_cnt.assign(pl.steps, 0);
+    pl.j_waves.assign(pl.steps, 0);
+    pl.gp_off.assign(pl.steps, 0);
+    pl.jp_off.assign(pl.steps, 0);
+    int gsum = 0, jsum = 0, gps = 0, jps = 0;
+    for (int st = 0; st < pl.steps; ++st) {
+        const int j0 = st * nb;
+        int act = 0, gc = 0;
+        for (int q = 0; q < count; ++q) {
+            const int ni = n[pl.order[q]];
+            if (ni <= j0) break;
+            ++act;
+            const int jb = nb < ni - j0 ? nb : ni - j0;
+            if (j0 + jb < ni) ++gc;
+        }
+        pl.nact[st] = act;
+        pl.g_off[st] = gsum;
+        pl.g_cnt[st] = gc;
+        pl.j_off[st] = jsum;
+        pl.j_cnt[st] = 2 * gc;
+        pl.gp_off[st] = gps;
+        pl.jp_off[st] = jps;
+        gsum += gc;
+        jsum += 2 * gc;
+        gps += gc + 1;
+        jps += 2 * gc + 1;
+    }
+    pl.o_gemm = off;
+    off += align256((size_t)gsum * sizeof(GemmArgs));
+    pl.o_gpre = off;
+    off += align256((size_t)gps * sizeof(int));
+    pl.o_jobs = off;
+    off += align256((size_t)jsum * sizeof(SliceJob));
+    pl.o_jpre = off;
+    off += align256((size_t)jps * sizeof(int));
+    pl.o_planes = off;
+    pl.sys_planes.assign(count, 0);
+    for (int q = 0; q < count; ++q) {
+        pl.sys_planes[q] = off;
+        off += region_bytes(n[pl.order[q]], nb, s);
+    }
+    pl.total = off;
+}
+
+// Descriptor contents for the given matrices and scratch base.
+static void plan_fill(BatchPlan &pl, const int *n, const int *nrhs, double *const *A,
+                      const int *lda, int *const *ipiv, int *info, double *const *B,
+                      const int *ldb, char *base) {
+    const int count = pl.count, nb = pl.nb, s = pl.s;
+    pl.sys.resize(count);
+    for (int q = 0; q < count; ++q) {
+        const int i = pl.order[q];
+        BSys &S = pl.sys[q];
+        S.A = A[i];
+        S.lda = lda[i];
+        S.n = n[i];
+        S.nrhs = nrhs ? nrhs[i] : 0;
+        S.ipiv = ipiv[i];
+        S.info = info + i;
+        S.B = B ? B[i] : nullptr;
+        S.ldb = ldb ? ldb[i] : 1;
+    }
+    pl.gemm.clear();
+    pl.jobs.clear();
+    pl.gprefix.clear();
+    pl.jprefix.clear();
+    for (int st = 0; st < pl.steps; ++st) {
+        const int j0 = st * nb;
+        int tiles = 0, waves = 0;
+        pl.gprefix.push_back(0);
+        pl.jprefix.push_back(0);
+        for (int q = 0; q < pl.nact[st]; ++q) {
+            const BSys &S = pl.sys[q];
+            const int jb = nb < S.n - j0 ? nb : S.n - j0;
+            const int j1 = j0 + jb;
+            if (j1 >= S.n) continue;
+            const int lines = S.n - j1;
+            const Planes g = plane_geom(lines, jb);
+            char *reg = base + pl.sys_planes[q];
+            const size_t half = region_bytes(S.n, nb, s) / 2;
+            int *codeA = reinterpret_cast<int *>(reg);
+            int8_t *pa = reinterpret_cast<int8_t *>(reg + align256((size_t)g.LB * 32 * sizeof(int)));
+            int *codeB = reinterpret_cast<int *>(reg + half);
+            int8_t *pb = reinterpret_cast<int8_t *>(reg + half +
+                                                    align256((size_t)g.LB * 32 * sizeof(int)));
+            SliceJob ja{S.A + j1 + (long long)j0 * S.lda, S.lda, lines, jb, 1, g.LB, codeA, pa,
+                        g.plane_bytes};
+            SliceJob jbj{S.A + j0 + (long long)j1 * S.lda, S.lda, lines, jb, 0, g.LB, codeB, pb,
+                         g.plane_bytes};
+            pl.jobs.push_back(ja);
+            waves += g.LB;
+            pl.jprefix.push_back(waves);
+            pl.jobs.push_back(jbj);
+            waves += g.LB;
+            pl.jprefix.push_back(waves);
+            GemmArgs ga{};
+            ga.Ap = pa;
+            ga.Bp = pb;
+            ga.a_plane = g.plane_bytes;
+            ga.b_plane = g.plane_bytes;
+            ga.codeA = codeA;
+            ga.codeB = codeB;
+            ga.M = lines;
+            ga.N = lines;
+            ga.KB = g.KB;
+            ga.alpha = -1.0;
+            ga.beta = 1.0;
+            ga.C = S.A + j1 + (long long)j1 * S.lda;
+            ga.ldc = S.lda;
+            gemm_tile_counts(s, lines, lines, &ga.tiles_m, &ga.tiles_n);
+            pl.gemm.push_back(ga);
+            tiles += ga.tiles_m * ga.tiles_n;
+            pl.gprefix.push_back(tiles);
+        }
+        pl.g_tiles[st] = tiles;
+        pl.j_waves[st] = waves;
+    }
+}
+
+static int plan_upload(const BatchPlan &pl, char *base, hipStream_t st) {
+    EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_sys, pl.sys.data(), pl.sys.size() * sizeof(BSys),
+                               hipMemcpyHostToDevice, st));
+    if (!pl.gemm.empty()) {
+        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_gemm, pl.gemm.data(),
+                                   pl.gemm.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
+        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_gpre, pl.gprefix.data(),
+                                   pl.gprefix.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_jobs, pl.jobs.data(),
+                                   pl.jobs.size() * sizeof(SliceJob), hipMemcpyHostToDevice, st));
+        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_jpre, pl.jprefix.data(),
+                                   pl.jprefix.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    // the host vectors are refilled on the next call: wait for the copies
+    EMU_TRY_HIP(hipStreamSynchronize(st));
+    return 0;
+}
+
+static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hipStream_t st) {
+    const BSys *sys = reinterpret_cast<const BSys *>(base + pl.o_sys);
+    hipLaunchKernelGGL(k_binfo_clear, dim3((pl.count + 255) / 256), dim3(256), 0, st, sys,
+                       pl.count);
+    const int ggrid = cus * gemm_grouped_blocks_per_cu(pl.s) * pl.grid_mult;
+    for (int stp = 0; stp < pl.steps; ++stp) {
+        const int j0 = stp * pl.nb;
+        const int act = pl.nact[stp];
+        hipLaunchKernelGGL(k_bpanel, dim3(act), dim3(1024), 0, st, sys, j0, pl.nb);
+        const int cblocks = (pl.nmax + 255) / 256;
+        hipLaunchKernelGGL(k_blaswp, dim3(cblocks, act), dim3(256), 0, st, sys, j0, pl.nb);
+        hipLaunchKernelGGL(k_btrsm, dim3(cblocks, act), dim3(256), 0, st, sys, j0, pl.nb);
+        EMU_TRY_HIP(hipGetLastError());
+        if (pl.g_cnt[stp] > 0) {
+            const SliceJob *jobs = reinterpret_cast<const SliceJob *>(base + pl.o_jobs) +
+                                   pl.j_off[stp];
+            const int *jpre = reinterpret_cast<const int *>(base + pl.o_jpre) + pl.jp_off[stp];
+            EMU_TRY(launch_slice_small_grouped(jobs, jpre, pl.j_cnt[stp], pl.j_waves[stp], pl.s,
+                                               status, st));
+            const GemmArgs *probs = reinterpret_cast<const GemmArgs *>(base + pl.o_gemm) +
+                                    pl.g_off[stp];
+            const int *gpre = reinterpret_cast<const int *>(base + pl.o_gpre) + pl.gp_off[stp];
+            EMU_TRY(launch_slicegemm_grouped(probs, gpre, pl.g_cnt[stp], pl.g_tiles[stp], ggrid,
+                                             pl.s, st));
+        }
+    }
+    if (pl.solve) {
+        hipLaunchKernelGGL(k_bgetrs, dim3(pl.count), dim3(1024), 0, st, sys);
+        EMU_TRY_HIP(hipGetLastError());
+    }
+    return 0;
+}
+
+// ------------------------------------------------------ graph cache, tuning
+struct GraphEntry {
+    BatchPlan plan;
+    hipGraphExec_t exec = nullptr;
+    void *ws = nullptr;
+};
+static std::mutex g_bmu;
+static std::map<std::string, GraphEntry> g_graphs;
+static std::map<std::string, std::pair<int, int>> g_tuned;   // shape -> (nb, grid_mult)
+static bool g_tuned_loaded = false;
+
+static std::string shape_key(int count, const int *n, const int *nrhs, int nb, int s,
+                             bool solve, int mult) {
+    std::string k = std::to_string(count) + ":" + std::to_string(nb) + ":" + std::to_string(s) +
+                    ":" + (solve ? "1" : "0") + ":" + std::to_string(mult) + ":";
+    unsigned long long h = 1469598103934665603ull;
+    for (int i = 0; i < count; ++i) {
+        h = (h ^ (unsigned long long)n[i]) * 1099511628211ull;
+        h = (h ^ (unsigned long long)(nrhs ? nrhs[i] : 0)) * 1099511628211ull;
+    }
+    return k + std::to_string(h);
+}
+
+// Tuning key: the batch's coarse shape (count, largest n, slice count).
+static std::string tune_key(int count, int nmax, int s) {
+    return std::to_string(count) + "/" + std::to_string(nmax) + "/" + std::to_string(s);
+}
+
+static const char *tune_file() { return std::getenv("EMU_AUTOTUNE_CACHE"); }
+
+static void tune_load() {
+    if (g_tuned_loaded) return;
+    g_tuned_loaded = true;
+    const char *f = tune_file();
+    if (!f) return;
+    FILE *fp = std::fopen(f, "r");
+    if (!fp) return;
+    // one entry per line: "key nb grid_mult"
+    char key[256];
+    int nb, mult;
+    while (std::fscanf(fp, "%255s %d %d", key, &nb, &mult) == 3) g_tuned[key] = {nb, mult};
+    std::fclose(fp);
+}
+
+static void tune_save() {
+    const char *f = tune_file();
+    if (!f) return;
+    FILE *fp = std::fopen(f, "w");
+    if (!fp) return;
+    for (auto &kv : g_tuned) std::fprintf(fp, "%s %d %d\n", kv.first.c_str(), kv.second.first,
+                                          kv.second.second);
+    std::fclose(fp);
+}
+
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
+static int check_batch(int count, const int *n, const int *nrhs, double *const *A, const int *lda,
+                       int *const *ipiv, int *info, double *const *B, const int *ldb, int nb,
+                       int nslices, bool solve) {
+    if (count < 0) return -1;
+    if (count > 0 && !n) return -2;
+    if (solve && count > 0 && !nrhs) return -3;
+    if (count > 0 && !A) return -4;
+    if (count > 0 && !lda) return -5;
+    if (count > 0 && !ipiv) return -6;
+    if (count > 0 && !info) return -7;
+    if (solve && count > 0 && (!B || !ldb)) return -8;
+    if (nb < 0 || nb > BMAX_NB) return -9;
+    if (nslices < 1 || nslices > EMU_MAX_SLICES) return -10;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 1 || n[i] > BMAX_N) {
+            set_error("batched: system %d has n = %d (supported 1..%d)", i, n[i], BMAX_N);
+            return EMU_ERR_UNSUPPORTED;
+        }
+        if (!A[i] || lda[i] < n[i] || !ipiv[i]) return -4;
+        if (solve) {
+            if (nrhs[i] < 1 || nrhs[i] > BMAX_RHS) {
+                set_error("batched: system %d has %d right-hand sides (1..%d)", i, nrhs[i],
+                          BMAX_RHS);
+                return EMU_ERR_UNSUPPORTED;
+            }
+            if (!B[i] || ldb[i] < n[i]) return -8;
+        }
+    }
+    return 0;
+}
+
+// Factor (and solve) a batch through the cached graph of its shape.
+static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
+                     const int *lda, int *const *ipiv, int *info, double *const *B,
+                     const int *ldb, int nb, int nslices, int mult, bool solve) {
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    std::lock_guard<std::mutex> lk(g_bmu);
+    const std::string key = shape_key(count, n, nrhs, nb, nslices, solve, mult);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end() || it->second.ws != dev->ws) {
+        if (it != g_graphs.end()) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            g_graphs.erase(it);
+        }
+        GraphEntry e;
+        plan_shape(e.plan, count, n, nrhs, nb, nslices, solve);
+        e.plan.grid_mult = mult;
+        const void *before = dev->ws;
+        EMU_TRY(reserve(dev, st, e.plan.total));
+        if (dev->ws != before) {                 // scratch moved: every graph is stale
+            for (auto &kv : g_graphs)
+                if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            g_graphs.clear();
+        }
+        char *base = static_cast<char *>(dev->ws);
+        plan_fill(e.plan, n, nrhs, A, lda, ipiv, info, B, ldb, base);
+        EMU_TRY(plan_upload(e.plan, base, st));
+        hipStream_t cap;
+        EMU_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        EMU_TRY_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        int rc = plan_launch(e.plan, base, dev->status, device_cus(), cap);
+        hipGraph_t graph = nullptr;
+        hipError_t ec = hipStreamEndCapture(cap, &graph);
+        (void)hipStreamDestroy(cap);
+        if (rc != 0) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail_hip(ec, "hipStreamEndCapture");
+        ec = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ec != hipSuccess) return fail_hip(ec, "hipGraphInstantiate");
+        e.ws = dev->ws;
+        it = g_graphs.emplace(key, std::move(e)).first;
+    } else {
+        plan_fill(it->second.plan, n, nrhs, A, lda, ipiv, info, B, ldb,
+                  static_cast<char *>(dev->ws));
+        EMU_TRY(plan_upload(it->second.plan, static_cast<char *>(dev->ws), st));
+    }
+    EMU_TRY_HIP(hipGraphLaunch(it->second.exec, st));
+    return 0;
+}
+
+}  // namespace emu
+
+using namespace emu;
+
+extern "C" {
+
+int emu_dgetrf_batched(int count, const int *n, double *const *A, const int *lda,
+                       int *const *ipiv, int *info, int nb, int nslices) {
+    int bad = check_batch(count, n, nullptr, A, lda, ipiv, info, nullptr, nullptr, nb, nslices,
+                          false);
+    if (bad) return bad;
+    if (count == 0) return 0;
+    int mult = 1;
+    if (nb == 0) {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        tune_load();
+        int nmax = *std::max_element(n, n + count);
+        auto t = g_tuned.find(tune_key(count, nmax, nslices));
+        nb = t != g_tuned.end() ? t->second.first : BMAX_NB;
+        mult = t != g_tuned.end() ? t->second.second : 1;
+    }
+    return run_batch(count, n, nullptr, A, lda, ipiv, info, nullptr, nullptr, nb, nslices, mult,
+                     false);
+}
+
+int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A,
+                      const int *lda, int *const *ipiv, int *info, double *const *B,
+                      const int *ldb, int nb, int nslices) {
+    int bad = check_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, true);
+    if (bad) return bad;
+    if (count == 0) return 0;
+    int mult = 1;
+    if (nb == 0) {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        tune_load();
+        int nmax = *std::max_element(n, n + count);
+        auto t = g_tuned.find(tune_key(count, nmax, nslices));
+        nb = t != g_tuned.end() ? t->second.first : BMAX_NB;
+        mult = t != g_tuned.end() ? t->second.second : 1;
+    }
+    return run_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, mult, true);
+}
+
+int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const *A,
+                         const int *lda, double *const *B, const int *ldb, int nslices,
+                         int *best_nb, int *best_mult, double *best_ms) {
+    if (count <= 0) return -1;
+    if (!best_nb || !best_mult || !best_ms) return -9;
+    std::vector<int *> piv(count, nullptr);
+    // private copies: the tuning runs factor in place
+    std::vector<double *> Ac(count, nullptr), Bc(count, nullptr);
+    std::vector<int> ldc(count), ldbc(count);
+    int *dinfo = nullptr;
+    int rc = 0;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    EMU_TRY_HIP(hipMalloc(&dinfo, count * sizeof(int)));
+    for (int i = 0; i < count && rc == 0; ++i) {
+        ldc[i] = n[i];
+        ldbc[i] = n[i];
+        if (hipMalloc(&Ac[i], (size_t)n[i] * n[i] * sizeof(double)) != hipSuccess ||
+            hipMalloc(&Bc[i], (size_t)n[i] * nrhs[i] * sizeof(double)) != hipSuccess ||
+            hipMalloc(&piv[i], n[i] * sizeof(int)) != hipSuccess)
+            rc = EMU_ERR_WORKSPACE;
+    }
+    const int nbs[2] = {16, 32};
+    const int mults[2] = {1, 2};
+    double best = 1e30;
+    int bnb = BMAX_NB, bm = 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == 0 && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = EMU_ERR_HIP;
+    for (int a = 0; a < 2 && rc == 0; ++a)
+        for (int b = 0; b < 2 && rc == 0; ++b) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && rc == 0; ++rep) {
+                for (int i = 0; i < count; ++i) {
+                    (void)hipMemcpy2DAsync(Ac[i], n[i] * sizeof(double), A[i],
+                                           lda[i] * sizeof(double), n[i] * sizeof(double), n[i],
+                                           hipMemcpyDeviceToDevice, st);
+                    (void)hipMemcpy2DAsync(Bc[i], n[i] * sizeof(double), B[i],
+                                           ldb[i] * sizeof(double), n[i] * sizeof(double),
+                                           nrhs[i], hipMemcpyDeviceToDevice, st);
+                }
+                (void)hipEventRecord(e0, st);
+                rc = run_batch(count, n, nrhs, Ac.data(), ldc.data(), piv.data(), dinfo,
+                               Bc.data(), ldbc.data(), nbs[a], nslices, mults[b], true);
+                (void)hipEventRecord(e1, st);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (rc == 0 && ms < best) {
+                best = ms;
+                bnb = nbs[a];
+                bm = mults[b];
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    for (int i = 0; i < count; ++i) {
+        if (Ac[i]) (void)hipFree(Ac[i]);
+        if (Bc[i]) (void)hipFree(Bc[i]);
+        if (piv[i]) (void)hipFree(piv[i]);
+    }
+    (void)hipFree(dinfo);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        tune_load();
+        const int nmax = *std::max_element(n, n + count);
+        g_tuned[tune_key(count, nmax, nslices)] = {bnb, bm};
+        tune_save();
+    }
+    *best_nb = bnb;
+    *best_mult = bm;
+    *best_ms = best;
+    return 0;
+}
+
+}  // extern "C"

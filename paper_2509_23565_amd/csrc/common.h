@@ -89,11 +89,41 @@ int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
                  int s, int *code, int8_t *planes, int *status,
                  hipStream_t stream);
 
+// One operand of a grouped slicing pass with K <= 32 (one fragment block
+// along K): exponent scan and digits in a single pass.
+struct SliceJob {
+    const double *X;
+    long long ldx;
+    int lines, k, by_rows, LB;
+    int *code;
+    int8_t *planes;
+    size_t plane_bytes;
+};
+// jobs and wave_prefix (nj + 1 running sums of LB) are device arrays.
+int launch_slice_small_grouped(const SliceJob *jobs, const int *wave_prefix, int nj,
+                               int total_waves, int s, int *status, hipStream_t stream);
+
 // Unpack planes to plain column-major int8 (debug entry).
 int launch_unpack(const int8_t *planes, const Planes &g, int s, int by_rows,
                   int8_t *out, hipStream_t stream);
 int launch_codes_to_exps(const int *code, int lines, int *exps, int *nonfinite,
                          hipStream_t stream);
+
+// One slice-product GEMM problem (device pointers; planes in fragment order).
+struct GemmArgs {
+    const int8_t *Ap;
+    const int8_t *Bp;
+    size_t a_plane, b_plane;
+    const int *codeA;
+    const int *codeB;
+    int M, N, KB;         // logical sizes, K in 32-blocks
+    int chunk_kb;         // K-blocks per chunk (chunked partial mode)
+    int tiles_m, tiles_n;
+    double alpha, beta;
+    double *C;
+    long long ldc;
+    int32_t *part;        // chunk partials [chunk][g-2][n][m]
+};
 
 // Slice-product GEMM with fused recombination, or the raw diagonal sums
 // D_g (Dout != null, int64 [t-1][n][m]).  ws_part: INT32 scratch for K-chunk
@@ -106,6 +136,14 @@ int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
                      double beta, double *C, long long ldc, int64_t *Dout,
                      int32_t *ws_part, hipStream_t stream);
 bool gemm_supported(int s, int t);
+// Many problems of one (s, t = s + 1) in one persistent launch: probs[q]
+// (device) holds problem q with tiles_m/tiles_n set by gemm_tile_counts;
+// tile_prefix (device, nprob + 1) is the running sum of tiles_m * tiles_n.
+// K of every problem must not need chunking (K <= 32 * 462 for s = 9).
+void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n);
+int gemm_grouped_blocks_per_cu(int s);
+int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
+                             int total_tiles, int grid, int s, hipStream_t stream);
 
 // FP64 LU pieces.
 int launch_fill_int(int *p, int v, int count, hipStream_t stream);

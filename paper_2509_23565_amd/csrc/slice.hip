@@ -211,6 +211,92 @@ int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
     return 0;
 }
 
+// ------------------------------------------------ grouped, K <= 32
+// One wave per 32-line block of one job: lane l holds line l%32 and the
+// k-half l/32; the two lanes of a line exchange their maxima, so exponent
+// and digits come from one read of the operand.
+template <int S>
+__global__ __launch_bounds__(256) void k_slice_small_grouped(const SliceJob *__restrict__ jobs,
+                                                             const int *__restrict__ prefix,
+                                                             int nj, int total, int *status) {
+    const int wave = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= total) return;
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= wave) lo = mid;
+        else hi = mid - 1;
+    }
+    const SliceJob J = jobs[lo];
+    const int lb = wave - prefix[lo];
+    const int line = lb * 32 + (lane & 31);
+    const int kbase = (lane >> 5) * 16;
+    const bool ok = line < J.lines;
+    double x[16];
+    int code = CODE_ZERO;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        const int kx = kbase + kk;
+        x[kk] = 0.0;
+        if (ok && kx < J.k)
+            x[kk] = J.by_rows ? J.X[line + (long long)kx * J.ldx] : J.X[kx + (long long)line * J.ldx];
+        code = max(code, exp_code(x[kk]));
+    }
+    code = max(code, __shfl_xor(code, 32, 64));
+    if (ok && lane < 32) J.code[line] = code;
+    if (code == CODE_NONFINITE && lane < 32 && ok) atomicOr(status, EMU_STATUS_NONFINITE);
+    const int e = code_to_exp(code);
+    const bool good = ok && code != CODE_NONFINITE;
+    unsigned int w[S][4];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[d][q] = 0u;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        int neg;
+        const unsigned long long Z = digits_word(good ? x[kk] : 0.0, e, S, &neg);
+#pragma unroll
+        for (int d = 0; d < S; ++d) {
+            int q = (int)((Z >> (7 * (S - 1 - d))) & 127ull);
+            if (neg) q = -q;
+            w[d][kk >> 2] |= ((unsigned int)(q & 0xff)) << (8 * (kk & 3));
+        }
+    }
+    const size_t off = (size_t)lb * FRAG_BYTES + (size_t)lane * 16;
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+        uint4 v;
+        v.x = w[d][0];
+        v.y = w[d][1];
+        v.z = w[d][2];
+        v.w = w[d][3];
+        *reinterpret_cast<uint4 *>(J.planes + d * J.plane_bytes + off) = v;
+    }
+}
+
+int launch_slice_small_grouped(const SliceJob *jobs, const int *wave_prefix, int nj,
+                               int total_waves, int s, int *status, hipStream_t stream) {
+    if (total_waves <= 0 || nj <= 0) return 0;
+    dim3 grid((unsigned)((total_waves + 3) / 4));
+#define EMU_SCASE(S_)                                                                   \
+    case S_:                                                                            \
+        hipLaunchKernelGGL(k_slice_small_grouped<S_>, grid, dim3(256), 0, stream, jobs,  \
+                           wave_prefix, nj, total_waves, status);                       \
+        break;
+    switch (s) {
+        EMU_SCASE(1) EMU_SCASE(2) EMU_SCASE(3) EMU_SCASE(4) EMU_SCASE(5) EMU_SCASE(6)
+        EMU_SCASE(7) EMU_SCASE(8) EMU_SCASE(9)
+        default:
+            set_error("grouped slicing: slice count %d unsupported", s);
+            return EMU_ERR_UNSUPPORTED;
+    }
+#undef EMU_SCASE
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
 // ------------------------------------------------------------ debug views
 __global__ void k_unpack(const int8_t *__restrict__ planes, int lines, int k, int LB,
                          int KB, size_t plane_bytes, int s, int by_rows,

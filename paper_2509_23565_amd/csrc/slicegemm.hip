@@ -95,20 +95,6 @@ struct Cfg {
     }
 };
 
-struct GemmArgs {
-    const int8_t *Ap;
-    const int8_t *Bp;
-    size_t a_plane, b_plane;
-    const int *codeA;
-    const int *codeB;
-    int M, N, KB;         // logical sizes, K in 32-blocks
-    int chunk_kb;         // K-blocks per chunk (chunked partial mode)
-    int tiles_m, tiles_n;
-    double alpha, beta;
-    double *C;
-    long long ldc;
-    int32_t *part;        // chunk partials [chunk][g-2][n][m]
-};
 
 // XCD-aware tile order: consecutive workgroups go to different XCDs
 // (round-robin dispatch), so give XCD x the contiguous range of tile ids
@@ -129,29 +115,21 @@ __device__ __forceinline__ void tile_of(int L, int tiles_m, int tiles_n, int *tm
     *tn = in / gm;
 }
 
-// MODE 0: recombine into C.  MODE 2: write chunk partial INT32 D_g.
+// One output tile (tm, tn) over K blocks [kb0, kb1) of problem p.
+// MODE 0: recombine into C.  MODE 2: write the INT32 D_g of chunk `chunk`.
 template <int S, int T, bool SPLIT, int MODE>
-__global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
+__device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, int kb0,
+                                           int kb1, int chunk, int8_t *lds0, int8_t *lds1) {
     using CF = Cfg<S, T, SPLIT>;
     static_assert(CF::THREADS == 512, "launch bounds assume 8 waves");
     constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
     constexpr int NSLOT = CF::NSLOT;
-    __shared__ __attribute__((aligned(1024))) int8_t lds0[FR * FRAG_BYTES];
-    __shared__ __attribute__((aligned(1024))) int8_t lds1[FR * FRAG_BYTES];
 
     const int lane = threadIdx.x & 63;
     // wave index as a uniform (scalar) value, so per-wave addresses live in SGPRs
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int tm, tn;
-    tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
     const int mb0 = tm * TM, nb0 = tn * TN;
     const int wm = w % CF::WAVES_M, wn = w / CF::WAVES_M;
-
-    int kb0 = 0, kb1 = p.KB;
-    if (MODE == 2) {
-        kb0 = blockIdx.y * p.chunk_kb;
-        kb1 = min(p.KB, kb0 + p.chunk_kb);
-    }
 
     // fragment sources of this wave for one K step (uniform per wave)
     const int8_t *src[(FR + NW - 1) / NW];
@@ -254,7 +232,7 @@ __global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
                 if (MODE == 2) {
 #pragma unroll
                     for (int g = 0; g < T - 1; ++g)
-                        p.part[(((size_t)blockIdx.y * (T - 1) + g) * p.N + n) * p.M + m] =
+                        p.part[(((size_t)chunk * (T - 1) + g) * p.N + n) * p.M + m] =
                             acc[i][j][g][r];
                 } else {
                     const int cb = p.codeB[n];
@@ -279,6 +257,45 @@ __global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
                 }
             }
         }
+    }
+}
+
+template <int S, int T, bool SPLIT, int MODE>
+__global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
+    using CF = Cfg<S, T, SPLIT>;
+    __shared__ __attribute__((aligned(1024))) int8_t lds0[CF::FR * FRAG_BYTES];
+    __shared__ __attribute__((aligned(1024))) int8_t lds1[CF::FR * FRAG_BYTES];
+    int tm, tn;
+    tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
+    int kb0 = 0, kb1 = p.KB;
+    if (MODE == 2) {
+        kb0 = blockIdx.y * p.chunk_kb;
+        kb1 = min(p.KB, kb0 + p.chunk_kb);
+    }
+    sgemm_tile<S, T, SPLIT, MODE>(p, tm, tn, kb0, kb1, blockIdx.y, lds0, lds1);
+}
+
+// Persistent grouped form: every workgroup walks the concatenated tile list
+// of all problems (tile_prefix[q] = first tile of problem q).
+template <int S, int T>
+__global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__restrict__ probs,
+                                                           const int *__restrict__ tile_prefix,
+                                                           int nprob, int total) {
+    using CF = Cfg<S, T, false>;
+    __shared__ __attribute__((aligned(1024))) int8_t lds0[CF::FR * FRAG_BYTES];
+    __shared__ __attribute__((aligned(1024))) int8_t lds1[CF::FR * FRAG_BYTES];
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        int lo = 0, hi = nprob - 1;               // last q with prefix[q] <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_prefix[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmArgs p = probs[lo];
+        const int local = tile - tile_prefix[lo];
+        const int tm = local % p.tiles_m, tn = local / p.tiles_m;
+        __syncthreads();                          // LDS of the previous tile is free
+        sgemm_tile<S, T, false, 0>(p, tm, tn, 0, p.KB, 0, lds0, lds1);
     }
 }
 
@@ -436,6 +453,42 @@ int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
 #undef EMU_CASE
     set_error("no kernel for s=%d t=%d", s, t);
     return EMU_ERR_UNSUPPORTED;
+}
+
+void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n) {
+    // plain t = s + 1 shapes (Cfg): 128 x 128 tiles while s <= 5, else 64 x 128
+    const int tmr = (s <= 5) ? 128 : 64, tnc = 128;
+    *tiles_m = (m + tmr - 1) / tmr;
+    *tiles_n = (n + tnc - 1) / tnc;
+}
+
+int gemm_grouped_blocks_per_cu(int s) {
+    // LDS per workgroup: 2 buffers x s digits x (TM + TN) fragments of 1 KB
+    const int frags = (s <= 5) ? 8 : 6;
+    const int kb = 2 * s * frags;
+    int b = 160 / (kb > 0 ? kb : 1);
+    return b < 1 ? 1 : (b > 2 ? 2 : b);
+}
+
+int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
+                             int total_tiles, int grid, int s, hipStream_t stream) {
+    if (total_tiles <= 0 || nprob <= 0) return 0;
+    if (grid > total_tiles) grid = total_tiles;
+#define EMU_GCASE(S_)                                                                  \
+    case S_:                                                                           \
+        hipLaunchKernelGGL((k_slicegemm_grouped<S_, S_ + 1>), dim3(grid), dim3(512), 0, \
+                           stream, probs, tile_prefix, nprob, total_tiles);            \
+        break;
+    switch (s) {
+        EMU_GCASE(1) EMU_GCASE(2) EMU_GCASE(3) EMU_GCASE(4) EMU_GCASE(5) EMU_GCASE(6)
+        EMU_GCASE(7) EMU_GCASE(8) EMU_GCASE(9)
+        default:
+            set_error("grouped GEMM: slice count %d unsupported", s);
+            return EMU_ERR_UNSUPPORTED;
+    }
+#undef EMU_GCASE
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
 }
 
 }  // namespace emu

@@ -310,3 +310,75 @@ def test_refinement_singular_reports_info():
     B = matgen.uniform(200, 1, seed=26)
     _, inf = emu.dgesv_ir(emu.colmajor(A), emu.colmajor(B), nb=64, nslices=5)
     assert inf["info"] == 51 and inf["rc"] == 0
+
+
+# ------------------------------------------------------------ batched form
+
+def _batch(count, seed, nmin=64, nmax=1024):
+    specs = matgen.batched_specs(count, seed=seed, nmin=nmin, nmax=nmax)
+    As = [matgen.phi_matrix(n, n, phi, seed=seed, substream=1000 + i)
+          for i, (n, phi, r) in enumerate(specs)]
+    Bs = [matgen.uniform(n, r, seed=seed, substream=5000 + i)
+          for i, (n, phi, r) in enumerate(specs)]
+    return specs, As, Bs
+
+
+@pytest.mark.parametrize("nb,s", [(32, 5), (16, 3)])
+def test_batched_solve_bit_exact_vs_oracle_and_single(nb, s):
+    specs, As, Bs = _batch(12, seed=31, nmin=40, nmax=700)
+    Ag = [emu.colmajor(a) for a in As]
+    Bg = [emu.colmajor(b) for b in Bs]
+    ipivs, info = emu.dgesv_batched(Ag, Bg, nb=nb, nslices=s)
+    assert not _host(info).any()
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        LU, piv, inf = O.getrf(A, nb=nb, s=s)
+        X = O.getrs(LU, piv, B)
+        assert np.array_equal(_host(ipivs[i]), piv), i
+        assert _same_bits(_host(Ag[i]), LU), i
+        assert _same_bits(_host(Bg[i]), X), i
+        # grouped == single-system path with the same block size
+        A1 = emu.colmajor(A)
+        p1, _ = emu.dgetrf(A1, nb=nb, nslices=s)
+        assert _same_bits(_host(A1), LU) and np.array_equal(_host(p1), piv)
+
+
+def test_batched_graph_replay_with_new_matrices():
+    specs, As, Bs = _batch(10, seed=32, nmin=30, nmax=500)
+    for rep in range(3):
+        # same shapes, new values: the cached graph is replayed
+        As2 = [a * (1.0 + 0.25 * rep) + rep for a in As]
+        Ag = [emu.colmajor(a) for a in As2]
+        Bg = [emu.colmajor(b) for b in Bs]
+        ipivs, info = emu.dgesv_batched(Ag, Bg, nb=32, nslices=4)
+        torch.cuda.synchronize()
+        for i in (0, 4, 9):
+            LU, piv, _ = O.getrf(As2[i], nb=32, s=4)
+            assert _same_bits(_host(Ag[i]), LU), (rep, i)
+            assert _same_bits(_host(Bg[i]), O.getrs(LU, piv, Bs[i])), (rep, i)
+
+
+def test_batched_singular_info_and_limits():
+    specs, As, Bs = _batch(5, seed=33, nmin=50, nmax=200)
+    A2 = np.array(As[2], order="F")
+    A2[:, 7] = 0.0
+    As[2] = A2
+    Ag = [emu.colmajor(a) for a in As]
+    ipivs, info = emu.dgetrf_batched(Ag, nb=32, nslices=5)
+    h = _host(info)
+    assert h[2] == 8 and h[[0, 1, 3, 4]].sum() == 0
+    big = [emu.colmajor(np.eye(1100))]
+    with pytest.raises(emu.EmuError):
+        emu.dgetrf_batched(big, nb=32, nslices=5)
+
+
+def test_batched_autotune_records_choice():
+    specs, As, Bs = _batch(8, seed=34, nmin=64, nmax=400)
+    Ag = [emu.colmajor(a) for a in As]
+    Bg = [emu.colmajor(b) for b in Bs]
+    nb, mult, ms = emu.autotune_batched(Ag, Bg, nslices=5)
+    assert nb in (16, 32) and mult in (1, 2) and ms > 0
+    # inputs untouched by tuning; nb = 0 then uses the tuned block size
+    assert _same_bits(_host(Ag[3]), As[3])
+    ipivs, info = emu.dgesv_batched(Ag, Bg, nb=0, nslices=5)
+    LU, piv, _ = O.getrf(As[3], nb=nb, s=5)
+    assert _same_bits(_host(Ag[3]), LU)
