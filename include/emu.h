@@ -186,6 +186,20 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
                  int *iters, double *berr, int *s_final, int *info);
 
 /*
+ * emu_refine: FP64 iterative refinement of an existing solution X of
+ * A X = B with existing factors (LU, ipiv from any emu_dgetrf variant):
+ * repeat R = B - A X, eta = max over columns of ||R||_inf /
+ * (||A||_inf ||X||_inf + ||B||_inf); stop at eta <= tol; else, unless eta
+ * failed to halve or `maxiter` corrections were applied (then
+ * EMU_ERR_NOT_CONVERGED), X += getrs(R).  *iters, *berr on the HOST.
+ * Argument numbers: n=1 nrhs=2 A=3 lda=4 LU=5 ldlu=6 ipiv=7 B=8 ldb=9 X=10
+ * ldx=11 tol=12 maxiter=13 iters=14 berr=15.
+ */
+int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int ldlu,
+               const int *ipiv, const double *B, int ldb, double *X, int ldx, double tol,
+               int maxiter, int *iters, double *berr);
+
+/*
  * Batched grouped form (not in the paper; every system is the paper's LU):
  * `count` independent systems i with n[i] in 1..1024 (host array), A[i]
  * (host array of DEVICE pointers, lda[i] >= n[i]), ipiv[i] (host array of
@@ -224,6 +238,77 @@ int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A
 int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const *A,
                          const int *lda, double *const *B, const int *ldb, int nslices,
                          int *best_nb, int *best_mult, double *best_ms);
+
+/*
+ * Learned slice count (not in the paper; it builds on the paper's
+ * observation that an element loses the digits by which its exponent sits
+ * below its row's or column's largest, eqn (3)).
+ *
+ * emu_features: 16 features per 256 x 256 tile (I, J) of the update
+ * C = L21 U12 (L21 m x k, ldl; U12 k x n, ldu; device): over the nonzero
+ * finite elements of L21's rows in block I and U12's columns in block J,
+ * rho = (frexp exponent) - (largest frexp exponent of its row / column);
+ * features = [min rho, max rho, mean rho, std rho, fraction of -rho in each
+ * of the 12 bins [0,7), [7,14), ..., [77, inf)] (zeros for an empty tile).
+ * feat: device float[tiles][16], tile index I + J * ceil(m/256).
+ * Argument numbers: m=1 n=2 k=3 L21=4 ldl=5 U12=6 ldu=7 feat=8.
+ */
+int emu_features(int m, int n, int k, const double *L21, int ldl, const double *U12, int ldu,
+                 float *feat);
+
+/* Number of MLP parameters (5703): W1[64][16] b1[64] W2[64][64] b2[64]
+ * W3[7][64] b3[7], float32, in that order. */
+int emu_mlp_nparam(void);
+
+/*
+ * emu_mlp_train_step: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected with `step` >= 1) of the MLP 16 -> 64 (ReLU) -> 64 (ReLU)
+ * -> 7 (softmax over s = 3..9) on the mean cross-entropy of B samples:
+ * X device float[B][16], labels device int32[B] in 0..6 (class = s - 3),
+ * params/m/v device float[nparam], updated in place; loss (device float[B],
+ * may be NULL) receives the per-sample losses before the step.
+ * Argument numbers: params=1 X=2 labels=3 B=4 m=5 v=6 step=7 lr=8 loss=9.
+ */
+int emu_mlp_train_step(float *params, const float *X, const int *labels, int B, float *m,
+                       float *v, int step, float lr, float *loss);
+
+/* emu_mlp_grad: the gradient of that loss (device float[nparam]) without
+ * an update.  Argument numbers: params=1 X=2 labels=3 B=4 grad=5. */
+int emu_mlp_grad(const float *params, const float *X, const int *labels, int B, float *grad);
+
+/* emu_mlp_infer: class probabilities (device float[B][7]) and, if s_out is
+ * not NULL, the slice count per sample: the smallest s whose cumulative
+ * probability reaches conf (device int32[B], values 3..9).
+ * Argument numbers: params=1 X=2 B=3 prob=4 s_out=5 conf=6. */
+int emu_mlp_infer(const float *params, const float *X, int B, float *prob, int *s_out,
+                  float conf);
+
+/*
+ * emu_tile_labels: training labels produced by the emulator: X_s = L21 U12
+ * emulated with s slices for s = s_lo..s_hi; label of 256 x 256 tile q =
+ * the smallest s with ||X_s - X_shi||_F <= tau ||X_shi||_F on that tile
+ * (s_hi if none).  labels: device int32[tiles] (values s, not classes).
+ * Argument numbers: m=1 n=2 k=3 L21=4 ldl=5 U12=6 ldu=7 s_lo=8 s_hi=9
+ * tau=10 labels=11.
+ */
+int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const double *U12, int ldu,
+                    int s_lo, int s_hi, double tau, int *labels);
+
+/*
+ * emu_dgetrf_adaptive: emu_dgetrf whose every Schur update uses a slice count
+ * per 256 x 256 tile predicted by the MLP (params, device) from
+ * emu_features of that update, capped at s_full; operands are sliced once at
+ * the step's largest count and each tile uses the leading digit planes.
+ * smaps (HOST int32, capacity smaps_cap, may be NULL) receives every step's
+ * tile counts in order; products (HOST int64[3]) receives the slice products
+ * used (sum of tile area x s(s+1)/2), the same at s_full, and the number of
+ * tiles.  Synchronizes the stream once per block step.
+ * Argument numbers: m=1 n=2 A=3 lda=4 ipiv=5 info=6 nb=7 params=8
+ * s_full=9 conf=10 smaps=11 smaps_cap=12 products=13.
+ */
+int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, int nb,
+                        const float *params, int s_full, float conf, int *smaps,
+                        long long smaps_cap, long long *products);
 
 /*
  * emu_debug_slices: expose the exponent scan and digit slicing of one

@@ -28,6 +28,10 @@ __all__ = [
     "emu_set_param", "emu_dgesv_ir", "set_param", "dgesv_ir",
     "emu_dgetrf_batched", "emu_dgesv_batched", "emu_autotune_batched",
     "dgetrf_batched", "dgesv_batched", "autotune_batched",
+    "emu_mlp_nparam", "emu_features", "emu_mlp_train_step", "emu_mlp_grad", "emu_mlp_infer",
+    "emu_tile_labels", "emu_dgetrf_adaptive", "features", "mlp_init", "mlp_train_step",
+    "emu_refine", "refine",
+    "mlp_grad", "mlp_infer", "tile_labels", "dgetrf_adaptive",
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status",
 ]
@@ -67,6 +71,16 @@ _SIGNATURES = {
     "emu_dgesv_batched": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I], _I),
     "emu_autotune_batched": ([_I, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_I),
                               ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
+    "emu_refine": ([_I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _I, _D, _I, ctypes.POINTER(_I),
+                    ctypes.POINTER(_D)], _I),
+    "emu_mlp_nparam": ([], _I),
+    "emu_features": ([_I, _I, _I, _P, _I, _P, _I, _P], _I),
+    "emu_mlp_train_step": ([_P, _P, _P, _I, _P, _P, _I, ctypes.c_float, _P], _I),
+    "emu_mlp_grad": ([_P, _P, _P, _I, _P], _I),
+    "emu_mlp_infer": ([_P, _P, _I, _P, _P, ctypes.c_float], _I),
+    "emu_tile_labels": ([_I, _I, _I, _P, _I, _P, _I, _I, _I, _D, _P], _I),
+    "emu_dgetrf_adaptive": ([_I, _I, _P, _I, _P, _P, _I, _P, _I, ctypes.c_float, _P,
+                             ctypes.c_longlong, _P], _I),
     "emu_profile_start": ([], _I),
     "emu_profile_stop": ([], _I),
     "emu_profile_read": ([_I, ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
@@ -115,6 +129,14 @@ emu_dgesv_ir = _raw("emu_dgesv_ir")
 emu_dgetrf_batched = _raw("emu_dgetrf_batched")
 emu_dgesv_batched = _raw("emu_dgesv_batched")
 emu_autotune_batched = _raw("emu_autotune_batched")
+emu_refine = _raw("emu_refine")
+emu_mlp_nparam = _raw("emu_mlp_nparam")
+emu_features = _raw("emu_features")
+emu_mlp_train_step = _raw("emu_mlp_train_step")
+emu_mlp_grad = _raw("emu_mlp_grad")
+emu_mlp_infer = _raw("emu_mlp_infer")
+emu_tile_labels = _raw("emu_tile_labels")
+emu_dgetrf_adaptive = _raw("emu_dgetrf_adaptive")
 emu_profile_start = _raw("emu_profile_start")
 emu_profile_stop = _raw("emu_profile_stop")
 emu_profile_read = _raw("emu_profile_read")
@@ -320,6 +342,115 @@ def autotune_batched(As, Bs, nslices=5):
                                 ctypes.byref(bnb), ctypes.byref(bm), ctypes.byref(bms)),
            "emu_autotune_batched")
     return bnb.value, bm.value, bms.value
+
+
+def refine(A, LU, ipiv, B, X, tol=1e-15, maxiter=10):
+    """Refine X in place with existing factors; returns (rc, iters, berr)."""
+    n = A.shape[0]
+    nrhs = B.shape[1]
+    pa, lda = _mat(A, "A")
+    pl, ldl = _mat(LU, "LU")
+    pb, ldb = _mat(B, "B")
+    px, ldx = _mat(X, "X")
+    it = ctypes.c_int(0)
+    be = ctypes.c_double(0.0)
+    _bind_stream()
+    rc = emu_refine(n, nrhs, pa, lda, pl, ldl, ipiv.data_ptr(), pb, ldb, px, ldx, float(tol),
+                    int(maxiter), ctypes.byref(it), ctypes.byref(be))
+    if rc not in (0, 1004):
+        _check(rc, "emu_refine")
+    return rc, it.value, be.value
+
+
+# --------------------------------------------------------------- learned
+def _tiles(m, n):
+    return ((m + 255) // 256) * ((n + 255) // 256)
+
+
+def features(L21, U12):
+    """float32 device tensor [tiles][16] of the update L21 @ U12."""
+    torch = _torch()
+    m, k = L21.shape
+    n = U12.shape[1]
+    pl, ldl = _mat(L21, "L21")
+    pu, ldu = _mat(U12, "U12")
+    f = torch.zeros((max(_tiles(m, n), 1), 16), dtype=torch.float32, device=L21.device)
+    _bind_stream()
+    _check(emu_features(m, n, k, pl, ldl, pu, ldu, f.data_ptr()), "emu_features")
+    return f[:_tiles(m, n)]
+
+
+def mlp_init(seed=0, device="cuda"):
+    """Xavier-uniform weights, zero biases (float32 device tensor)."""
+    import numpy as np
+    torch = _torch()
+    g = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((64, 16), (64, 64), (7, 64)):
+        lim = (6.0 / (fan_in + fan_out)) ** 0.5
+        parts.append(g.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == emu_mlp_nparam()
+    return torch.as_tensor(p, device=device)
+
+
+def mlp_train_step(params, X, labels, m, v, step, lr=1e-3, loss=None):
+    _bind_stream()
+    _check(emu_mlp_train_step(params.data_ptr(), X.data_ptr(), labels.data_ptr(),
+                              int(X.shape[0]), m.data_ptr(), v.data_ptr(), int(step),
+                              float(lr), loss.data_ptr() if loss is not None else None),
+           "emu_mlp_train_step")
+
+
+def mlp_grad(params, X, labels):
+    torch = _torch()
+    g = torch.zeros_like(params)
+    _bind_stream()
+    _check(emu_mlp_grad(params.data_ptr(), X.data_ptr(), labels.data_ptr(), int(X.shape[0]),
+                        g.data_ptr()), "emu_mlp_grad")
+    return g
+
+
+def mlp_infer(params, X, conf=0.95):
+    torch = _torch()
+    B = int(X.shape[0])
+    prob = torch.zeros((max(B, 1), 7), dtype=torch.float32, device=X.device)
+    s = torch.zeros(max(B, 1), dtype=torch.int32, device=X.device)
+    _bind_stream()
+    _check(emu_mlp_infer(params.data_ptr(), X.data_ptr(), B, prob.data_ptr(), s.data_ptr(),
+                         float(conf)), "emu_mlp_infer")
+    return prob[:B], s[:B]
+
+
+def tile_labels(L21, U12, s_lo=3, s_hi=9, tau=2.0 ** -40):
+    torch = _torch()
+    m, k = L21.shape
+    n = U12.shape[1]
+    pl, ldl = _mat(L21, "L21")
+    pu, ldu = _mat(U12, "U12")
+    lab = torch.zeros(_tiles(m, n), dtype=torch.int32, device=L21.device)
+    _bind_stream()
+    _check(emu_tile_labels(m, n, k, pl, ldl, pu, ldu, int(s_lo), int(s_hi), float(tau),
+                           lab.data_ptr()), "emu_tile_labels")
+    return lab
+
+
+def dgetrf_adaptive(A, params, nb=256, s_full=9, conf=0.95, smaps_cap=1 << 20):
+    """In-place LU with per-tile slice counts; returns (ipiv, info, smaps, products)."""
+    torch = _torch()
+    m, n = A.shape
+    pa, lda = _mat(A, "A")
+    ipiv = torch.zeros(max(min(m, n), 1), dtype=torch.int32, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    smaps = (ctypes.c_int * smaps_cap)()
+    prods = (ctypes.c_longlong * 3)()
+    _bind_stream()
+    _check(emu_dgetrf_adaptive(m, n, pa, lda, ipiv.data_ptr(), info.data_ptr(), int(nb),
+                               params.data_ptr(), int(s_full), float(conf), smaps,
+                               smaps_cap, prods), "emu_dgetrf_adaptive")
+    used, full, ntiles = prods[0], prods[1], prods[2]
+    return ipiv[:min(m, n)], info, list(smaps[:min(ntiles, smaps_cap)]), (used, full)
 
 
 def debug_slices(X, by_rows, nslices):

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libemu.so")
 ARCH = "gfx950"
 SOURCES = ["api.hip", "slice.hip", "slicegemm.hip", "lu.hip", "panel.hip", "refine.hip",
-           "batched.hip"]
+           "batched.hip", "learned.hip"]
 
 
 def _hipcc() -> str:

@@ -602,4 +602,325 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     }
 }
 
+int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int ldlu,
+               const int *ipiv, const double *B, int ldb, double *X, int ldx, double tol,
+               int maxiter, int *iters, double *berr) {
+    if (n < 0) return -1;
+    if (nrhs < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < imax1(n)) return -4;
+    if (n > 0 && !LU) return -5;
+    if (ldlu < imax1(n)) return -6;
+    if (n > 0 && !ipiv) return -7;
+    if (n > 0 && nrhs > 0 && !B) return -8;
+    if (ldb < imax1(n)) return -9;
+    if (n > 0 && nrhs > 0 && !X) return -10;
+    if (ldx < imax1(n)) return -11;
+    if (!(tol > 0.0)) return -12;
+    if (maxiter < 0) return -13;
+    if (!iters) return -14;
+    if (!berr) return -15;
+    *iters = 0;
+    *berr = 0.0;
+    if (n == 0 || nrhs == 0) return 0;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    size_t off = 0;
+    const size_t o_r = off;
+    off += align256((size_t)n * nrhs * sizeof(double));
+    const size_t o_part = off;
+    off += align256(refine_partial_bytes(n, nrhs));
+    const size_t o_stats = off;
+    off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
+    const size_t o_sub = off;
+    off += getrs_scratch_bytes(n, nrhs);
+    EMU_TRY(reserve(dev, st, off));
+    char *ws = static_cast<char *>(dev->ws);
+    double *R = reinterpret_cast<double *>(ws + o_r);
+    double *part = reinterpret_cast<double *>(ws + o_part);
+    double *normA = reinterpret_cast<double *>(ws + o_stats);
+    double *stats = normA + 1;
+    EMU_TRY(launch_norm_inf(A, lda, n, part, normA, st));
+    std::vector<double> hstats(3 * (size_t)nrhs);
+    double hnorm = 0.0, prev = -1.0;
+    for (int it = 0;; ++it) {
+        EMU_TRY(launch_residual(A, lda, n, X, ldx, B, ldb, nrhs, R, n, part, stats, st));
+        EMU_TRY_HIP(hipMemcpyAsync(hstats.data(), stats, hstats.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        EMU_TRY_HIP(hipMemcpyAsync(&hnorm, normA, sizeof(double), hipMemcpyDeviceToHost, st));
+        EMU_TRY_HIP(hipStreamSynchronize(st));
+        double eta = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+            const double den = hnorm * hstats[3 * r + 1] + hstats[3 * r + 2];
+            const double e = den > 0.0 ? hstats[3 * r] / den : hstats[3 * r];
+            if (!(e <= eta)) eta = e;
+        }
+        *berr = eta;
+        *iters = it;
+        if (eta <= tol) return 0;
+        if (it >= maxiter || (prev >= 0.0 && !(eta <= 0.5 * prev)) || eta != eta) {
+            set_error("emu_refine: eta %g above %g after %d corrections", eta, tol, it);
+            return EMU_ERR_NOT_CONVERGED;
+        }
+        prev = eta;
+        EMU_TRY(launch_getrs(n, nrhs, LU, ldlu, ipiv, R, n, reinterpret_cast<int *>(ws + o_sub),
+                             st));
+        EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
+    }
+}
+
+// ------------------------------------------------------------ learned form
+int emu_mlp_nparam(void) { return learned_nparam(); }
+
+int emu_features(int m, int n, int k, const double *L21, int ldl, const double *U12, int ldu,
+                 float *feat) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (k < 0) return -3;
+    if (m > 0 && k > 0 && !L21) return -4;
+    if (ldl < imax1(m)) return -5;
+    if (n > 0 && k > 0 && !U12) return -6;
+    if (ldu < imax1(k)) return -7;
+    if (m > 0 && n > 0 && !feat) return -8;
+    if (m == 0 || n == 0) return 0;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    EMU_TRY(reserve(dev, st, features_ws_bytes(m, n)));
+    return launch_features(L21, ldl, U12, ldu, m, n, k, feat, dev->ws, st);
+}
+
+int emu_mlp_train_step(float *params, const float *X, const int *labels, int B, float *m,
+                       float *v, int step, float lr, float *loss) {
+    if (!params) return -1;
+    if (B > 0 && !X) return -2;
+    if (B > 0 && !labels) return -3;
+    if (B < 1) return -4;
+    if (!m) return -5;
+    if (!v) return -6;
+    if (step < 1) return -7;
+    if (!(lr > 0.0f)) return -8;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    EMU_TRY(reserve(dev, st, mlp_train_ws_bytes(B)));
+    return launch_mlp_train_step(params, X, labels, B, m, v, step, lr, dev->ws, loss, st);
+}
+
+int emu_mlp_grad(const float *params, const float *X, const int *labels, int B, float *grad) {
+    if (!params) return -1;
+    if (!X) return -2;
+    if (!labels) return -3;
+    if (B < 1) return -4;
+    if (!grad) return -5;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    EMU_TRY(reserve(dev, st, mlp_train_ws_bytes(B)));
+    return launch_mlp_grad_only(params, X, labels, B, grad, dev->ws, st);
+}
+
+int emu_mlp_infer(const float *params, const float *X, int B, float *prob, int *s_out,
+                  float conf) {
+    if (!params) return -1;
+    if (B > 0 && !X) return -2;
+    if (B < 0) return -3;
+    if (B > 0 && !prob) return -4;
+    if (!(conf > 0.0f && conf <= 1.0f)) return -6;
+    if (B == 0) return 0;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    return launch_mlp_infer(params, X, B, prob, s_out, conf, st);
+}
+
+int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const double *U12, int ldu,
+                    int s_lo, int s_hi, double tau, int *labels) {
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (k < 1) return -3;
+    if (!L21) return -4;
+    if (ldl < m) return -5;
+    if (!U12) return -6;
+    if (ldu < k) return -7;
+    if (s_lo < 1 || s_lo > EMU_MAX_SLICES) return -8;
+    if (s_hi < s_lo || s_hi > EMU_MAX_SLICES) return -9;
+    if (!(tau > 0.0)) return -10;
+    if (!labels) return -11;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    const int tm = (m + 255) / 256, tn = (n + 255) / 256, nt = tm * tn;
+    // scratch: X_ref | X_s | err2 | ref2 | GEMM scratch
+    size_t off = 0;
+    const size_t o_ref = off;
+    off += align256((size_t)m * n * sizeof(double));
+    const size_t o_x = off;
+    off += align256((size_t)m * n * sizeof(double));
+    const size_t o_e = off;
+    off += align256((size_t)nt * sizeof(double));
+    const size_t o_r = off;
+    off += align256((size_t)nt * sizeof(double));
+    const size_t o_g = off;
+    GemmScratch g = gemm_scratch(m, n, k, s_hi, s_hi + 1);
+    off += g.total;
+    EMU_TRY(reserve(dev, st, off));
+    char *ws = static_cast<char *>(dev->ws);
+    double *Xr = reinterpret_cast<double *>(ws + o_ref);
+    double *Xs = reinterpret_cast<double *>(ws + o_x);
+    double *e2 = reinterpret_cast<double *>(ws + o_e);
+    double *r2 = reinterpret_cast<double *>(ws + o_r);
+    EMU_TRY(launch_fill_int(labels, -1, nt, st));
+    EMU_TRY(gemm_core(dev, ws + o_g, st, gemm_scratch(m, n, k, s_hi, s_hi + 1), m, n, k, 1.0,
+                      L21, ldl, U12, ldu, 0.0, Xr, m, s_hi, s_hi + 1, nullptr));
+    for (int s = s_lo; s < s_hi; ++s) {
+        EMU_TRY(gemm_core(dev, ws + o_g, st, gemm_scratch(m, n, k, s, s + 1), m, n, k, 1.0, L21,
+                          ldl, U12, ldu, 0.0, Xs, m, s, s + 1, nullptr));
+        EMU_TRY(launch_tile_err(Xs, Xr, m, m, n, e2, r2, st));
+        EMU_TRY(launch_tile_label(e2, r2, nt, s, tau, labels, st));
+    }
+    // tiles no smaller count reaches take the largest
+    EMU_TRY(launch_tile_err(Xr, Xr, m, m, n, e2, r2, st));
+    EMU_TRY(launch_tile_label(e2, r2, nt, s_hi, 1.0, labels, st));
+    return 0;
+}
+
+int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, int nb,
+                        const float *params, int s_full, float conf, int *smaps,
+                        long long smaps_cap, long long *products) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && n > 0 && !A) return -3;
+    if (lda < imax1(m)) return -4;
+    const int mn = m < n ? m : n;
+    if (mn > 0 && !ipiv) return -5;
+    if (!info) return -6;
+    if (nb > 1024) return -7;
+    if (!params) return -8;
+    if (s_full < 3 || s_full > EMU_MAX_SLICES) return -9;
+    if (!(conf > 0.0f && conf <= 1.0f)) return -10;
+    if (smaps_cap < 0) return -12;
+    if (!products) return -13;
+    if (nb <= 0) nb = 64;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    const int jb0 = nb < mn ? nb : mn;
+    const int M0 = m - jb0 > 0 ? m - jb0 : 1, N0 = n - jb0 > 0 ? n - jb0 : 1;
+    const int tm0 = (M0 + 255) / 256, tn0 = (N0 + 255) / 256, nt0 = tm0 * tn0;
+    // scratch: getrf pieces | features | probs | smap | tile problems | prefix
+    size_t off = 0;
+    const size_t o_lu = off;
+    off += align256(getrf_scratch_bytes(m, n, nb, s_full));
+    const size_t o_fs = off;
+    off += align256(features_ws_bytes(M0, N0));
+    const size_t o_feat = off;
+    off += align256((size_t)nt0 * 16 * sizeof(float));
+    const size_t o_prob = off;
+    off += align256((size_t)nt0 * 7 * sizeof(float));
+    const size_t o_smap = off;
+    off += align256((size_t)nt0 * sizeof(int));
+    const size_t o_prob2 = off;
+    off += align256((size_t)nt0 * sizeof(GemmArgs));
+    const size_t o_pre = off;
+    off += align256((size_t)(nt0 + 1) * sizeof(int));
+    EMU_TRY(reserve(dev, st, off));
+    char *ws = static_cast<char *>(dev->ws);
+    char *lws = ws + o_lu;
+    char *pws = lws + getrf_gemm_bytes(m, n, nb, s_full);
+    float *feat = reinterpret_cast<float *>(ws + o_feat);
+    float *prob = reinterpret_cast<float *>(ws + o_prob);
+    int *smap = reinterpret_cast<int *>(ws + o_smap);
+    GemmArgs *dprob = reinterpret_cast<GemmArgs *>(ws + o_prob2);
+    int *dpre = reinterpret_cast<int *>(ws + o_pre);
+    EMU_TRY(launch_fill_int(info, 0, 1, st));
+    long long used = 0, full = 0, rec = 0;
+    std::vector<int> hs(nt0);
+    std::vector<GemmArgs> probs;
+    std::vector<int> pre;
+    int cus = 0, did = 0;
+    (void)hipGetDevice(&did);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, did);
+    if (cus <= 0) cus = 256;
+    const long long ld = lda;
+    for (int j0 = 0; j0 < mn; j0 += nb) {
+        const int jb = nb < mn - j0 ? nb : mn - j0;
+        const int j1 = j0 + jb;
+        double *Ajj = A + j0 + (long long)j0 * ld;
+        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, st));
+        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, st));
+        if (j1 >= n) continue;
+        double *U12 = A + j0 + (long long)j1 * ld;
+        EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));
+        if (j1 >= m) continue;
+        const int M = m - j1, N = n - j1;
+        const double *L21 = A + j1 + (long long)j0 * ld;
+        const int tm = (M + 255) / 256, tn = (N + 255) / 256, nt = tm * tn;
+        EMU_TRY(launch_features(L21, ld, U12, ld, M, N, jb, feat, ws + o_fs, st));
+        EMU_TRY(launch_mlp_infer(params, feat, nt, prob, smap, conf, st));
+        EMU_TRY_HIP(hipMemcpyAsync(hs.data(), smap, nt * sizeof(int), hipMemcpyDeviceToHost, st));
+        EMU_TRY_HIP(hipStreamSynchronize(st));
+        int smax = 1;
+        for (int q = 0; q < nt; ++q) {
+            if (hs[q] > s_full) hs[q] = s_full;
+            if (hs[q] > smax) smax = hs[q];
+        }
+        if (smaps && rec + nt <= smaps_cap)
+            for (int q = 0; q < nt; ++q) smaps[rec + q] = hs[q];
+        rec += nt;
+        // one slicing at the largest count: every smaller count uses the
+        // leading digit planes (truncated digits are prefixes of each other)
+        GemmScratch g = gemm_scratch(M, N, jb, smax, smax + 1);
+        int *codeA = reinterpret_cast<int *>(lws + g.off_codeA);
+        int *codeB = reinterpret_cast<int *>(lws + g.off_codeB);
+        int8_t *pa = reinterpret_cast<int8_t *>(lws + g.off_pa);
+        int8_t *pb = reinterpret_cast<int8_t *>(lws + g.off_pb);
+        EMU_TRY(launch_slice(L21, ld, 1, g.ga, smax, codeA, pa, dev->status, st));
+        EMU_TRY(launch_slice(U12, ld, 0, g.gb, smax, codeB, pb, dev->status, st));
+        for (int s = 1; s <= smax; ++s) {
+            probs.clear();
+            pre.assign(1, 0);
+            for (int q = 0; q < nt; ++q) {
+                const long long area = (long long)((q % tm == tm - 1) ? M - (q % tm) * 256 : 256) *
+                                       ((q / tm == tn - 1) ? N - (q / tm) * 256 : 256);
+                if (s == smax) full += area * (long long)(s_full * (s_full + 1) / 2);
+                if (hs[q] != s) continue;
+                used += area * (long long)(s * (s + 1) / 2);
+                const int I = q % tm, J = q / tm;
+                GemmArgs a{};
+                a.Ap = pa + (size_t)I * 8 * g.ga.KB * FRAG_BYTES;
+                a.Bp = pb + (size_t)J * 8 * g.gb.KB * FRAG_BYTES;
+                a.a_plane = g.ga.plane_bytes;
+                a.b_plane = g.gb.plane_bytes;
+                a.codeA = codeA + I * 256;
+                a.codeB = codeB + J * 256;
+                a.M = M - I * 256 < 256 ? M - I * 256 : 256;
+                a.N = N - J * 256 < 256 ? N - J * 256 : 256;
+                a.KB = g.ga.KB;
+                a.alpha = -1.0;
+                a.beta = 1.0;
+                a.C = A + (j1 + I * 256) + (long long)(j1 + J * 256) * ld;
+                a.ldc = ld;
+                gemm_tile_counts(s, a.M, a.N, &a.tiles_m, &a.tiles_n);
+                probs.push_back(a);
+                pre.push_back(pre.back() + a.tiles_m * a.tiles_n);
+            }
+            if (probs.empty()) continue;
+            EMU_TRY_HIP(hipMemcpyAsync(dprob, probs.data(), probs.size() * sizeof(GemmArgs),
+                                       hipMemcpyHostToDevice, st));
+            EMU_TRY_HIP(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int),
+                                       hipMemcpyHostToDevice, st));
+            EMU_TRY(launch_slicegemm_grouped(dprob, dpre, (int)probs.size(), pre.back(),
+                                             cus * gemm_grouped_blocks_per_cu(s), s, st));
+            // the host tables are reused by the next launch
+            EMU_TRY_HIP(hipStreamSynchronize(st));
+        }
+    }
+    products[0] = used;
+    products[1] = full;
+    products[2] = rec;
+    return 0;
+}
+
 }  // extern "C"

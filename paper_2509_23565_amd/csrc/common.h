@@ -173,4 +173,22 @@ int launch_add_cols(double *X, long long ldx, const double *D, long long ldd, in
 int launch_copy_mat(const double *src, long long lds_, double *dst, long long ldd, int n,
                     int cols, hipStream_t stream);
 
+// Learned slice count (learned.hip).
+int learned_nparam();
+size_t features_ws_bytes(int m, int n);
+int launch_features(const double *L21, long long ldl, const double *U12, long long ldu, int m,
+                    int n, int k, float *feat, void *stat_ws, hipStream_t st);
+size_t mlp_train_ws_bytes(int B);
+int launch_mlp_train_step(float *params, const float *X, const int *label, int B, float *m,
+                          float *v, int step, float lr, void *ws, float *loss_out,
+                          hipStream_t st);
+int launch_mlp_grad_only(const float *params, const float *X, const int *label, int B,
+                         float *grad_out, void *ws, hipStream_t st);
+int launch_mlp_infer(const float *params, const float *X, int B, float *prob, int *s_out,
+                     float conf, hipStream_t st);
+int launch_tile_err(const double *Xs, const double *Xr, long long ld, int m, int n,
+                    double *err2, double *ref2, hipStream_t st);
+int launch_tile_label(const double *err2, const double *ref2, int ntiles, int s, double tau,
+                      int *label, hipStream_t st);
+
 }  // namespace emu

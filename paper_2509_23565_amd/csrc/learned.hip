@@ -1,0 +1,440 @@
+// Learned slice count: exponent-spread features of the update's operands,
+// a small MLP (16 -> 64 -> 64 -> 7, FP32, ReLU, softmax over s = 3..9) with
+// hand-written forward, backward and Adam kernels, tile labels produced by
+// the emulator itself, and an LU whose Schur updates use a per-tile slice
+// count (this form is not in the paper; its motivating observation is the
+// paper's: the digits an element loses depend on how far its exponent sits
+// below the largest one of its row or column, eqn (3)).
+//
+// Features of the 256 x 256 tile (I, J) of the update C = L21 U12, over the
+// nonzero elements of L21's rows I (exponent relative to the row's largest)
+// and of U12's columns J (relative to the column's largest): rho <= 0;
+// features = [min rho, max rho, mean rho, std rho, 12 fractions of -rho in
+// bins [0,7), [7,14), ..., [77, inf)].  All statistics are integer sums, so
+// the features are reproducible bit for bit.
+#include "common.h"
+
+#include <cmath>
+#include <vector>
+
+namespace emu {
+
+constexpr int FT = 256;             // feature tile edge
+constexpr int NBIN = 12;
+constexpr int NFEAT = 16;
+constexpr int H = 64;
+constexpr int NCLS = 7;             // s = 3..9
+constexpr int NPARAM = H * NFEAT + H + H * H + H + NCLS * H + NCLS;   // 5703
+// parameter layout: W1[H][NFEAT] b1[H] W2[H][H] b2[H] W3[NCLS][H] b3[NCLS]
+constexpr int P_W1 = 0, P_B1 = P_W1 + H * NFEAT, P_W2 = P_B1 + H, P_B2 = P_W2 + H * H,
+              P_W3 = P_B2 + H, P_B3 = P_W3 + NCLS * H;
+
+struct Stat {            // integer statistics of rho over one line block
+    long long cnt, sum, sumsq;
+    int mn, mx;
+    int hist[NBIN];
+};
+
+__device__ __forceinline__ int fexp(double x) {   // frexp exponent (x != 0, finite)
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    int eb = (int)((b >> 52) & 0x7ff);
+    unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
+    if (eb == 0) return (63 - __clzll((long long)fr)) - 1073;
+    return eb - 1022;
+}
+
+__device__ __forceinline__ bool usable(double x) { return x != 0.0 && isfinite(x); }
+
+// Statistics of one block of up to 256 lines of an operand.  by_rows: lines
+// are rows of X (rows x k), else columns of X (k x cols).  One thread per line.
+__global__ __launch_bounds__(FT) void k_feat_lines(const double *__restrict__ X, long long ldx,
+                                                   int lines, int k, int by_rows,
+                                                   Stat *__restrict__ out) {
+    __shared__ long long s_cnt, s_sum, s_sq;
+    __shared__ int s_mn, s_mx, s_hist[NBIN];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        s_cnt = 0;
+        s_sum = 0;
+        s_sq = 0;
+        s_mn = INT_MAX;
+        s_mx = INT_MIN;
+    }
+    if (t < NBIN) s_hist[t] = 0;
+    __syncthreads();
+    const int line = blockIdx.x * FT + t;
+    long long cnt = 0, sum = 0, sq = 0;
+    int mn = INT_MAX, mx = INT_MIN;
+    int hist[NBIN];
+#pragma unroll
+    for (int b = 0; b < NBIN; ++b) hist[b] = 0;
+    if (line < lines) {
+        int e = INT_MIN;
+        for (int kk = 0; kk < k; ++kk) {
+            const double x = by_rows ? X[line + (long long)kk * ldx] : X[kk + (long long)line * ldx];
+            if (usable(x)) e = max(e, fexp(x));
+        }
+        for (int kk = 0; kk < k; ++kk) {
+            const double x = by_rows ? X[line + (long long)kk * ldx] : X[kk + (long long)line * ldx];
+            if (!usable(x)) continue;
+            const int rho = fexp(x) - e;
+            ++cnt;
+            sum += rho;
+            sq += (long long)rho * rho;
+            mn = min(mn, rho);
+            mx = max(mx, rho);
+            const int bin = min(NBIN - 1, (-rho) / 7);
+#pragma unroll
+            for (int b = 0; b < NBIN; ++b)
+                if (b == bin) ++hist[b];
+        }
+    }
+    atomicAdd((unsigned long long *)&s_cnt, (unsigned long long)cnt);
+    atomicAdd((unsigned long long *)&s_sum, (unsigned long long)sum);
+    atomicAdd((unsigned long long *)&s_sq, (unsigned long long)sq);
+    atomicMin(&s_mn, mn);
+    atomicMax(&s_mx, mx);
+#pragma unroll
+    for (int b = 0; b < NBIN; ++b)
+        if (hist[b]) atomicAdd(&s_hist[b], hist[b]);
+    __syncthreads();
+    if (t == 0) {
+        Stat &o = out[blockIdx.x];
+        o.cnt = s_cnt;
+        o.sum = s_sum;
+        o.sumsq = s_sq;
+        o.mn = s_mn;
+        o.mx = s_mx;
+        for (int b = 0; b < NBIN; ++b) o.hist[b] = s_hist[b];
+    }
+}
+
+// Tile (I, J) features from row block I of L21 and column block J of U12.
+__global__ void k_feat_tiles(const Stat *__restrict__ rs, const Stat *__restrict__ cs, int tiles_m,
+                             int tiles_n, float *__restrict__ feat) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tiles_m * tiles_n) return;
+    const int I = idx % tiles_m, J = idx / tiles_m;
+    const Stat &a = rs[I], &b = cs[J];
+    const long long cnt = a.cnt + b.cnt;
+    float *f = feat + (long long)idx * NFEAT;
+    if (cnt == 0) {
+        for (int q = 0; q < NFEAT; ++q) f[q] = 0.0f;
+        return;
+    }
+    const double c = (double)cnt;
+    const double mean = (double)(a.sum + b.sum) / c;
+    const double var = (double)(a.sumsq + b.sumsq) / c - mean * mean;
+    f[0] = (float)min(a.mn, b.mn);
+    f[1] = (float)max(a.mx, b.mx);
+    f[2] = (float)mean;
+    f[3] = (float)sqrt(var > 0.0 ? var : 0.0);
+    for (int q = 0; q < NBIN; ++q) f[4 + q] = (float)((double)(a.hist[q] + b.hist[q]) / c);
+}
+
+// ------------------------------------------------------------------- MLP
+// Thread per sample, parameters in LDS.  Saves h1, h2 and the deltas
+// (feature-major, [unit][B]) for the gradient pass; loss[b] = -log p_label.
+__global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const float *__restrict__ params,
+                                                     const float *__restrict__ X,
+                                                     const int *__restrict__ label, int B,
+                                                     float *__restrict__ h1s,
+                                                     float *__restrict__ h2s,
+                                                     float *__restrict__ d1s,
+                                                     float *__restrict__ d2s,
+                                                     float *__restrict__ d3s,
+                                                     float *__restrict__ prob,
+                                                     float *__restrict__ loss) {
+    __shared__ float P[NPARAM];
+    for (int e = threadIdx.x; e < NPARAM; e += blockDim.x) P[e] = params[e];
+    __syncthreads();
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float x[NFEAT];
+#pragma unroll
+    for (int q = 0; q < NFEAT; ++q) x[q] = X[(long long)b * NFEAT + q];
+    float h1[H], h2[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        float a = P[P_B1 + i];
+#pragma unroll
+        for (int q = 0; q < NFEAT; ++q) a = fmaf(P[P_W1 + i * NFEAT + q], x[q], a);
+        h1[i] = a > 0.0f ? a : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        float a = P[P_B2 + i];
+#pragma unroll
+        for (int q = 0; q < H; ++q) a = fmaf(P[P_W2 + i * H + q], h1[q], a);
+        h2[i] = a > 0.0f ? a : 0.0f;
+    }
+    float z[NCLS];
+    float zmax = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+        float a = P[P_B3 + c];
+#pragma unroll
+        for (int q = 0; q < H; ++q) a = fmaf(P[P_W3 + c * H + q], h2[q], a);
+        z[c] = a;
+        zmax = fmaxf(zmax, a);
+    }
+    float den = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+        z[c] = expf(z[c] - zmax);
+        den += z[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+        z[c] = z[c] / den;
+        if (prob) prob[(long long)b * NCLS + c] = z[c];
+    }
+    if (!label) return;
+    const int y = label[b];
+    float py = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c)
+        if (c == y) py = z[c];
+    loss[b] = -logf(fmaxf(py, 1e-30f));
+    // backward: d3 = p - onehot; d2 = (W3^T d3) * relu'(h2); d1 = (W2^T d2) * relu'(h1)
+    float d3[NCLS];
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+        d3[c] = z[c] - (c == y ? 1.0f : 0.0f);
+        d3s[(long long)c * B + b] = d3[c];
+    }
+    float d2[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        float a = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NCLS; ++c) a = fmaf(P[P_W3 + c * H + q], d3[c], a);
+        d2[q] = h2[q] > 0.0f ? a : 0.0f;
+        d2s[(long long)q * B + b] = d2[q];
+        h2s[(long long)q * B + b] = h2[q];
+    }
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        float a = 0.0f;
+#pragma unroll
+        for (int i = 0; i < H; ++i) a = fmaf(P[P_W2 + i * H + q], d2[i], a);
+        d1s[(long long)q * B + b] = h1[q] > 0.0f ? a : 0.0f;
+        h1s[(long long)q * B + b] = h1[q];
+    }
+}
+
+// Gradient rows, one workgroup each: rows 0..63 of layer 1 (16 weights +
+// bias), 64..127 of layer 2 (64 + bias), 128..134 of layer 3 (64 + bias).
+// Sums over samples in a fixed order (per-thread strided, then a tree), and
+// the mean over the batch.
+__global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ X,
+                                                  const float *__restrict__ h1s,
+                                                  const float *__restrict__ h2s,
+                                                  const float *__restrict__ d1s,
+                                                  const float *__restrict__ d2s,
+                                                  const float *__restrict__ d3s, int B,
+                                                  float *__restrict__ grad) {
+    __shared__ float red[256];
+    const int row = blockIdx.x;
+    const float *delta;
+    const float *inp;          // [fan_in][B] (layer 1: X is [B][16])
+    int fan_in, w_off, b_off, r;
+    if (row < H) {
+        r = row;
+        delta = d1s + (long long)r * B;
+        inp = nullptr;
+        fan_in = NFEAT;
+        w_off = P_W1 + r * NFEAT;
+        b_off = P_B1 + r;
+    } else if (row < 2 * H) {
+        r = row - H;
+        delta = d2s + (long long)r * B;
+        inp = h1s;
+        fan_in = H;
+        w_off = P_W2 + r * H;
+        b_off = P_B2 + r;
+    } else {
+        r = row - 2 * H;
+        delta = d3s + (long long)r * B;
+        inp = h2s;
+        fan_in = H;
+        w_off = P_W3 + r * H;
+        b_off = P_B3 + r;
+    }
+    const float invB = 1.0f / (float)B;
+    for (int j = -1; j < fan_in; ++j) {          // j = -1: the bias
+        float acc = 0.0f;
+        for (int b = threadIdx.x; b < B; b += blockDim.x) {
+            float in = 1.0f;
+            if (j >= 0) in = inp ? inp[(long long)j * B + b] : X[(long long)b * NFEAT + j];
+            acc = fmaf(delta[b], in, acc);
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) grad[j < 0 ? b_off : w_off + j] = red[0] * invB;
+        __syncthreads();
+    }
+}
+
+__global__ void k_adam(float *__restrict__ params, const float *__restrict__ grad,
+                       float *__restrict__ m, float *__restrict__ v, int count, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// s per sample: smallest class whose cumulative probability reaches conf.
+__global__ void k_decode(const float *__restrict__ prob, int B, float conf, int *__restrict__ s) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float acc = 0.0f;
+    int c = 0;
+    for (; c < NCLS - 1; ++c) {
+        acc += prob[(long long)b * NCLS + c];
+        if (acc >= conf) break;
+    }
+    s[b] = 3 + c;
+}
+
+// ---------------------------------------------------------------- labels
+// Per 256 x 256 tile: sum of squares of X_s - X_ref and of X_ref (FP64, fixed
+// order); label = smallest s in [s_lo, s_hi] with rel. error <= tau.
+__global__ __launch_bounds__(256) void k_tile_err(const double *__restrict__ Xs,
+                                                  const double *__restrict__ Xr, long long ld,
+                                                  int m, int n, int tiles_m,
+                                                  double *__restrict__ err2,
+                                                  double *__restrict__ ref2) {
+    __shared__ double re[256], rr[256];
+    const int I = blockIdx.x % tiles_m, J = blockIdx.x / tiles_m;
+    const int i0 = I * FT, j0 = J * FT;
+    double e = 0.0, r = 0.0;
+    const int i = i0 + threadIdx.x;
+    if (i < m)
+        for (int j = j0; j < min(n, j0 + FT); ++j) {
+            const double a = Xs[i + (long long)j * ld], c = Xr[i + (long long)j * ld];
+            e += (a - c) * (a - c);
+            r += c * c;
+        }
+    re[threadIdx.x] = e;
+    rr[threadIdx.x] = r;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            re[threadIdx.x] += re[threadIdx.x + s];
+            rr[threadIdx.x] += rr[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        err2[blockIdx.x] = re[0];
+        ref2[blockIdx.x] = rr[0];
+    }
+}
+
+__global__ void k_tile_label(const double *__restrict__ err2, const double *__restrict__ ref2,
+                             int ntiles, int s, double tau, int *__restrict__ label) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ntiles) return;
+    // walking s upward: the first s that passes keeps its label
+    if (label[q] < 0 && sqrt(err2[q]) <= tau * sqrt(ref2[q])) label[q] = s;
+}
+
+// ------------------------------------------------------------- launchers
+int learned_nparam() { return NPARAM; }
+
+int launch_features(const double *L21, long long ldl, const double *U12, long long ldu, int m,
+                    int n, int k, float *feat, void *stat_ws, hipStream_t st) {
+    const int tm = (m + FT - 1) / FT, tn = (n + FT - 1) / FT;
+    Stat *rs = static_cast<Stat *>(stat_ws);
+    Stat *cs = rs + tm;
+    hipLaunchKernelGGL(k_feat_lines, dim3(tm), dim3(FT), 0, st, L21, ldl, m, k, 1, rs);
+    hipLaunchKernelGGL(k_feat_lines, dim3(tn), dim3(FT), 0, st, U12, ldu, n, k, 0, cs);
+    hipLaunchKernelGGL(k_feat_tiles, dim3((tm * tn + 255) / 256), dim3(256), 0, st, rs, cs, tm,
+                       tn, feat);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+size_t features_ws_bytes(int m, int n) {
+    return sizeof(Stat) * (size_t)((m + FT - 1) / FT + (n + FT - 1) / FT);
+}
+
+size_t mlp_train_ws_bytes(int B) {
+    return sizeof(float) * (size_t)B * (4 * H + NCLS + NCLS + 1) + sizeof(float) * NPARAM;
+}
+
+int launch_mlp_train_step(float *params, const float *X, const int *label, int B, float *m,
+                          float *v, int step, float lr, void *ws, float *loss_out,
+                          hipStream_t st) {
+    float *f = static_cast<float *>(ws);
+    float *h1 = f, *h2 = h1 + (size_t)H * B, *d1 = h2 + (size_t)H * B, *d2 = d1 + (size_t)H * B;
+    float *d3 = d2 + (size_t)H * B, *prob = d3 + (size_t)NCLS * B, *loss = prob + (size_t)NCLS * B;
+    float *grad = loss + B;
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((B + 255) / 256), dim3(256), 0, st, params, X, label,
+                       B, h1, h2, d1, d2, d3, prob, loss);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(2 * H + NCLS), dim3(256), 0, st, X, h1, h2, d1, d2, d3,
+                       B, grad);
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, params, grad, m, v,
+                       NPARAM, lr, b1, b2, 1e-8f, c1, c2);
+    if (loss_out) EMU_TRY_HIP(hipMemcpyAsync(loss_out, loss, sizeof(float) * B,
+                                             hipMemcpyDeviceToDevice, st));
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_mlp_grad_only(const float *params, const float *X, const int *label, int B,
+                         float *grad_out, void *ws, hipStream_t st) {
+    float *f = static_cast<float *>(ws);
+    float *h1 = f, *h2 = h1 + (size_t)H * B, *d1 = h2 + (size_t)H * B, *d2 = d1 + (size_t)H * B;
+    float *d3 = d2 + (size_t)H * B, *prob = d3 + (size_t)NCLS * B, *loss = prob + (size_t)NCLS * B;
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((B + 255) / 256), dim3(256), 0, st, params, X, label,
+                       B, h1, h2, d1, d2, d3, prob, loss);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(2 * H + NCLS), dim3(256), 0, st, X, h1, h2, d1, d2, d3,
+                       B, grad_out);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_mlp_infer(const float *params, const float *X, int B, float *prob, int *s_out,
+                     float conf, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((B + 255) / 256), dim3(256), 0, st, params, X,
+                       (const int *)nullptr, B, (float *)nullptr, (float *)nullptr,
+                       (float *)nullptr, (float *)nullptr, (float *)nullptr, prob,
+                       (float *)nullptr);
+    if (s_out)
+        hipLaunchKernelGGL(k_decode, dim3((B + 255) / 256), dim3(256), 0, st, prob, B, conf,
+                           s_out);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_tile_err(const double *Xs, const double *Xr, long long ld, int m, int n,
+                    double *err2, double *ref2, hipStream_t st) {
+    const int tm = (m + FT - 1) / FT, tn = (n + FT - 1) / FT;
+    hipLaunchKernelGGL(k_tile_err, dim3(tm * tn), dim3(256), 0, st, Xs, Xr, ld, m, n, tm, err2,
+                       ref2);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_tile_label(const double *err2, const double *ref2, int ntiles, int s, double tau,
+                      int *label, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_label, dim3((ntiles + 255) / 256), dim3(256), 0, st, err2, ref2,
+                       ntiles, s, tau, label);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+}  // namespace emu
