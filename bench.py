@@ -15,7 +15,10 @@ Printed on one JSON line, beside value: the slice-product kernel's roofline
 dense INT8 peak), the CPU oracle timed on a bounded sample of the same
 product (and the sampled block checked bit for bit), the normwise error of
 that block against a double-double reference, native FP64 DGEMM and LU
-(torch / ROCm libraries) on the same GPU, and the plain-method LU solve.
+(torch / ROCm libraries) on the same GPU, and the LU solves: the plain
+method (n = 1024, 7 slices), the precision form (n = 8192, reduced slices
+plus FP64 refinement to a backward error of 1e-15, against native FP64 with
+and without refinement) and the batched form (2000 uneven systems).
 """
 from __future__ import annotations
 
@@ -43,6 +46,165 @@ def pairs(s, t):
     return sum(1 for i in range(1, s + 1) for j in range(1, s + 1) if i + j <= t)
 
 
+def _time(torch, fn, reps=3):
+    """Median wall time (ms) of fn() on the current stream, after one warmup."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def _native_solve(torch, At, bt):
+    LU, piv = torch.linalg.lu_factor(At)
+    return torch.linalg.lu_solve(LU, piv, bt)
+
+
+def _native_refined(torch, At, bt, tol, maxiter=5):
+    """Native FP64 LU + FP64 refinement to the same backward-error target."""
+    LU, piv = torch.linalg.lu_factor(At)
+    x = torch.linalg.lu_solve(LU, piv, bt)
+    nA = At.abs().sum(dim=1).max()
+    for _ in range(maxiter):
+        r = bt - At @ x
+        eta = (r.abs().max() / (nA * x.abs().max() + bt.abs().max())).item()
+        if eta <= tol:
+            break
+        x = x + torch.linalg.lu_solve(LU, piv, r)
+    return x
+
+
+def bench_solvers(args, emu, torch, matgen):
+    """Plain-method LU, precision form and batched form, each next to native
+    FP64 on the same GPU; backward errors from the oracle's double-double
+    residual when the CPU leg is enabled."""
+    out = {}
+    import oracle
+    tol = 1e-15
+    # plain method, small: n = 1024, U(-1,1), 1 RHS, nb = 64, s = 7, seed 0
+    nl = 1024
+    Al = matgen.uniform(nl, nl, seed=0, substream=0)
+    bl = matgen.uniform(nl, 1, seed=0, substream=1)
+    Ag, bg = emu.colmajor(Al), emu.colmajor(bl)
+
+    def plain():
+        LU = Ag.clone()
+        x = bg.clone()
+        ipiv, info = emu.dgetrf(LU, nb=64, nslices=7)
+        emu.dgetrs(LU, ipiv, x)
+        return x
+    t_plain = _time(torch, plain)
+    x = plain()
+    X = emu.dgesv_ir(Ag, bg, nb=64, nslices=7, tol=tol)
+
+    def ir():
+        return emu.dgesv_ir(Ag, bg, nb=64, nslices=7, tol=tol)
+    t_ir = _time(torch, ir)
+    At, bt = torch.as_tensor(Al, device="cuda"), torch.as_tensor(bl, device="cuda")
+    t_nat = _time(torch, lambda: _native_solve(torch, At, bt))
+    xn = _native_solve(torch, At, bt)
+    out["plain_n1024"] = {
+        "workload": "n=1024 U(-1,1), 1 RHS, nb=64, s=7, seed 0",
+        "emulated_ms": round(t_plain, 3),
+        "eta": oracle.backward_error(Al, x.cpu().numpy(), bl),
+        "emulated_ir_ms": round(t_ir, 3), "ir_iters": X[1]["iters"],
+        "ir_eta": oracle.backward_error(Al, X[0].cpu().numpy(), bl),
+        "native_ms": round(t_nat, 3),
+        "native_eta": oracle.backward_error(Al, xn.cpu().numpy(), bl),
+    }
+    log(f"plain n=1024: emu {t_plain:.2f} ms, emu+IR {t_ir:.2f} ms, native {t_nat:.2f} ms")
+
+    # precision form: n = lu_n, phi = 1 entries, diagonal scaling for kappa,
+    # reduced slices + FP64 refinement to 1e-15, vs native (+ refinement)
+    if args.lu_n > 0:
+        n = args.lu_n
+        res = []
+        for kappa, s_lo, nb in ((1e2, 3, 256), (1e6, 4, 256), (1e10, 5, 256)):
+            A = matgen.kappa_matrix(n, 1.0, kappa, seed=0, variant="scaled")
+            b = matgen.uniform(n, 1, seed=0, substream=1)
+            Ag2, bg2 = emu.colmajor(A), emu.colmajor(b)
+            t_e = _time(torch, lambda: emu.dgesv_ir(Ag2, bg2, nb=nb, nslices=s_lo, tol=tol),
+                        reps=2)
+            X, inf = emu.dgesv_ir(Ag2, bg2, nb=nb, nslices=s_lo, tol=tol)
+            At2, bt2 = Ag2.contiguous(), bg2.contiguous()
+            t_n = _time(torch, lambda: _native_solve(torch, At2, bt2), reps=2)
+            t_nr = _time(torch, lambda: _native_refined(torch, At2, bt2, tol), reps=2)
+            xn = _native_solve(torch, At2, bt2)
+            xr = _native_refined(torch, At2, bt2, tol)
+            entry = {"kappa": kappa, "nslices": s_lo, "nb": nb,
+                     "emulated_ir_ms": round(t_e, 2), "iters": inf["iters"],
+                     "s_final": inf["s_final"], "berr_fp64": inf["berr"],
+                     "native_ms": round(t_n, 2), "native_refined_ms": round(t_nr, 2),
+                     "speedup_vs_native_refined": round(t_nr / t_e, 3)}
+            if not args.no_cpu:
+                entry["eta_dd"] = oracle.backward_error(A, X.cpu().numpy(), b)
+                entry["native_eta_dd"] = oracle.backward_error(A, xn.cpu().numpy(), b)
+                entry["native_refined_eta_dd"] = oracle.backward_error(A, xr.cpu().numpy(), b)
+            res.append(entry)
+            log(f"precision n={n} kappa={kappa:.0e} s={s_lo}: emu+IR {t_e:.1f} ms "
+                f"({inf['iters']} steps), native {t_n:.1f} ms, native+IR {t_nr:.1f} ms")
+            del Ag2, bg2, At2, bt2
+            torch.cuda.empty_cache()
+        out["precision_form"] = {"n": n, "workload": "A = D_r (G + sigma I) D_c, G phi=1 "
+                                 "entries, log-spaced diagonal scalings, 1 RHS U(-1,1), "
+                                 "tol 1e-15", "runs": res}
+
+    # batched form: count systems, n ~ U{64..1024}, phi ~ U(0,4), 1-8 RHS
+    if args.batch_count > 0:
+        specs = matgen.batched_specs(args.batch_count, seed=0)
+        As = [emu.colmajor(matgen.phi_matrix(n, n, phi, seed=0, substream=1000 + i))
+              for i, (n, phi, r) in enumerate(specs)]
+        Bs = [emu.colmajor(matgen.uniform(n, r, seed=0, substream=5000 + i))
+              for i, (n, phi, r) in enumerate(specs)]
+        s_b = 7
+        Aw = [a.clone() for a in As]
+        Bw = [b.clone() for b in Bs]
+
+        def batched():
+            for a, a0 in zip(Aw, As):
+                a.copy_(a0)
+            for b, b0 in zip(Bw, Bs):
+                b.copy_(b0)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            emu.dgesv_batched(Aw, Bw, nb=32, nslices=s_b)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1)
+        batched()                          # builds and caches the graph
+        tb = float(np.median([batched() for _ in range(3)]))
+        flops = sum(2.0 / 3.0 * n ** 3 for n, _, _ in specs)
+
+        def native_loop():
+            for a, b in zip(As, Bs):
+                torch.linalg.solve(a, b)
+        t_nl = _time(torch, native_loop, reps=1)
+        entry = {"count": args.batch_count, "nslices": s_b, "nb": 32,
+                 "emulated_ms": round(tb, 2), "tflops_equiv": round(flops / tb / 1e9, 2),
+                 "native_looped_ms": round(t_nl, 2),
+                 "workload": "n ~ U{64..1024}, phi ~ U(0,4), nrhs ~ U{1..8}, seed 0"}
+        if not args.no_cpu:
+            worst = 0.0
+            for i in range(0, len(specs), max(1, len(specs) // 16)):
+                n, phi, r = specs[i]
+                A = matgen.phi_matrix(n, n, phi, seed=0, substream=1000 + i)
+                B = matgen.uniform(n, r, seed=0, substream=5000 + i)
+                worst = max(worst, oracle.backward_error(A, Bw[i].cpu().numpy(), B))
+            entry["max_eta_dd_sampled"] = worst
+        out["batched"] = entry
+        log(f"batched {args.batch_count} systems: {tb:.1f} ms, native looped {t_nl:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +218,11 @@ def main():
     ap.add_argument("--sample-cols", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-native", action="store_true", help="skip native FP64")
-    ap.add_argument("--no-lu", action="store_true", help="skip the LU solve")
+    ap.add_argument("--no-lu", action="store_true", help="skip the LU solves")
+    ap.add_argument("--lu-n", type=int, default=8192,
+                    help="size of the precision-form solve (0 skips it)")
+    ap.add_argument("--batch-count", type=int, default=2000,
+                    help="systems in the batched solve (0 skips it)")
     ap.add_argument("--sweep-s", type=str, default="",
                     help="comma-separated slice counts to time on the same inputs "
                          "(adds a 'sweep' list to the JSON line)")
@@ -265,52 +431,9 @@ def main():
     del Ag, Bg, Cg
     torch.cuda.empty_cache()
 
-    # ------------------------------------------------- plain-method LU solve
+    # ------------------------------------------------------------ solvers
     if not args.no_lu:
-        import oracle
-        nl = 1024
-        Al = matgen.uniform(nl, nl, seed=0, substream=0)
-        bl = matgen.uniform(nl, 1, seed=0, substream=1)
-        times = []
-        for rep in range(4):
-            Alg = emu.colmajor(Al)
-            xg = emu.colmajor(bl)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            ipiv, info = emu.dgetrf(Alg, nb=64, nslices=7)
-            emu.dgetrs(Alg, ipiv, xg)
-            e1.record()
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        x = xg.cpu().numpy()
-        eta = oracle.backward_error(Al, x, bl) if not args.no_cpu else None
-        # native FP64 LU on the same GPU
-        At = torch.as_tensor(Al, device="cuda")
-        bt = torch.as_tensor(bl, device="cuda")
-        nt = []
-        for rep in range(4):
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            LUt, pv = torch.linalg.lu_factor(At)
-            xt = torch.linalg.lu_solve(LUt, pv, bt)
-            e1.record()
-            torch.cuda.synchronize()
-            nt.append(e0.elapsed_time(e1))
-        eta_nat = oracle.backward_error(Al, xt.cpu().numpy(), bl) if not args.no_cpu else None
-        result["lu_solve"] = {
-            "workload": "n=1024 U(-1,1), 1 RHS, nb=64, s=7, seed 0",
-            "emulated_ms": round(float(np.median(times[1:])), 3),
-            "eta_inf": eta,
-            "native_ms": round(float(np.median(nt[1:])), 3),
-            "native_eta_inf": eta_nat,
-            "native_library": "torch.linalg.lu_factor/lu_solve float64",
-        }
-        log(f"LU n=1024: emulated {result['lu_solve']['emulated_ms']} ms eta={eta}, "
-            f"native {result['lu_solve']['native_ms']} ms")
+        result["lu_solve"] = bench_solvers(args, emu, torch, matgen)
 
     print(json.dumps(result), flush=True)
 

@@ -21,6 +21,15 @@ Parity status of each function (what pins it, in tests/test_oracle_pins.py):
   gesv_ir                       - the delivered solution's double-double
                                   backward error meets the tolerance; forced
                                   failures take the fallback
+  learned.features              - hand-computed statistics of small tiles,
+                                  invariance under power-of-two line scaling
+  learned.mlp_forward/grad      - zero weights give the uniform class
+                                  distribution; central finite differences
+  learned.adam_step             - first-step closed form (lr * sign(g))
+  learned.decode                - hand-built cumulative distributions
+  learned.tile_labels           - small-integer inputs are exact at s = 3
+  learned.getrf_tiles           - a constant slice map equals getrf
+(pins of the learned part: tests/test_learned_oracle.py)
 """
 from .emu import (  # noqa: F401
     DIGIT_BITS, EPS, line_exponents, slice_digits, slice_products, recombine,
