@@ -36,10 +36,34 @@ if ROOT not in sys.path:
 
 PEAK_INT8_OPS = 5.0e15     # MI355X dense INT8 MFMA, ops/s
 PEAK_HBM = 8.0e12          # MI355X HBM3E, bytes/s
+# HBM traffic of the slice-product kernel per launch, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE), valid only while the kernel source is
+# byte-identical to the one the counters were taken on
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_slicegemm_16384_s9_traffic.json")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2509_23565_amd", "csrc", "slicegemm.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(n, s, phi):
+    """HBM bytes per launch of the slice-product kernel from the committed
+    counter record, or None when there is none for this workload or the
+    kernel has changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+        with open(GEMM_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    if (rec.get("n"), rec.get("nslices"), rec.get("phi")) != (n, s, phi):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def pairs(s, t):
@@ -317,7 +341,7 @@ def main():
             "peak": PEAK_INT8_OPS / 1e12,
             "unit": "TFLOP/s",
             "frac": round(achieved / (PEAK_INT8_OPS / 1e12), 4),
-            "traffic": None,
+            "traffic": measured_traffic(n, s, phi),
             "avg_ms": round(gemm_avg, 4),
             "launches": gemm_cnt,
             "algorithmic_ops_per_launch": int8_ops,

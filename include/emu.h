@@ -56,6 +56,10 @@ extern "C" {
                                         largest slice count */
 
 #define EMU_STATUS_NONFINITE   1     /* an emulated GEMM met Inf/NaN input */
+#define EMU_STATUS_PANEL_WAIT  2     /* a multi-workgroup panel leaf (more than
+                                        2048 rows) gave up a grid-wide wait that
+                                        exceeded its bound; those LU factors are
+                                        invalid */
 
 #define EMU_MAX_SLICES         9     /* GPU slice-count range is 1..9 */
 
@@ -153,6 +157,11 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
  *   "ir_force_fail" (value >= 0): the next `value` convergence checks of
  *   emu_dgesv_ir on this thread count as failed, which exercises the
  *   fallback to more slices (a test hook; the checks still run).
+ *   "lu_lookahead" (0 or 1, default 1): emu_dgetrf (and the LU inside
+ *   emu_dgesv_ir) updates the columns right of the next panel on a
+ *   library-owned side stream of the device while that panel is factored;
+ *   the caller's stream waits for it, so the call stays ordered on the
+ *   caller's stream.  The factors are identical either way.
  * Returns -1 for an unknown key, -2 for an invalid value.
  */
 int emu_set_param(const char *key, long long value);

@@ -188,6 +188,18 @@ static int gemm_core(Device *dev, char *ws, hipStream_t stream, const GemmScratc
 static inline int imax1(int a) { return a > 1 ? a : 1; }
 
 static thread_local int g_ir_force_fail = 0;
+static thread_local int g_lu_lookahead = 1;
+
+// The device's side stream and its two events, created on first use.
+static int side_stream(Device *dev) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!dev->side) {
+        EMU_TRY_HIP(hipStreamCreateWithFlags(&dev->side, hipStreamNonBlocking));
+        EMU_TRY_HIP(hipEventCreateWithFlags(&dev->ev_go, hipEventDisableTiming));
+        EMU_TRY_HIP(hipEventCreateWithFlags(&dev->ev_done, hipEventDisableTiming));
+    }
+    return 0;
+}
 
 // Scratch of one blocked LU: the largest trailing update's GEMM scratch
 // (the first update; later ones are smaller), then the panel's buffers.
@@ -209,28 +221,65 @@ static size_t getrs_scratch_bytes(int n, int nrhs) {
 }
 
 // Right-looking blocked LU on reserved scratch `ws` (getrf_scratch_bytes).
+//
+// Look-ahead: after panel k is factored and its interchanges applied, the
+// columns of panel k + 1 are updated first; the update of every column to
+// the right of them is queued on the device's side stream, where it runs
+// while panel k + 1 is factored on the caller's stream, and the caller's
+// stream waits for it before panel k + 1's interchanges.  Each element
+// receives exactly the same operations as without look-ahead (exponents are
+// per row of L21 and per column of U12, so splitting the update by columns
+// changes no bit).  The two updates of a step never overlap, so they share
+// the GEMM scratch; the panel's scratch is separate.
 static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, double *A,
                       long long ld, int *ipiv, int *info, int nb, int s) {
     EMU_TRY(launch_fill_int(info, 0, 1, st));
     char *pws = ws + getrf_gemm_bytes(m, n, nb, s);
     const int mn = m < n ? m : n;
     const int t = s + 1;
+    const bool la = g_lu_lookahead != 0 && mn > nb;
+    if (la) EMU_TRY(side_stream(dev));
+    // TRSM + emulated GEMM of columns [c0, c1) by the panel at (j0, jb)
+    auto update = [&](int j0, int jb, int c0, int c1, hipStream_t sx) -> int {
+        if (c1 <= c0) return 0;
+        const int j1 = j0 + jb;
+        const double *Ajj = A + j0 + (long long)j0 * ld;
+        double *U12 = A + j0 + (long long)c0 * ld;
+        EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, c1 - c0, sx));
+        if (j1 < m) {
+            GemmScratch gs = gemm_scratch(m - j1, c1 - c0, jb, s, t);
+            EMU_TRY(gemm_core(dev, ws, sx, gs, m - j1, c1 - c0, jb, -1.0,
+                              A + j1 + (long long)j0 * ld, ld, U12, ld, 1.0,
+                              A + j1 + (long long)c0 * ld, ld, s, t, nullptr));
+        }
+        return 0;
+    };
+    auto panel = [&](int j0) -> int {
+        const int jb = nb < mn - j0 ? nb : mn - j0;
+        return launch_panel(A + j0 + (long long)j0 * ld, ld, m - j0, jb, ipiv + j0, j0, info,
+                            pws, dev->status, st);
+    };
+    if (mn > 0) EMU_TRY(panel(0));
     for (int j0 = 0; j0 < mn; j0 += nb) {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
-        double *Ajj = A + j0 + (long long)j0 * ld;
-        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, st));
         EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, st));
-        if (j1 < n) {
-            double *U12 = A + j0 + (long long)j1 * ld;
-            EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));
-            if (j1 < m) {
-                GemmScratch gs = gemm_scratch(m - j1, n - j1, jb, s, t);
-                EMU_TRY(gemm_core(dev, ws, st, gs, m - j1, n - j1, jb, -1.0,
-                                  A + j1 + (long long)j0 * ld, ld, U12, ld, 1.0,
-                                  A + j1 + (long long)j1 * ld, ld, s, t, nullptr));
-            }
+        const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
+        if (!la || jn == 0) {
+            EMU_TRY(update(j0, jb, j1, n, st));
+            if (jn > 0) EMU_TRY(panel(j1));
+            continue;
         }
+        const int j2 = j1 + jn;
+        EMU_TRY(update(j0, jb, j1, j2, st));
+        if (j2 < n) {
+            EMU_TRY_HIP(hipEventRecord(dev->ev_go, st));
+            EMU_TRY_HIP(hipStreamWaitEvent(dev->side, dev->ev_go, 0));
+            EMU_TRY(update(j0, jb, j2, n, dev->side));
+            EMU_TRY_HIP(hipEventRecord(dev->ev_done, dev->side));
+        }
+        EMU_TRY(panel(j1));
+        if (j2 < n) EMU_TRY_HIP(hipStreamWaitEvent(st, dev->ev_done, 0));
     }
     return 0;
 }
@@ -260,6 +309,9 @@ int emu_finalize(void) {
         EMU_TRY_HIP(hipDeviceSynchronize());
         if (d.ws) EMU_TRY_HIP(hipFree(d.ws));
         if (d.status) EMU_TRY_HIP(hipFree(d.status));
+        if (d.ev_go) EMU_TRY_HIP(hipEventDestroy(d.ev_go));
+        if (d.ev_done) EMU_TRY_HIP(hipEventDestroy(d.ev_done));
+        if (d.side) EMU_TRY_HIP(hipStreamDestroy(d.side));
         d = Device();
     }
     EMU_TRY_HIP(hipSetDevice(cur));
@@ -472,6 +524,11 @@ int emu_set_param(const char *key, long long value) {
     if (std::strcmp(key, "ir_force_fail") == 0) {
         if (value < 0) return -2;
         g_ir_force_fail = (int)value;
+        return 0;
+    }
+    if (std::strcmp(key, "lu_lookahead") == 0) {
+        if (value != 0 && value != 1) return -2;
+        g_lu_lookahead = (int)value;
         return 0;
     }
     set_error("emu_set_param: unknown key \"%s\"", key);
@@ -848,7 +905,7 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
         double *Ajj = A + j0 + (long long)j0 * ld;
-        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, st));
+        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, dev->status, st));
         EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, st));
         if (j1 >= n) continue;
         double *U12 = A + j0 + (long long)j1 * ld;

@@ -33,6 +33,9 @@ struct Device {
     int *status = nullptr;        // device word: OR of EMU_STATUS_* bits
     void *ws = nullptr;           // library scratch
     size_t ws_bytes = 0;
+    hipStream_t side = nullptr;   // LU look-ahead: trailing updates (default priority)
+    hipEvent_t ev_go = nullptr;   // main stream -> side stream
+    hipEvent_t ev_done = nullptr; // side stream -> main stream
 };
 
 // Current device's state (initialised on first use) and the thread's stream.
@@ -148,10 +151,11 @@ int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int 
 // FP64 LU pieces.
 int launch_fill_int(int *p, int v, int count, hipStream_t stream);
 // Panel factorization (recursive, see panel.hip) of the rows x jb block at
-// A (global row/column row0); ws: panel_scratch_bytes(rows) bytes.
+// A (global row/column row0); ws: panel_scratch_bytes(rows) bytes; status:
+// the device status word (EMU_STATUS_PANEL_WAIT on an aborted tall leaf).
 size_t panel_scratch_bytes(int rows);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
-                 int row0, int *info, char *ws, hipStream_t stream);
+                 int row0, int *info, char *ws, int *status, hipStream_t stream);
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
                  int ncols_right, const int *ipiv, int k1, int k2, int row0,
                  hipStream_t stream);

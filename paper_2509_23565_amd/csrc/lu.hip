@@ -16,7 +16,10 @@ namespace emu {
 // most 2 (k2 - k1) rows), then applied to columns [0, ncols_left) and
 // [col_right, col_right + ncols_right): every workgroup reads its columns'
 // touched rows into LDS and writes them back permuted, so the sequential
-// chain of swaps costs no memory round trips.
+// chain of swaps costs no memory round trips.  Consecutive threads take
+// consecutive touched rows of one column (the panel's rows are contiguous
+// there), not consecutive columns of one row, which lie a leading dimension
+// apart.
 constexpr int SW_MAX = 1024;          // interchanges per call
 constexpr int SW_TILE = 8192;         // doubles of LDS for the row tile
 
@@ -91,14 +94,14 @@ __global__ __launch_bounds__(256) void k_laswp_perm(double *__restrict__ A, long
     for (int cb = blockIdx.x * CW; cb < ncols; cb += gridDim.x * CW) {
         const int cw = min(CW, ncols - cb);
         for (int e = t; e < nslot * cw; e += blockDim.x) {
-            const int sl = e / cw, jj = e % cw;
+            const int sl = e % nslot, jj = e / nslot;   // down a column
             const int cidx = cb + jj;
             const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
             tile[e] = A[content[sl] + (long long)col * lda];
         }
         __syncthreads();
         for (int e = t; e < nslot * cw; e += blockDim.x) {
-            const int sl = e / cw, jj = e % cw;
+            const int sl = e % nslot, jj = e / nslot;   // down a column
             if (content[sl] == srow[sl]) continue;
             const int cidx = cb + jj;
             const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);

@@ -99,7 +99,12 @@ __global__ __launch_bounds__(256) void k_scan_cols(const double *__restrict__ X,
 
 // ---------------------------------------------------------------- slicing
 // One wave writes fragment block (lb, kb) of every plane.  Lane l handles
-// line lb*32 + l%32 and k = kb*32 + (l/32)*16 + 0..15.
+// line lb*32 + l%32 and k = kb*32 + (l/32)*16 + 0..15.  Columns of B
+// (ROWS = false) are first copied into a wave-private LDS tile with reads
+// that run down each column (16 lanes per 256-byte column segment), since
+// lanes reading 32 different columns directly would each touch their own
+// cache line 16 times.
+constexpr int SL_TILE_LD = 33;     // doubles per column of the LDS tile (padded)
 template <int S, bool ROWS>
 __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
                                                long long ldx, int lines, int k,
@@ -118,6 +123,22 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
     bool ok = line < lines && c != CODE_NONFINITE;
     int e = code_to_exp(c);
 
+    __shared__ double tile[ROWS ? 1 : 4][ROWS ? 1 : 32 * SL_TILE_LD];
+    if constexpr (!ROWS) {
+        double *tw = tile[(threadIdx.x >> 6) & 3];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int ecol = q * 2 + (lane >> 5);      // column within the block
+            const int ek = lane & 31;                  // k within the block
+            const int ln = lb * 32 + ecol, kx = kb * 32 + ek;
+            tw[ecol * SL_TILE_LD + ek] =
+                (ln < lines && kx < k) ? X[kx + (long long)ln * ldx] : 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
     unsigned int w[S][4];
 #pragma unroll
     for (int d = 0; d < S; ++d)
@@ -129,7 +150,10 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
         int kx = kbase + kk;
         double x = 0.0;
         if (ok && kx < k) {
-            x = ROWS ? X[line + (long long)kx * ldx] : X[kx + (long long)line * ldx];
+            if constexpr (ROWS)
+                x = X[line + (long long)kx * ldx];
+            else
+                x = tile[(threadIdx.x >> 6) & 3][(lane & 31) * SL_TILE_LD + (lane >> 5) * 16 + kk];
         }
         int neg;
         unsigned long long Z = digits_word(x, e, S, &neg);
@@ -181,8 +205,16 @@ int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
     EMU_TRY(launch_fill_int(code, CODE_ZERO, g.lines, stream));
     if (g.k > 0 && g.lines > 0) {
         if (by_rows) {
-            int kper = 256;
-            dim3 grid((g.lines + 255) / 256, (g.k + kper - 1) / kper);
+            // enough workgroups to cover the chip when the panel is narrow
+            // (an LU's L21 has k = nb): split k so that about 2048
+            // workgroups run, at least 8 columns each
+            const int gx = (g.lines + 255) / 256;
+            int gy = (2048 + gx - 1) / gx;
+            const int gy_max = (g.k + 7) / 8;
+            if (gy > gy_max) gy = gy_max;
+            if (gy < 1) gy = 1;
+            const int kper = (g.k + gy - 1) / gy;
+            dim3 grid(gx, (g.k + kper - 1) / kper);
             hipLaunchKernelGGL(k_scan_rows, grid, dim3(256), 0, stream, X, ldx,
                                g.lines, g.k, kper, code, status);
         } else {

@@ -225,6 +225,16 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
 #pragma unroll
         for (int j = 0; j < CF::WN; ++j) {
             const int nbase = (nb0 + wn * CF::WN + j) * 32 + 4 * (lane >> 5);
+            // all C reads of the block before any store, so the 16 loads are
+            // in flight together instead of one round trip per element
+            double cin[16];
+            if (MODE != 2) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int n = nbase + 8 * (r >> 2) + (r & 3);
+                    cin[r] = (p.beta != 0.0 && n < p.N) ? p.C[(size_t)n * p.ldc + m] : 0.0;
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int n = nbase + 8 * (r >> 2) + (r & 3);
@@ -251,7 +261,7 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
                     const double X = ldexp(Ssum, ea + eb);
                     double *pc = p.C + (size_t)n * p.ldc + m;
                     double out = (p.beta == 0.0) ? fma(p.alpha, X, 0.0)
-                                                 : fma(p.alpha, X, p.beta * *pc);
+                                                 : fma(p.alpha, X, p.beta * cin[r]);
                     if (badA || badB) out = __builtin_nan("");
                     *pc = out;
                 }

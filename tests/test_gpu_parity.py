@@ -194,15 +194,35 @@ def test_full_slice_count_normwise_error(phi):
                                       (300, 200, 64, 7), (200, 300, 32, 9),
                                       (257, 257, 128, 3), (2600, 300, 64, 5),
                                       (2300, 2300, 128, 4), (4100, 96, 96, 3),
-                                      (700, 700, 200, 6)])
+                                      (700, 700, 200, 6), (9000, 40, 32, 3),
+                                      (4096, 48, 48, 3)])
 def test_getrf_bit_exact(m, n, nb, s):
+    # tall cases run the multi-workgroup panel leaf (more than 2048 rows)
     A = matgen.phi_matrix(m, n, 1.0, seed=13)
     Ag = emu.colmajor(A)
+    emu.status()
     ipiv, info = emu.dgetrf(Ag, nb=nb, nslices=s)
+    assert emu.status() == 0       # in particular no aborted panel wait
     LU, piv, inf = O.getrf(A, nb=nb, s=s)
     assert int(_host(info)[0]) == inf
     assert np.array_equal(_host(ipiv), piv)
     assert _same_bits(_host(Ag), LU)
+
+
+@pytest.mark.parametrize("m,n,nb,s", [(3000, 3000, 128, 3), (2500, 1800, 96, 6)])
+def test_getrf_lookahead_changes_no_bit(m, n, nb, s):
+    # the look-ahead (next panel beside the trailing update on a side
+    # stream) against the plain step order, which the oracle tests cover
+    A = emu.colmajor(matgen.phi_matrix(m, n, 2.0, seed=17))
+    A0 = A.clone()
+    try:
+        emu.set_param("lu_lookahead", 0)
+        ip0, inf0 = emu.dgetrf(A0, nb=nb, nslices=s)
+    finally:
+        emu.set_param("lu_lookahead", 1)
+    ip1, inf1 = emu.dgetrf(A, nb=nb, nslices=s)
+    assert torch.equal(ip0, ip1) and torch.equal(inf0, inf1)
+    assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
 
 
 def test_lu_solve_small_config_bit_exact_and_backward_error():
