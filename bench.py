@@ -253,6 +253,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
+    ap.add_argument("--lu-trace", type=str, default="",
+                    help="N,NB,S: only factor one N x N phi=1 matrix twice with emu_dgetrf "
+                         "(block NB, S slices) and exit, for kernel traces of the LU")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -273,6 +276,14 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
         del src, dst
+    if args.lu_trace:
+        ln, lnb, ls = (int(v) for v in args.lu_trace.split(","))
+        Al = emu.colmajor(matgen.phi_matrix(ln, ln, 1.0, seed=args.seed))
+        for _ in range(2):
+            emu.dgetrf(Al.clone(), nb=lnb, nslices=ls)
+        torch.cuda.synchronize()
+        print("done", flush=True)
+        return
     n, s, phi = args.n, args.s, args.phi
     t = s + 1
     P = pairs(s, t)
