@@ -43,12 +43,14 @@ constexpr int LF_MAX_G = 32;                   // workgroups of one leaf (65536 
 constexpr int LF_SPIN_LIMIT = 1 << 20;         // polls of one grid-wide wait
 
 // Cross-workgroup exchange of a multi-workgroup leaf (global scratch).
+// Per column and workgroup one record: [0] best |value|, [1] its row (as
+// an integer), [4..19] a copy of that row, [20..35] a copy of row c (only
+// workgroup 0, which owns it); the record is published by writing its
+// sequence number after it.  Double-buffered by column parity.
+constexpr int REC = 36;
 struct LeafX {
-    double *val;        // [2][LF_MAX_G] best |value| per workgroup
-    int *idx;           // [2][LF_MAX_G] its row
-    double *row;        // [2][LF_MAX_G][LEAF_W] a copy of that row
-    double *rowc;       // [2][LEAF_W] a copy of row c
-    unsigned *count;    // arrivals; zero before the launch
+    double *rec;        // [2][LF_MAX_G][REC]
+    unsigned *seq;      // [2][LF_MAX_G] sequence number of each record
     int *abort;         // set by a workgroup whose wait exceeded the bound
     int *status;        // device status word (EMU_STATUS_PANEL_WAIT)
 };
@@ -83,16 +85,23 @@ __device__ __forceinline__ void st_relaxed(int *p, int v) {
 __device__ __forceinline__ int ld_relaxed(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned ld_relaxed(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 struct LeafLds {
     double val[2][LF_WAVES];
     int idx[2][LF_WAVES];
     double row[2][LF_WAVES][LEAF_W];
     double xrow[2][LEAF_W];
-    double ur[2][LEAF_W];
+    double grow[2][LF_MAX_G][LEAF_W];   // multi-workgroup: every record's row
     double xr[2][LEAF_W];
     int p[2];
     int abort;
+    int piv[LEAF_W];          // pivot row (leaf coordinates) of each column
+    int srow[2 * LEAF_W];     // panel-row interchanges: row of each slot
+    int ssrc[2 * LEAF_W];     // and the row whose old values it receives
+    int nslot;
 };
 
 // Column c of a leaf: pivot search, interchange, scaling, rank-1 update of
@@ -143,59 +152,80 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     } else {
         const int G = (int)gridDim.x;
         if (wid == 0) {
+            // publish this workgroup's record, then its sequence number
+            const unsigned expect = base + (unsigned)c + 1u;
+            double *mine = x.rec + ((long long)buf * LF_MAX_G + g) * REC;
             if (lane < LEAF_W) {
-                const double *src = L.row[buf][((wi - base_row) % LF_THREADS) / 64];
-                st_relaxed(x.row + ((long long)buf * LF_MAX_G + g) * LEAF_W + lane, src[lane]);
-                if (g == 0) st_relaxed(x.rowc + buf * LEAF_W + lane, L.xrow[buf][lane]);
+                st_relaxed(mine + 4 + lane, L.row[buf][((wi - base_row) % LF_THREADS) / 64][lane]);
+            } else if (lane < 2 * LEAF_W) {
+                if (g == 0) st_relaxed(mine + 20 + (lane - LEAF_W), L.xrow[buf][lane - LEAF_W]);
+            } else if (lane == 2 * LEAF_W) {
+                st_relaxed(mine, wv);
+            } else if (lane == 2 * LEAF_W + 1) {
+                st_relaxed(mine + 1, (double)wi);
             }
-            if (lane == 0) {
-                st_relaxed(x.val + buf * LF_MAX_G + g, wv);
-                st_relaxed(x.idx + buf * LF_MAX_G + g, wi);
-                // arrive, then wait for every workgroup of this column
-                __hip_atomic_fetch_add(x.count, 1u, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned target = base + (unsigned)G * (unsigned)(c + 1);
-                int spins = 0;
-                while (__hip_atomic_load(x.count, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(x.seq + buf * LF_MAX_G + g, expect, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            // wait until every workgroup's record of this column is out
+            bool ok = lane >= G;
+            int spins = 0;
+            for (;;) {
+                if (!ok) ok = ld_relaxed(x.seq + buf * LF_MAX_G + lane) == expect;
+                if (__ballot(!ok) == 0ull) break;
+                if ((++spins & 63) == 0) {
                     if (ld_relaxed(x.abort) != 0) {
-                        L.abort = 1;
+                        if (lane == 0) L.abort = 1;
                         break;
                     }
-                    if (++spins > LF_SPIN_LIMIT) {
-                        st_relaxed(x.abort, 1);
-                        __hip_atomic_fetch_or(x.status, EMU_STATUS_PANEL_WAIT,
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        L.abort = 1;
+                    if (spins > LF_SPIN_LIMIT) {
+                        if (lane == 0) {
+                            st_relaxed(x.abort, 1);
+                            __hip_atomic_fetch_or(x.status, EMU_STATUS_PANEL_WAIT,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            L.abort = 1;
+                        }
                         break;
                     }
-                    __builtin_amdgcn_s_sleep(1);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __builtin_amdgcn_s_sleep(1);
             }
-            // the grid's winner, its row and row c
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // every record at once: values and rows (no dependent second read)
+            const double *recs = x.rec + (long long)buf * LF_MAX_G * REC;
             const int l = lane & (LF_MAX_G - 1);
             double gv = -1.0;
             int gi = INT_MAX;
             if (l < G) {
-                gv = ld_relaxed(x.val + buf * LF_MAX_G + l);
-                gi = ld_relaxed(x.idx + buf * LF_MAX_G + l);
+                gv = ld_relaxed(recs + (long long)l * REC);
+                gi = (int)ld_relaxed(recs + (long long)l * REC + 1);
             }
+            double rv[LF_MAX_G * LEAF_W / 64];
+#pragma unroll
+            for (int q = 0; q < LF_MAX_G * LEAF_W / 64; ++q) {
+                const int e = lane + 64 * q, sl = e / LEAF_W, j = e % LEAF_W;
+                rv[q] = sl < G ? ld_relaxed(recs + (long long)sl * REC + 4 + j) : 0.0;
+            }
+            const double rc = lane < LEAF_W ? ld_relaxed(recs + 20 + lane) : 0.0;
             lanes_best<LF_MAX_G>(gv, gi);
-            const int gp = (gi >= 0 && gi < G * LF_ROWS) ? gi / LF_ROWS : 0;
-            if (lane < LEAF_W) {
-                L.ur[buf][lane] = ld_relaxed(x.row + ((long long)buf * LF_MAX_G + gp) * LEAF_W + lane);
-                L.xr[buf][lane] = ld_relaxed(x.rowc + buf * LEAF_W + lane);
+#pragma unroll
+            for (int q = 0; q < LF_MAX_G * LEAF_W / 64; ++q) {
+                const int e = lane + 64 * q, sl = e / LEAF_W, j = e % LEAF_W;
+                if (sl < G) L.grow[buf][sl][j] = rv[q];
             }
+            if (lane < LEAF_W) L.xr[buf][lane] = rc;
             if (lane == 0) L.p[buf] = gi;
         }
         __syncthreads();
         if (L.abort) return false;
         p = L.p[buf];
-        ur = L.ur[buf];
+        const int gp = (p >= 0 && p < G * LF_ROWS) ? p / LF_ROWS : 0;
+        ur = L.grow[buf][gp];
         xr = L.xr[buf];
     }
     const double piv = ur[c];
+    if (t == 0) L.piv[c] = p;
     if (g == 0 && t == 0) {
         ipiv[c] = grow0 + p + 1;
         if (piv == 0.0 && *info == 0) *info = grow0 + c + 1;
@@ -241,14 +271,94 @@ __device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L,
     }
 }
 
+// The leaf's interchanges applied to the other columns of its panel: ncl
+// columns left of the leaf (ending at P - lda) and ncr right of it (from
+// P + w lda), rows in leaf coordinates.  The w interchanges are composed
+// into one permutation of at most 2w rows by wave 0 (lane x = slot x);
+// then every workgroup moves its share of the columns, all reads of a round
+// before any write.  Called after the leaf's last column (L.piv complete).
+constexpr int SWAP_ROUND = 8;       // 32-column passes per read/write round
+__device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int ncr,
+                                 LeafLds &L, int g, int G) {
+    const int t = threadIdx.x, lane = t & 63;
+    __syncthreads();
+    if (t < 64) {
+        const int pk = lane < w ? L.piv[lane] : -1;
+        // lane k: is pk (a row below the leaf's top w) seen here first?
+        bool first = lane < w && pk >= w;
+        for (int k2 = 0; k2 < w; ++k2) {
+            const int pk2 = __builtin_amdgcn_readlane(pk, k2);
+            if (k2 < lane && pk2 == pk) first = false;
+        }
+        const unsigned long long fm = __ballot(first);
+        const int nslot = w + __popcll(fm);
+        const int myslot = w + __popcll(fm & ((1ull << lane) - 1ull));
+        int pslot = pk;                          // slot of row pk
+        int srow = lane < w ? lane : -1;         // row of slot `lane`
+        for (int k2 = 0; k2 < w; ++k2) {
+            if (!((fm >> k2) & 1ull)) continue;  // uniform
+            const int r = __builtin_amdgcn_readlane(pk, k2);
+            const int sl = __builtin_amdgcn_readlane(myslot, k2);
+            if (lane < w && pk == r) pslot = sl;
+            if (lane == sl) srow = r;
+        }
+        // the interchanges in order on the slot contents
+        int content = srow;
+        for (int k = 0; k < w; ++k) {
+            const int b = __builtin_amdgcn_readlane(pslot, k);
+            const int va = __builtin_amdgcn_readlane(content, k);
+            const int vb = __builtin_amdgcn_readlane(content, b);
+            if (lane == k) content = vb;
+            if (lane == b) content = va;
+        }
+        if (lane < 2 * LEAF_W) {
+            L.srow[lane] = srow;
+            L.ssrc[lane] = content;
+        }
+        if (lane == 0) L.nslot = nslot;
+    }
+    __syncthreads();
+    const int nslot = L.nslot;
+    const int x = t & 31, jj = t >> 5;           // slot, column within a 32-column pass
+    const int nc = ncl + ncr;
+    const int srow = x < nslot ? L.srow[x] : 0;
+    const int ssrc = x < nslot ? L.ssrc[x] : 0;
+    const bool moves = x < nslot && srow != ssrc;
+    for (int j0 = g * 32; j0 < nc; j0 += 32 * G * SWAP_ROUND) {
+        double vals[SWAP_ROUND];
+#pragma unroll
+        for (int r = 0; r < SWAP_ROUND; ++r) {
+            const int j = j0 + r * 32 * G + jj;
+            vals[r] = 0.0;
+            if (moves && j < nc) {
+                const double *col = j < ncl ? P + (long long)(j - ncl) * lda
+                                            : P + (long long)(w + j - ncl) * lda;
+                vals[r] = col[ssrc];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SWAP_ROUND; ++r) {
+            const int j = j0 + r * 32 * G + jj;
+            if (moves && j < nc) {
+                double *col = j < ncl ? P + (long long)(j - ncl) * lda
+                                      : P + (long long)(w + j - ncl) * lda;
+                col[srow] = vals[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // P: top-left of the leaf (global row grow0), rows x w, w <= 16, rows >= w.
 // Workgroup g owns rows [2048 g, 2048 g + 2048): thread t rows
 // 2048 g + t and 2048 g + t + 1024.  MULTI: launched cooperatively; the
-// arrival counter holds `base` at the launch (it only grows within a panel).
+// records of column c carry sequence number base + c + 1.
 template <bool MULTI>
 __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, long long lda,
                                                      int rows, int w, int *ipiv, int grow0,
-                                                     int *info, LeafX x, unsigned base) {
+                                                     int *info, LeafX x, unsigned base,
+                                                     int ncl, int ncr) {
     __shared__ LeafLds L;
     const int t = threadIdx.x;
     const int g = MULTI ? (int)blockIdx.x : 0;
@@ -271,6 +381,7 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
             for (int j = 0; j < LEAF_W; ++j)
                 if (j < w) P[i + (long long)j * lda] = v[q][j];
     }
+    if (ncl + ncr > 0) leaf_panel_swaps(P, lda, w, ncl, ncr, L, g, MULTI ? (int)gridDim.x : 1);
 }
 
 // --------------------------------------------- order-preserving FP64 tiles
@@ -339,50 +450,37 @@ static int gemm_seq(const double *A, long long lda, const double *B, long long l
 }
 
 // ---------------------------------------------------------- unit-lower TRSM
-// B (jb x ncols) <- L^-1 B for jb <= NB: one wave per 64 columns, a thread
-// per column with the column in registers, L in LDS; for k increasing,
-// b_i = b_i - l_ik b_k (i > k).  The column tile is staged through LDS so
-// that global reads and writes run down the columns (contiguous), not
-// across them (64 lanes a leading dimension apart).
-constexpr int TR_COLS = 64;
-template <int NB>
-__global__ __launch_bounds__(TR_COLS) void k_trsm_reg(const double *__restrict__ L,
-                                                      long long ldl, int jb,
-                                                      double *__restrict__ B, long long ldb,
-                                                      int ncols) {
-    __shared__ double Ls[NB * NB];
-    __shared__ double Bt[NB][TR_COLS + 1];
-    const int t = threadIdx.x;
-    const int col0 = blockIdx.x * TR_COLS;
-    const int nc = min(TR_COLS, ncols - col0);
-    for (int idx = t; idx < jb * jb; idx += TR_COLS) {
+// B (jb x ncols) <- L^-1 B for jb <= 64: one wave per column, lane i holding
+// b_i (the column is read and written contiguously); for k increasing, b_k
+// is broadcast from lane k and lanes i > k compute b_i = b_i - l_ik b_k.
+// L sits in LDS, column-major, so lane i reads l_ik without bank conflicts.
+constexpr int TR_NB = 64;
+constexpr int TR_WAVES = 4;
+__global__ __launch_bounds__(64 * TR_WAVES) void k_trsm_lanes(const double *__restrict__ L,
+                                                              long long ldl, int jb,
+                                                              double *__restrict__ B,
+                                                              long long ldb, int ncols) {
+    __shared__ double Ls[TR_NB * TR_NB];
+    for (int idx = threadIdx.x; idx < jb * jb; idx += blockDim.x) {
         const int i = idx % jb, k = idx / jb;
-        Ls[k * NB + i] = L[i + (long long)k * ldl];
-    }
-    for (int e = t; e < jb * nc; e += TR_COLS) {
-        const int i = e % jb, c = e / jb;
-        Bt[i][c] = B[i + (long long)(col0 + c) * ldb];
+        Ls[k * TR_NB + i] = L[i + (long long)k * ldl];
     }
     __syncthreads();
-    double b[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) b[i] = i < jb ? Bt[i][t] : 0.0;
-#pragma unroll
-    for (int k = 0; k < NB - 1; ++k) {
-        if (k < jb - 1) {
-            const double bk = b[k];
-#pragma unroll
-            for (int i = k + 1; i < NB; ++i)
-                if (i < jb) b[i] = b[i] - Ls[k * NB + i] * bk;
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * TR_WAVES;
+    for (int col = blockIdx.x * TR_WAVES + (threadIdx.x >> 6); col < ncols; col += nw) {
+        double *bc = B + (long long)col * ldb;
+        double b = lane < jb ? bc[lane] : 0.0;
+#pragma unroll 8
+        for (int k = 0; k < jb - 1; ++k) {
+            const long long bits = __double_as_longlong(b);
+            const int lo = __builtin_amdgcn_readlane((int)bits, k);
+            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), k);
+            const double bk = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+            const double l = Ls[k * TR_NB + lane];
+            if (lane > k) b = b - l * bk;
         }
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        if (i < jb) Bt[i][t] = b[i];
-    __syncthreads();
-    for (int e = t; e < jb * nc; e += TR_COLS) {
-        const int i = e % jb, c = e / jb;
-        B[i + (long long)(col0 + c) * ldb] = Bt[i][c];
+        if (lane < jb) bc[lane] = b;
     }
 }
 
@@ -390,19 +488,16 @@ __global__ __launch_bounds__(TR_COLS) void k_trsm_reg(const double *__restrict__
 int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B, long long ldb,
                      int ncols, hipStream_t stream) {
     if (ncols <= 0 || jb <= 1) return 0;
-    constexpr int D = 64;
+    constexpr int D = TR_NB;
+    int blocks = (ncols + TR_WAVES - 1) / TR_WAVES;
+    if (blocks > 1024) blocks = 1024;
     for (int k0 = 0; k0 < jb; k0 += D) {
         const int kb = jb - k0 < D ? jb - k0 : D;
-        dim3 grid((ncols + TR_COLS - 1) / TR_COLS);
         const double *Lkk = L + k0 + (long long)k0 * ldl;
         double *Bk = B + k0;
         if (kb > 1) {
-            if (kb <= 32)
-                hipLaunchKernelGGL(k_trsm_reg<32>, grid, dim3(TR_COLS), 0, stream, Lkk, ldl, kb,
-                                   Bk, ldb, ncols);
-            else
-                hipLaunchKernelGGL(k_trsm_reg<64>, grid, dim3(TR_COLS), 0, stream, Lkk, ldl, kb,
-                                   Bk, ldb, ncols);
+            hipLaunchKernelGGL(k_trsm_lanes, dim3(blocks), dim3(64 * TR_WAVES), 0, stream, Lkk,
+                               ldl, kb, Bk, ldb, ncols);
             EMU_TRY_HIP(hipGetLastError());
         }
         const int below = jb - (k0 + kb);
@@ -415,9 +510,8 @@ int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B, long lon
 
 // ------------------------------------------------------------ recursion
 static size_t leafx_bytes() {
-    return align256(2 * LF_MAX_G * sizeof(double)) + align256(2 * LF_MAX_G * sizeof(int)) +
-           align256(2 * LF_MAX_G * LEAF_W * sizeof(double)) +
-           align256(2 * LEAF_W * sizeof(double)) + align256(2 * sizeof(int));
+    return align256(2 * LF_MAX_G * REC * sizeof(double)) +
+           align256(2 * LF_MAX_G * sizeof(unsigned) + sizeof(int));
 }
 
 size_t panel_scratch_bytes(int rows) {
@@ -427,24 +521,16 @@ size_t panel_scratch_bytes(int rows) {
 
 static LeafX leaf_x(char *ws, int *status) {
     LeafX x;
-    char *p = ws;
-    x.val = reinterpret_cast<double *>(p);
-    p += align256(2 * LF_MAX_G * sizeof(double));
-    x.idx = reinterpret_cast<int *>(p);
-    p += align256(2 * LF_MAX_G * sizeof(int));
-    x.row = reinterpret_cast<double *>(p);
-    p += align256(2 * LF_MAX_G * LEAF_W * sizeof(double));
-    x.rowc = reinterpret_cast<double *>(p);
-    p += align256(2 * LEAF_W * sizeof(double));
-    x.count = reinterpret_cast<unsigned *>(p);
-    x.abort = reinterpret_cast<int *>(p) + 1;
+    x.rec = reinterpret_cast<double *>(ws);
+    x.seq = reinterpret_cast<unsigned *>(ws + align256(2 * LF_MAX_G * REC * sizeof(double)));
+    x.abort = reinterpret_cast<int *>(x.seq + 2 * LF_MAX_G);
     x.status = status;
     return x;
 }
 
-// One panel factorization: scratch, status word, and the arrivals the
-// multi-workgroup leaves of this panel have made so far (the counter is
-// zeroed once per panel).
+// One panel factorization: scratch, status word, and the columns the
+// multi-workgroup leaves of this panel have finished so far (record sequence
+// numbers continue from there; they are zeroed once per panel).
 struct PanelRun {
     char *ws;
     int *status;
@@ -452,11 +538,11 @@ struct PanelRun {
 };
 
 static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0, int *info,
-                PanelRun &pr, hipStream_t st) {
+                int ncl, int ncr, PanelRun &pr, hipStream_t st) {
     LeafX x = leaf_x(pr.ws, pr.status);
     if (rows <= LF_ROWS) {
         hipLaunchKernelGGL(k_leaf<false>, dim3(1), dim3(LF_THREADS), 0, st, P, lda, rows, w,
-                           ipiv, grow0, info, x, 0u);
+                           ipiv, grow0, info, x, 0u, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
         return 0;
     }
@@ -466,33 +552,32 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
         return EMU_ERR_UNSUPPORTED;
     }
     unsigned base = pr.arrivals;
-    void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base};
+    void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
     EMU_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_leaf<true>),
                                            dim3(G), dim3(LF_THREADS), args, 0, st));
-    pr.arrivals += (unsigned)G * (unsigned)w;
+    pr.arrivals += (unsigned)w;
     return 0;
 }
 
-// Factor columns [c0, c0 + w) of the panel whose top-left is A (global row
-// and column row0), rows [c0, m_rows) of it; ipiv/info as in getrf.
-static int panel_rec(double *A, long long lda, int m_rows, int c0, int w, int *ipiv, int row0,
-                     int *info, PanelRun &pr, hipStream_t st) {
+// Factor columns [c0, c0 + w) of the panel (pw columns) whose top-left is A
+// (global row and column row0), rows [c0, m_rows) of it; ipiv/info as in
+// getrf.  Every leaf applies its interchanges to all other columns of the
+// panel itself, so no separate interchange pass is needed here.
+static int panel_rec(double *A, long long lda, int m_rows, int pw, int c0, int w, int *ipiv,
+                     int row0, int *info, PanelRun &pr, hipStream_t st) {
     double *P = A + c0 + (long long)c0 * lda;
     if (w <= LEAF_W)
-        return leaf(P, lda, m_rows - c0, w, ipiv + c0, row0 + c0, info, pr, st);
+        return leaf(P, lda, m_rows - c0, w, ipiv + c0, row0 + c0, info, c0, pw - c0 - w, pr,
+                    st);
     int w1 = (w / 2) / LEAF_W * LEAF_W;
     if (w1 < LEAF_W) w1 = LEAF_W;
     const int w2 = w - w1;
-    EMU_TRY(panel_rec(A, lda, m_rows, c0, w1, ipiv, row0, info, pr, st));
-    // interchanges of the left part on the right part's rows
-    EMU_TRY(launch_laswp(A, lda, m_rows, 0, c0 + w1, w2, ipiv, c0, c0 + w1, row0, st));
+    EMU_TRY(panel_rec(A, lda, m_rows, pw, c0, w1, ipiv, row0, info, pr, st));
     // U of the right part's top, then the rest of the right part
     EMU_TRY(launch_trsm_llnu(P, lda, w1, P + (long long)w1 * lda, lda, w2, st));
     EMU_TRY(gemm_seq(P + w1, lda, P + (long long)w1 * lda, lda, P + w1 + (long long)w1 * lda,
                      lda, m_rows - c0 - w1, w2, w1, st));
-    EMU_TRY(panel_rec(A, lda, m_rows, c0 + w1, w2, ipiv, row0, info, pr, st));
-    // interchanges of the right part on the left part's rows
-    EMU_TRY(launch_laswp(A, lda, m_rows, 0, c0, w1, ipiv, c0 + w1, c0 + w, row0, st));
+    EMU_TRY(panel_rec(A, lda, m_rows, pw, c0 + w1, w2, ipiv, row0, info, pr, st));
     return 0;
 }
 
@@ -500,11 +585,12 @@ int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0
                  char *ws, int *status, hipStream_t stream) {
     PanelRun pr{ws, status, 0u};
     if (rows > LF_ROWS) {
-        // arrival counter and abort flag start at zero (a fill kernel, not a memset)
+        // sequence numbers and the abort flag start at zero (a fill kernel,
+        // not a memset)
         LeafX x = leaf_x(ws, status);
-        EMU_TRY(launch_fill_int(reinterpret_cast<int *>(x.count), 0, 2, stream));
+        EMU_TRY(launch_fill_int(reinterpret_cast<int *>(x.seq), 0, 2 * LF_MAX_G + 1, stream));
     }
-    return panel_rec(A, lda, rows, 0, jb, ipiv, row0, info, pr, stream);
+    return panel_rec(A, lda, rows, jb, 0, jb, ipiv, row0, info, pr, stream);
 }
 
 }  // namespace emu

@@ -179,26 +179,32 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
         for (int i = 0; i < CF::WM; ++i) {
 #pragma unroll
             for (int j = 0; j < CF::WN; ++j) {
-                // all B digits of this block stay in registers; A digits are
-                // streamed, most-used first (digit ii pairs with T - ii
-                // B digits), so each LDS read is covered by the MFMAs of the
-                // digit before it
-                v4i b[S];
-#pragma unroll
-                for (int d = 0; d < S; ++d)
-                    b[d] = *reinterpret_cast<const v4i *>(
-                        cur + (FRA + d * TN + wn * CF::WN + j) * FRAG_BYTES + lane * 16);
+                // A digits are streamed least significant first: digit ii
+                // pairs with B digits 1..min(S, T - ii), so with T = S + 1
+                // each step needs exactly one new B digit besides the next A
+                // digit, and the first MFMA waits for two fragments instead
+                // of S + 1 (all waves start a K step together after the
+                // barrier, and LDS serves their reads in order).  B digits
+                // stay in registers once read.
+                static_assert(T == S + 1 || T == 2 * S, "supported thresholds");
+                constexpr bool TRI = (T == S + 1);
                 const int8_t *pa = cur + (wm * CF::WM + i) * FRAG_BYTES + lane * 16;
-                v4i a = *reinterpret_cast<const v4i *>(pa);
-                // schedule: the B reads and the first A read, then for each A
-                // digit the read of the next one ahead of this digit's MFMAs
-                __builtin_amdgcn_sched_group_barrier(0x100, S + 1, 0);
+                const int8_t *pb = cur + (FRA + wn * CF::WN + j) * FRAG_BYTES + lane * 16;
+                v4i b[S];
+                v4i a = *reinterpret_cast<const v4i *>(pa + (S - 1) * TM * FRAG_BYTES);
 #pragma unroll
-                for (int ii = 1; ii <= S; ++ii) {
+                for (int d = 0; d < (TRI ? 1 : S); ++d)
+                    b[d] = *reinterpret_cast<const v4i *>(pb + d * TN * FRAG_BYTES);
+                __builtin_amdgcn_sched_group_barrier(0x100, TRI ? 2 : S + 1, 0);
+#pragma unroll
+                for (int ii = S; ii >= 1; --ii) {
                     v4i an = a;
-                    if (ii < S) {
-                        an = *reinterpret_cast<const v4i *>(pa + ii * TM * FRAG_BYTES);
-                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    if (ii > 1) {
+                        an = *reinterpret_cast<const v4i *>(pa + (ii - 2) * TM * FRAG_BYTES);
+                        if (TRI)
+                            b[S + 1 - ii] = *reinterpret_cast<const v4i *>(
+                                pb + (S + 1 - ii) * TN * FRAG_BYTES);
+                        __builtin_amdgcn_sched_group_barrier(0x100, TRI ? 2 : 1, 0);
                     }
 #pragma unroll
                     for (int jj = 1; jj <= S; ++jj)
