@@ -213,7 +213,8 @@ static size_t getrf_gemm_bytes(int m, int n, int nb, int s) {
 
 static size_t getrf_scratch_bytes(int m, int n, int nb, int s) {
     if (nb <= 0) nb = 64;
-    return getrf_gemm_bytes(m, n, nb, s) + panel_scratch_bytes(m);
+    return getrf_gemm_bytes(m, n, nb, s) + align256(panel_scratch_bytes(m)) +
+           laswp_plan_bytes(m);
 }
 
 static size_t getrs_scratch_bytes(int n, int nrhs) {
@@ -235,6 +236,7 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
                       long long ld, int *ipiv, int *info, int nb, int s) {
     EMU_TRY(launch_fill_int(info, 0, 1, st));
     char *pws = ws + getrf_gemm_bytes(m, n, nb, s);
+    int *plan = reinterpret_cast<int *>(pws + align256(panel_scratch_bytes(m)));
     const int mn = m < n ? m : n;
     const int t = s + 1;
     const bool la = g_lu_lookahead != 0 && mn > nb;
@@ -263,7 +265,7 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
     for (int j0 = 0; j0 < mn; j0 += nb) {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
-        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, st));
+        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
         const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
         if (!la || jn == 0) {
             EMU_TRY(update(j0, jb, j1, n, st));
@@ -886,6 +888,7 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     char *ws = static_cast<char *>(dev->ws);
     char *lws = ws + o_lu;
     char *pws = lws + getrf_gemm_bytes(m, n, nb, s_full);
+    int *plan = reinterpret_cast<int *>(pws + align256(panel_scratch_bytes(m)));
     float *feat = reinterpret_cast<float *>(ws + o_feat);
     float *prob = reinterpret_cast<float *>(ws + o_prob);
     int *smap = reinterpret_cast<int *>(ws + o_smap);
@@ -906,7 +909,7 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
         const int j1 = j0 + jb;
         double *Ajj = A + j0 + (long long)j0 * ld;
         EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, dev->status, st));
-        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, st));
+        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
         if (j1 >= n) continue;
         double *U12 = A + j0 + (long long)j1 * ld;
         EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));

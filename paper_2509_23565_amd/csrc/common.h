@@ -156,8 +156,11 @@ int launch_fill_int(int *p, int v, int count, hipStream_t stream);
 size_t panel_scratch_bytes(int rows);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
                  int row0, int *info, char *ws, int *status, hipStream_t stream);
+// Interchanges ipiv[k1..k2) on columns [0, ncols_left) and [col_right,
+// col_right + ncols_right); plan: laswp_plan_bytes(nrows) bytes of scratch.
+size_t laswp_plan_bytes(int nrows);
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
-                 int ncols_right, const int *ipiv, int k1, int k2, int row0,
+                 int ncols_right, const int *ipiv, int k1, int k2, int row0, int *plan,
                  hipStream_t stream);
 int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
                      long long ldb, int ncols, hipStream_t stream);

@@ -10,141 +10,199 @@
 
 namespace emu {
 
-// ---------------------------------------------------------------- laswp
-// The interchanges ipiv[k1..k2) (1-based global rows; A's first row is global
-// row row0) are composed into one permutation of the rows they touch (at
-// most 2 (k2 - k1) rows), then applied to columns [0, ncols_left) and
-// [col_right, col_right + ncols_right): every workgroup reads its columns'
-// touched rows into LDS and writes them back permuted, so the sequential
-// chain of swaps costs no memory round trips.  Consecutive threads take
-// consecutive touched rows of one column (the panel's rows are contiguous
-// there), not consecutive columns of one row, which lie a leading dimension
-// apart.
-constexpr int SW_MAX = 1024;          // interchanges per call
-constexpr int SW_TILE = 8192;         // doubles of LDS for the row tile
+// Orders the LDS / memory accesses of one wave's lanes around it.
+__device__ __forceinline__ void wave_sync_mem() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
-__global__ __launch_bounds__(256) void k_laswp_perm(double *__restrict__ A, long long lda,
-                                                    int nrows, int ncols_left, int col_right,
-                                                    int ncols_right,
-                                                    const int *__restrict__ ipiv, int k1,
-                                                    int k2, int row0) {
-    __shared__ int pr[SW_MAX];            // target row of interchange c (local)
-    __shared__ int pslot[SW_MAX];         // slot of that row
-    __shared__ int first[SW_MAX];         // 1 if the row first appears here (outside [k1,k2))
-    __shared__ int srow[2 * SW_MAX];      // row of each slot
-    __shared__ int content[2 * SW_MAX];   // source row of each slot after all swaps
-    __shared__ double tile[SW_TILE];
-    __shared__ int s_nslot;
-    const int t = threadIdx.x;
-    const int J = k2 - k1;
-    for (int c = t; c < J; c += blockDim.x) {
-        int pv = ipiv[k1 + c] - 1 - row0;
-        if (pv < k1 + c || pv >= nrows) pv = k1 + c;       // invalid: no interchange
-        pr[c] = pv;
-    }
-    __syncthreads();
-    // first appearance of each target row outside [k1, k2)
-    for (int c = t; c < J; c += blockDim.x) {
-        const int pv = pr[c];
-        int f = (pv >= k2) ? 1 : 0;
-        if (f)
-            for (int c2 = 0; c2 < c; ++c2)
-                if (pr[c2] == pv) {
-                    f = 0;
-                    break;
-                }
-        first[c] = f;
-    }
-    __syncthreads();
-    if (t == 0) {
-        int nx = 0;
-        for (int c = 0; c < J; ++c) {
-            srow[c] = k1 + c;
-            content[c] = k1 + c;
+// ------------------------------------------------- composed interchanges
+// A run of row interchanges (c <-> p_c, c increasing, p_c >= c) is
+// sequential by definition.  One wave composes it into a permutation pm of
+// the rows it touches, 32 interchanges at a time: the 32 interchanges of a
+// block touch at most 64 rows, which get one lane ("slot") each; the swaps
+// are replayed on the slot contents with lane broadcasts, and the block's
+// net effect is applied to pm in one gather/scatter.  pm[r] is the row
+// whose old contents end up in row r (rows relative to the run's first).
+// Pivot c is piv[c] - 1 - piv_base relative to that row; values outside
+// [c, R) mean no interchange.
+__device__ void compose_interchanges(int *pm, int R, int J, const int *__restrict__ piv,
+                                     int piv_base) {
+    const int lane = threadIdx.x & 63;
+    for (int k0 = 0; k0 < J; k0 += 32) {
+        const int w = J - k0 < 32 ? J - k0 : 32;
+        int pk = -1;                                 // pivot of k0 + lane, relative to k0
+        if (lane < w) {
+            pk = piv[k0 + lane] - 1 - piv_base - k0;
+            if (pk < lane || pk >= R - k0) pk = lane;
         }
-        for (int c = 0; c < J; ++c) {
-            const int pv = pr[c];
-            if (pv < k2) {
-                pslot[c] = pv - k1;
-            } else if (first[c]) {
-                pslot[c] = J + nx;
-                srow[J + nx] = pv;
-                content[J + nx] = pv;
-                ++nx;
-            } else {
-                for (int c2 = 0; c2 < c; ++c2)
-                    if (pr[c2] == pv) {
-                        pslot[c] = pslot[c2];
-                        break;
-                    }
+        bool first = lane < w && pk >= w;            // first use of a row below the block
+        for (int k2 = 0; k2 < w; ++k2) {
+            const int pk2 = __builtin_amdgcn_readlane(pk, k2);
+            if (k2 < lane && pk2 == pk) first = false;
+        }
+        const unsigned long long fm = __ballot(first);
+        const int nslot = w + __popcll(fm);
+        const int myslot = w + __popcll(fm & ((1ull << lane) - 1ull));
+        int pslot = pk;
+        int srow = lane < w ? lane : -1;
+        for (int k2 = 0; k2 < w; ++k2) {
+            if (!((fm >> k2) & 1ull)) continue;
+            const int r = __builtin_amdgcn_readlane(pk, k2);
+            const int sl = __builtin_amdgcn_readlane(myslot, k2);
+            if (lane < w && pk == r) pslot = sl;
+            if (lane == sl) srow = r;
+        }
+        int content = srow;
+        for (int k = 0; k < w; ++k) {
+            const int b = __builtin_amdgcn_readlane(pslot, k);
+            const int va = __builtin_amdgcn_readlane(content, k);
+            const int vb = __builtin_amdgcn_readlane(content, b);
+            if (lane == k) content = vb;
+            if (lane == b) content = va;
+        }
+        int v = 0;
+        if (lane < nslot) v = pm[k0 + content];
+        wave_sync_mem();
+        if (lane < nslot) pm[k0 + srow] = v;
+        wave_sync_mem();
+    }
+}
+
+constexpr int PERM_LDS_MAX = 32768;
+
+// ---------------------------------------------------------------- laswp
+// The interchanges ipiv[k1..k2) (1-based global rows; A's first row is
+// global row row0) are applied to columns [0, ncols_left) and
+// [col_right, col_right + ncols_right) of rows [k1, nrows).  A one-wave
+// kernel composes them (above) and lists the rows that change as a plan:
+// plan[0] = count, then each row (relative to A) and the row whose old
+// values it receives.  The apply kernel reads the plan and moves, for its
+// columns, every listed row's old value into place (all reads of a
+// workgroup's tile before any write; consecutive threads walk down a
+// column).
+constexpr int SW_MAX = 1024;                 // interchanges per call
+constexpr int SW_SLOTS = 2 * SW_MAX;         // rows a call can change
+constexpr int SW_TILE = 4096;                // elements per workgroup pass
+
+size_t laswp_plan_bytes(int nrows) {
+    return align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int)) +
+           (nrows > PERM_LDS_MAX ? align256((size_t)nrows * sizeof(int)) : 0);
+}
+
+__global__ __launch_bounds__(64) void k_swap_plan(const int *__restrict__ ipiv, int k1, int k2,
+                                                  int nrows, int row0, int *__restrict__ plan,
+                                                  int *__restrict__ gperm) {
+    __shared__ int lp[PERM_LDS_MAX];
+    const int lane = threadIdx.x;
+    const int R = nrows - k1;
+    int *pm = R <= PERM_LDS_MAX ? lp : gperm;
+    for (int r = lane; r < R; r += 64) pm[r] = r;
+    wave_sync_mem();
+    compose_interchanges(pm, R, k2 - k1, ipiv + k1, row0 + k1);
+    int count = 0;
+    for (int r0 = 0; r0 < R; r0 += 64) {
+        const int r = r0 + lane;
+        const int src = r < R ? pm[r] : r;
+        const bool ch = r < R && src != r;
+        const unsigned long long m = __ballot(ch);
+        if (ch) {
+            const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+            plan[1 + pos] = k1 + r;
+            plan[1 + SW_SLOTS + pos] = k1 + src;
+        }
+        count += __popcll(m);
+    }
+    if (lane == 0) plan[0] = count;
+}
+
+__global__ __launch_bounds__(256) void k_swap_apply(double *__restrict__ A, long long lda,
+                                                    int ncols_left, int col_right,
+                                                    int ncols_right, int cw,
+                                                    const int *__restrict__ plan) {
+    constexpr int PER = SW_TILE / 256;
+    __shared__ int srow[SW_SLOTS], ssrc[SW_SLOTS];
+    const int t = threadIdx.x;
+    const int nslot = plan[0];
+    for (int e = t; e < nslot; e += 256) {
+        srow[e] = plan[1 + e];
+        ssrc[e] = plan[1 + SW_SLOTS + e];
+    }
+    __syncthreads();
+    if (nslot == 0) return;
+    const int ncols = ncols_left + ncols_right;
+    // columns of this workgroup, in passes of at most SW_TILE elements
+    const int cpp = nslot < SW_TILE ? SW_TILE / nslot : 1;      // columns per pass
+    const int c_begin = blockIdx.x * cw;
+    const int c_end = min(ncols, c_begin + cw);
+    for (int cb = c_begin; cb < c_end; cb += cpp) {
+        const int cn = min(cpp, c_end - cb);
+        const int total = nslot * cn;
+        double vals[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = t + 256 * k;
+            vals[k] = 0.0;
+            if (e < total) {
+                const int sl = e % nslot, jj = e / nslot;
+                const int cidx = cb + jj;
+                const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
+                vals[k] = A[ssrc[sl] + (long long)col * lda];
             }
         }
-        for (int c = 0; c < J; ++c) {        // the interchanges, in order
-            const int a = c, b = pslot[c];
-            const int x = content[a];
-            content[a] = content[b];
-            content[b] = x;
-        }
-        s_nslot = J + nx;
-    }
-    __syncthreads();
-    const int nslot = s_nslot;
-    const int CW = max(1, SW_TILE / nslot);                   // columns per pass
-    const int ncols = ncols_left + ncols_right;
-    for (int cb = blockIdx.x * CW; cb < ncols; cb += gridDim.x * CW) {
-        const int cw = min(CW, ncols - cb);
-        for (int e = t; e < nslot * cw; e += blockDim.x) {
-            const int sl = e % nslot, jj = e / nslot;   // down a column
-            const int cidx = cb + jj;
-            const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
-            tile[e] = A[content[sl] + (long long)col * lda];
-        }
         __syncthreads();
-        for (int e = t; e < nslot * cw; e += blockDim.x) {
-            const int sl = e % nslot, jj = e / nslot;   // down a column
-            if (content[sl] == srow[sl]) continue;
-            const int cidx = cb + jj;
-            const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
-            A[srow[sl] + (long long)col * lda] = tile[e];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = t + 256 * k;
+            if (e < total) {
+                const int sl = e % nslot, jj = e / nslot;
+                const int cidx = cb + jj;
+                const int col = cidx < ncols_left ? cidx : col_right + (cidx - ncols_left);
+                A[srow[sl] + (long long)col * lda] = vals[k];
+            }
         }
         __syncthreads();
     }
 }
 
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
-                 int ncols_right, const int *ipiv, int k1, int k2, int row0,
+                 int ncols_right, const int *ipiv, int k1, int k2, int row0, int *plan,
                  hipStream_t stream) {
     const int total = ncols_left + ncols_right;
-    if (total <= 0 || k2 <= k1) return 0;
+    if (total <= 0 || k2 <= k1 || nrows <= k1) return 0;
     if (k2 - k1 > SW_MAX) {
         set_error("more than %d interchanges in one call", SW_MAX);
         return EMU_ERR_UNSUPPORTED;
     }
+    int *gperm = reinterpret_cast<int *>(reinterpret_cast<char *>(plan) +
+                                         align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int)));
+    hipLaunchKernelGGL(k_swap_plan, dim3(1), dim3(64), 0, stream, ipiv, k1, k2, nrows, row0,
+                       plan, gperm);
+    // columns per workgroup from the largest possible plan (2 per interchange)
     const int nslot_max = 2 * (k2 - k1);
     const int cw = nslot_max < SW_TILE ? SW_TILE / nslot_max : 1;
-    int blocks = (total + cw - 1) / cw;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_laswp_perm, dim3(blocks), dim3(256), 0, stream, A, lda, nrows,
-                       ncols_left, col_right, ncols_right, ipiv, k1, k2, row0);
+    const int blocks = (total + cw - 1) / cw;
+    hipLaunchKernelGGL(k_swap_apply, dim3(blocks), dim3(256), 0, stream, A, lda, ncols_left,
+                       col_right, ncols_right, cw, plan);
     EMU_TRY_HIP(hipGetLastError());
     return 0;
 }
 
 // ---------------------------------------------------------------- getrs
-// The row interchanges of the whole factorization are composed into one
-// gather permutation by a single thread (they are sequential by definition),
-// then each right-hand side is gathered.
-__global__ void k_perm_from_ipiv(const int *__restrict__ ipiv, int n, int *perm) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int i = 0; i < n; ++i) perm[i] = i;
-    for (int c = 0; c < n; ++c) {
-        int p = ipiv[c] - 1;
-        if (p > c && p < n) {       // valid interchanges satisfy c <= p < n
-            int t = perm[c];
-            perm[c] = perm[p];
-            perm[p] = t;
-        }
-    }
+// The row interchanges of the whole factorization composed into one gather
+// permutation (in LDS when it fits).
+__global__ __launch_bounds__(64) void k_perm_from_ipiv(const int *__restrict__ ipiv, int n,
+                                                       int *__restrict__ perm) {
+    __shared__ int lp[PERM_LDS_MAX];
+    const int lane = threadIdx.x;
+    const bool in_lds = n <= PERM_LDS_MAX;
+    int *pm = in_lds ? lp : perm;
+    for (int i = lane; i < n; i += 64) pm[i] = i;
+    wave_sync_mem();
+    compose_interchanges(pm, n, n, ipiv, 0);
+    if (in_lds)
+        for (int i = lane; i < n; i += 64) perm[i] = lp[i];
 }
 
 // X (n x nrhs, scratch, leading dimension n) <- P B

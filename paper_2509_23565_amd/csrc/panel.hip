@@ -387,31 +387,35 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
 // --------------------------------------------- order-preserving FP64 tiles
 // C (m x n) -= A (m x k) B (k x n): every element c_ij is updated for k in
 // increasing order as c = c - a_ik b_kj (two roundings), as in elimination.
-constexpr int GS_T = 64, GS_K = 16;
+// Tile TM x 64 (TM = 64, 32 or 16; narrow tiles when the output is small,
+// so the launch still covers the chip), 256 threads of (TM / 16) x 4.
+constexpr int GS_N = 64, GS_K = 16;
+template <int TM>
 __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, long long lda,
                                                   const double *__restrict__ B, long long ldb,
                                                   double *__restrict__ C, long long ldc, int m,
                                                   int n, int k) {
-    __shared__ double As[GS_K][GS_T + 1];
-    __shared__ double Bs[GS_K][GS_T + 1];
+    constexpr int RM = TM / 16;
+    __shared__ double As[GS_K][TM + 1];
+    __shared__ double Bs[GS_K][GS_N + 1];
     const int t = threadIdx.x;
-    const int tr = t % 16, tc = t / 16;          // 16 x 16 threads, 4 x 4 each
-    const int m0 = blockIdx.x * GS_T, n0 = blockIdx.y * GS_T;
-    double c[4][4];
+    const int tr = t % 16, tc = t / 16;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * GS_N;
+    double c[RM][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RM; ++r)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int i = m0 + tr + 16 * r, j = n0 + tc + 16 * s;
             c[r][s] = (i < m && j < n) ? C[i + (long long)j * ldc] : 0.0;
         }
     for (int k0 = 0; k0 < k; k0 += GS_K) {
-        for (int e = t; e < GS_T * GS_K; e += 256) {
-            const int ii = e % GS_T, kk = e / GS_T;
+        for (int e = t; e < TM * GS_K; e += 256) {
+            const int ii = e % TM, kk = e / TM;
             const int i = m0 + ii, kx = k0 + kk;
             As[kk][ii] = (i < m && kx < k) ? A[i + (long long)kx * lda] : 0.0;
         }
-        for (int e = t; e < GS_T * GS_K; e += 256) {
+        for (int e = t; e < GS_N * GS_K; e += 256) {
             const int kk = e % GS_K, jj = e / GS_K;
             const int j = n0 + jj, kx = k0 + kk;
             Bs[kk][jj] = (j < n && kx < k) ? B[kx + (long long)j * ldb] : 0.0;
@@ -419,20 +423,20 @@ __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, 
         __syncthreads();
         const int kend = min(GS_K, k - k0);
         for (int kk = 0; kk < kend; ++kk) {
-            double a[4], b[4];
+            double a[RM], b[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][tr + 16 * r];
+            for (int r = 0; r < RM; ++r) a[r] = As[kk][tr + 16 * r];
 #pragma unroll
             for (int s = 0; s < 4; ++s) b[s] = Bs[kk][tc + 16 * s];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < RM; ++r)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) c[r][s] = c[r][s] - a[r] * b[s];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RM; ++r)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int i = m0 + tr + 16 * r, j = n0 + tc + 16 * s;
@@ -443,8 +447,18 @@ __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, 
 static int gemm_seq(const double *A, long long lda, const double *B, long long ldb, double *C,
                     long long ldc, int m, int n, int k, hipStream_t st) {
     if (m <= 0 || n <= 0 || k <= 0) return 0;
-    dim3 g((m + GS_T - 1) / GS_T, (n + GS_T - 1) / GS_T);
-    hipLaunchKernelGGL(k_gemm_seq, g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, m, n, k);
+    const int gy = (n + GS_N - 1) / GS_N;
+    const long long want = 1024;      // workgroups that keep every CU busy
+    if ((long long)((m + 63) / 64) * gy >= want) {
+        hipLaunchKernelGGL(k_gemm_seq<64>, dim3((m + 63) / 64, gy), dim3(256), 0, st, A, lda, B,
+                           ldb, C, ldc, m, n, k);
+    } else if ((long long)((m + 31) / 32) * gy >= want) {
+        hipLaunchKernelGGL(k_gemm_seq<32>, dim3((m + 31) / 32, gy), dim3(256), 0, st, A, lda, B,
+                           ldb, C, ldc, m, n, k);
+    } else {
+        hipLaunchKernelGGL(k_gemm_seq<16>, dim3((m + 15) / 16, gy), dim3(256), 0, st, A, lda, B,
+                           ldb, C, ldc, m, n, k);
+    }
     EMU_TRY_HIP(hipGetLastError());
     return 0;
 }
