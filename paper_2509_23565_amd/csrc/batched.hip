@@ -53,8 +53,8 @@ struct BSys {
 // registers (same operations and order as the single-system panel).
 __global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, int j0, int nb) {
     __shared__ double urow[BMAX_NB], xrow[BMAX_NB];
-    __shared__ double red_v[16 + 1];
-    __shared__ int red_i[16 + 1];
+    __shared__ long long red_k[16];
+    __shared__ int red_i[16];
     const BSys S = sys[blockIdx.x];
     const int rows = S.n - j0;
     if (rows <= 0) return;
@@ -71,13 +71,13 @@ __global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, i
 #pragma unroll
         for (int j = 0; j < BMAX_NB; ++j)
             if (j == c) vc = v[j];
-        double bv = -1.0;
+        long long bk = -1;
         int bi = INT_MAX;
         if (t >= c && t < rows) {
-            bv = fabs(vc);
+            bk = pivot_key(vc);
             bi = t;
         }
-        block_best<16>(bv, bi, red_v, red_i);
+        block_key_best<16>(bk, bi, red_k, red_i);
         const int p = bi;
         if (t == p)
 #pragma unroll

@@ -7,52 +7,74 @@
 
 namespace emu {
 
-// Pivot order: NaN ranks above every number; otherwise larger magnitude
-// wins; ties go to the smaller row index.
-__device__ __forceinline__ bool better(double va, int ia, double vb, int ib) {
-    bool na = va != va, nb = vb != vb;
-    if (na || nb) {
-        if (na && nb) return ia < ib;
-        return na;
-    }
-    if (va != vb) return va > vb;
-    return ia < ib;
+// Pivot order (partial pivoting): NaN ranks above every number, otherwise
+// the larger magnitude wins, ties go to the smaller row.  It is evaluated
+// branch-free on a key: the bit pattern of the magnitude as a signed 64-bit
+// integer (monotone in the magnitude for non-negative doubles), every NaN
+// mapped to one key above +inf, and -1 for "no candidate".
+__device__ __forceinline__ long long pivot_key(double v) {
+    const long long b = __double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFll;
+    return b > 0x7FF0000000000000ll ? 0x7FF8000000000000ll : b;
 }
 
-__device__ __forceinline__ void wave_best(double &v, int &i) {
-    for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(v, off, 64);
-        int oi = __shfl_xor(i, off, 64);
-        if (better(ov, oi, v, i)) {
-            v = ov;
-            i = oi;
-        }
+__device__ __forceinline__ bool key_better(long long ka, int ia, long long kb, int ib) {
+    return ka > kb || (ka == kb && ia < ib);
+}
+
+// One butterfly level through a DPP lane permutation (CTRL).
+template <int CTRL>
+__device__ __forceinline__ void key_dpp_step(long long &k, int &i) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)k, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(k >> 32), CTRL, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+    const long long ok = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    if (key_better(ok, oi, k, i)) {
+        k = ok;
+        i = oi;
     }
 }
 
-// Best (value, row) over the workgroup; every thread gets the result.
-// red_v/red_i: LDS arrays of at least nwaves + 1 entries.
+__device__ __forceinline__ void key_xor_step(long long &k, int &i, int off) {
+    const long long ok = __shfl_xor(k, off, 64);
+    const int oi = __shfl_xor(i, off, 64);
+    if (key_better(ok, oi, k, i)) {
+        k = ok;
+        i = oi;
+    }
+}
+
+// Best (key, row) over each aligned group of W lanes (W = 16, 32 or 64);
+// every lane of the group receives it.  The first four levels stay inside
+// rows of 16 lanes and use DPP (lane ^ 1, lane ^ 2, then the mirrors within
+// 8 and 16 lanes, which pair each half with the other once the halves are
+// uniform); the levels across rows use lane shuffles.
+template <int W>
+__device__ __forceinline__ void key_best(long long &k, int &i) {
+    key_dpp_step<0xB1>(k, i);    // quad_perm [1, 0, 3, 2]
+    key_dpp_step<0x4E>(k, i);    // quad_perm [2, 3, 0, 1]
+    key_dpp_step<0x141>(k, i);   // row_half_mirror
+    key_dpp_step<0x140>(k, i);   // row_mirror
+    if constexpr (W >= 32) key_xor_step(k, i, 16);
+    if constexpr (W >= 64) key_xor_step(k, i, 32);
+}
+
+// Best (key, row) over a workgroup of NWAVES waves (a power of two up to 16,
+// all waves present); every thread gets the result.  One barrier: each wave
+// then reduces the NWAVES wave results itself.  red_k / red_i: LDS arrays of
+// NWAVES entries, which the caller must not rewrite before a later barrier.
 template <int NWAVES>
-__device__ __forceinline__ void block_best(double &v, int &i, double *red_v, int *red_i) {
+__device__ __forceinline__ void block_key_best(long long &k, int &i, long long *red_k,
+                                               int *red_i) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    wave_best(v, i);
+    key_best<64>(k, i);
     if (lane == 0) {
-        red_v[wid] = v;
+        red_k[wid] = k;
         red_i[wid] = i;
     }
     __syncthreads();
-    if (wid == 0) {
-        double bv = lane < NWAVES ? red_v[lane] : -1.0;
-        int bi = lane < NWAVES ? red_i[lane] : INT_MAX;
-        wave_best(bv, bi);
-        if (lane == 0) {
-            red_v[NWAVES] = bv;
-            red_i[NWAVES] = bi;
-        }
-    }
-    __syncthreads();
-    v = red_v[NWAVES];
-    i = red_i[NWAVES];
+    k = red_k[lane & (NWAVES - 1)];
+    i = red_i[lane & (NWAVES - 1)];
+    key_best<NWAVES>(k, i);
 }
 
 }  // namespace emu

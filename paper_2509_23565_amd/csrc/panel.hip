@@ -43,7 +43,7 @@ constexpr int LF_MAX_G = 32;                   // workgroups of one leaf (65536 
 constexpr int LF_SPIN_LIMIT = 1 << 20;         // polls of one grid-wide wait
 
 // Cross-workgroup exchange of a multi-workgroup leaf (global scratch).
-// Per column and workgroup one record: [0] best |value|, [1] its row (as
+// Per column and workgroup one record: [0] best pivot key, [1] its row (as
 // an integer), [4..19] a copy of that row, [20..35] a copy of row c (only
 // workgroup 0, which owns it); the record is published by writing its
 // sequence number after it.  Double-buffered by column parity.
@@ -54,20 +54,6 @@ struct LeafX {
     int *abort;         // set by a workgroup whose wait exceeded the bound
     int *status;        // device status word (EMU_STATUS_PANEL_WAIT)
 };
-
-// Best (value, row) over aligned groups of W lanes (xor butterfly).
-template <int W>
-__device__ __forceinline__ void lanes_best(double &v, int &i) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(i, off, 64);
-        if (better(ov, oi, v, i)) {
-            v = ov;
-            i = oi;
-        }
-    }
-}
 
 __device__ __forceinline__ void st_relaxed(double *p, double v) {
     __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
@@ -90,7 +76,7 @@ __device__ __forceinline__ unsigned ld_relaxed(const unsigned *p) {
 }
 
 struct LeafLds {
-    double val[2][LF_WAVES];
+    long long val[2][LF_WAVES];   // pivot keys
     int idx[2][LF_WAVES];
     double row[2][LF_WAVES][LEAF_W];
     double xrow[2][LEAF_W];
@@ -113,17 +99,20 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     constexpr int buf = c & 1;
     // this thread's and this wave's candidate for column c
-    double bv = -1.0;
+    long long bv = -1;
     int bi = INT_MAX;
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * LF_THREADS;
-        if (i >= c && i < rows && better(fabs(v[q][c]), i, bv, bi)) {
-            bv = fabs(v[q][c]);
-            bi = i;
+        if (i >= c && i < rows) {
+            const long long kq = pivot_key(v[q][c]);
+            if (key_better(kq, i, bv, bi)) {
+                bv = kq;
+                bi = i;
+            }
         }
     }
-    lanes_best<64>(bv, bi);
+    key_best<64>(bv, bi);
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * LF_THREADS;
@@ -140,9 +129,9 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     }
     __syncthreads();
     // the workgroup's winner (every wave computes it)
-    double wv = L.val[buf][lane & (LF_WAVES - 1)];
+    long long wv = L.val[buf][lane & (LF_WAVES - 1)];
     int wi = L.idx[buf][lane & (LF_WAVES - 1)];
-    lanes_best<LF_WAVES>(wv, wi);
+    key_best<LF_WAVES>(wv, wi);
     int p;
     const double *ur, *xr;
     if constexpr (!MULTI) {
@@ -160,7 +149,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
             } else if (lane < 2 * LEAF_W) {
                 if (g == 0) st_relaxed(mine + 20 + (lane - LEAF_W), L.xrow[buf][lane - LEAF_W]);
             } else if (lane == 2 * LEAF_W) {
-                st_relaxed(mine, wv);
+                st_relaxed(mine, __longlong_as_double(wv));
             } else if (lane == 2 * LEAF_W + 1) {
                 st_relaxed(mine + 1, (double)wi);
             }
@@ -195,10 +184,10 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
             // every record at once: values and rows (no dependent second read)
             const double *recs = x.rec + (long long)buf * LF_MAX_G * REC;
             const int l = lane & (LF_MAX_G - 1);
-            double gv = -1.0;
+            long long gv = -1;
             int gi = INT_MAX;
             if (l < G) {
-                gv = ld_relaxed(recs + (long long)l * REC);
+                gv = __double_as_longlong(ld_relaxed(recs + (long long)l * REC));
                 gi = (int)ld_relaxed(recs + (long long)l * REC + 1);
             }
             double rv[LF_MAX_G * LEAF_W / 64];
@@ -208,7 +197,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                 rv[q] = sl < G ? ld_relaxed(recs + (long long)sl * REC + 4 + j) : 0.0;
             }
             const double rc = lane < LEAF_W ? ld_relaxed(recs + 20 + lane) : 0.0;
-            lanes_best<LF_MAX_G>(gv, gi);
+            key_best<LF_MAX_G>(gv, gi);
 #pragma unroll
             for (int q = 0; q < LF_MAX_G * LEAF_W / 64; ++q) {
                 const int e = lane + 64 * q, sl = e / LEAF_W, j = e % LEAF_W;

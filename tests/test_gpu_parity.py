@@ -225,6 +225,33 @@ def test_getrf_lookahead_changes_no_bit(m, n, nb, s):
     assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
 
 
+def _same_or_both_nan(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nan = np.isnan(a) & np.isnan(b)
+    return a.shape == b.shape and bool(np.all(nan | (a.view(np.int64) == b.view(np.int64))))
+
+
+@pytest.mark.parametrize("m,n,nb,s,special", [(300, 64, 32, 3, False), (2600, 48, 48, 3, False),
+                                              (2600, 48, 48, 3, True), (5000, 40, 16, 4, True)])
+def test_getrf_pivot_ties_and_nonfinite(m, n, nb, s, special):
+    # small integers: many equal magnitudes, so the smallest-row tie rule
+    # decides; planted NaN / Inf: NaN ranks above every number
+    g = np.random.default_rng(29)
+    A = np.asfortranarray(g.integers(-3, 4, size=(m, n)).astype(np.float64))
+    if special:
+        A[m // 2, 5] = np.nan
+        A[m - 100, 20] = np.inf
+        A[7, 30] = -np.inf
+    Ag = emu.colmajor(A)
+    ipiv, info = emu.dgetrf(Ag, nb=nb, nslices=s)
+    emu.status()
+    LU, piv, inf = O.getrf(A, nb=nb, s=s)
+    assert np.array_equal(_host(ipiv), piv)
+    assert int(_host(info)[0]) == inf
+    assert _same_or_both_nan(_host(Ag), LU)
+
+
 def test_lu_solve_small_config_bit_exact_and_backward_error():
     # plain method, small: n = 1024, U(-1,1), block 64, 7 slices, seed 0
     n = 1024
