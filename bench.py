@@ -254,8 +254,11 @@ def main():
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
     ap.add_argument("--lu-trace", type=str, default="",
-                    help="N,NB,S: only factor one N x N phi=1 matrix twice with emu_dgetrf "
-                         "(block NB, S slices) and exit, for kernel traces of the LU")
+                    help="N,NB,S[,ir|,batch]: only factor one N x N phi=1 matrix twice "
+                         "with emu_dgetrf (block NB, S slices); with ',ir' solve the "
+                         "precision-form kappa=1e2 system twice with emu_dgesv_ir; with "
+                         "',batch' solve N systems of the batched workload twice with "
+                         "emu_dgesv_batched; then exit (for kernel traces)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -277,10 +280,28 @@ def main():
         log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
         del src, dst
     if args.lu_trace:
-        ln, lnb, ls = (int(v) for v in args.lu_trace.split(","))
-        Al = emu.colmajor(matgen.phi_matrix(ln, ln, 1.0, seed=args.seed))
-        for _ in range(2):
-            emu.dgetrf(Al.clone(), nb=lnb, nslices=ls)
+        fields = args.lu_trace.split(",")
+        ln, lnb, ls = (int(v) for v in fields[:3])
+        if len(fields) > 3 and fields[3] == "batch":
+            # ln systems as in the batched workload, block lnb, ls slices
+            specs = matgen.batched_specs(ln, seed=args.seed)
+            As = [emu.colmajor(matgen.phi_matrix(n_, n_, phi_, seed=args.seed,
+                                                 substream=1000 + i))
+                  for i, (n_, phi_, r_) in enumerate(specs)]
+            Bs = [emu.colmajor(matgen.uniform(n_, r_, seed=args.seed, substream=5000 + i))
+                  for i, (n_, phi_, r_) in enumerate(specs)]
+            for _ in range(2):
+                emu.dgesv_batched([a.clone() for a in As], [b.clone() for b in Bs], nb=lnb,
+                                  nslices=ls)
+        elif len(fields) > 3 and fields[3] == "ir":
+            Al = emu.colmajor(matgen.kappa_matrix(ln, 1.0, 1e2, seed=args.seed))
+            bl = emu.colmajor(matgen.uniform(ln, 1, seed=args.seed, substream=1))
+            for _ in range(2):
+                emu.dgesv_ir(Al, bl, nb=lnb, nslices=ls, tol=1e-15)
+        else:
+            Al = emu.colmajor(matgen.phi_matrix(ln, ln, 1.0, seed=args.seed))
+            for _ in range(2):
+                emu.dgetrf(Al.clone(), nb=lnb, nslices=ls)
         torch.cuda.synchronize()
         print("done", flush=True)
         return

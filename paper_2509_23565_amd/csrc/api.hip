@@ -646,7 +646,8 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
                 break;
             }
             prev = eta;
-            EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, R, n, reinterpret_cast<int *>(subws), st));
+            EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, R, n, reinterpret_cast<int *>(subws), st,
+                                 true));
             EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
             ++total_iters;
         }
@@ -724,7 +725,7 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
         }
         prev = eta;
         EMU_TRY(launch_getrs(n, nrhs, LU, ldlu, ipiv, R, n, reinterpret_cast<int *>(ws + o_sub),
-                             st));
+                             st, it > 0));
         EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
     }
 }

@@ -164,9 +164,11 @@ int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_ri
                  hipStream_t stream);
 int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
                      long long ldb, int ncols, hipStream_t stream);
+// perm_ws holds the composed row permutation after a call; perm_ready
+// reuses it (same factors) instead of composing it again.
 int launch_getrs(int n, int nrhs, const double *LU, long long lda,
                  const int *ipiv, double *B, long long ldb, int *perm_ws,
-                 hipStream_t stream);
+                 hipStream_t stream, bool perm_ready = false);
 
 // Precision form (refine.hip).
 size_t refine_partial_bytes(int n, int nrhs);

@@ -30,13 +30,16 @@ __device__ __forceinline__ void wave_sync_mem() {
 __device__ void compose_interchanges(int *pm, int R, int J, const int *__restrict__ piv,
                                      int piv_base) {
     const int lane = threadIdx.x & 63;
+    // the pivots of the next block are loaded while this one is composed
+    int raw = lane < 32 && lane < J ? piv[lane] : 0;
     for (int k0 = 0; k0 < J; k0 += 32) {
         const int w = J - k0 < 32 ? J - k0 : 32;
         int pk = -1;                                 // pivot of k0 + lane, relative to k0
         if (lane < w) {
-            pk = piv[k0 + lane] - 1 - piv_base - k0;
+            pk = raw - 1 - piv_base - k0;
             if (pk < lane || pk >= R - k0) pk = lane;
         }
+        raw = lane < 32 && k0 + 32 + lane < J ? piv[k0 + 32 + lane] : 0;
         bool first = lane < w && pk >= w;            // first use of a row below the block
         for (int k2 = 0; k2 < w; ++k2) {
             const int pk2 = __builtin_amdgcn_readlane(pk, k2);
@@ -222,18 +225,47 @@ __global__ void k_copy_cols(const double *__restrict__ X, int n, double *__restr
 
 constexpr int TRSV_NB = 64;
 
+// Value of lane k (k uniform) broadcast to the wave.
+__device__ __forceinline__ double lane_bcast(double v, int k) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, k);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
+// The kb x kb diagonal block at (k0, k0) into LDS, column-major (lane i
+// reads row i of every column: contiguous in global memory, conflict-free
+// in LDS).
+__device__ __forceinline__ void load_diag_block(const double *__restrict__ LU, long long lda,
+                                                int k0, int kb, double *Ds) {
+    const int lane = threadIdx.x;
+    // all loads issued before the first store (no serialized round trips)
+    double col[TRSV_NB];
+#pragma unroll
+    for (int k = 0; k < TRSV_NB; ++k)
+        col[k] = (k < kb && lane < kb) ? LU[(k0 + lane) + (long long)(k0 + k) * lda] : 0.0;
+#pragma unroll
+    for (int k = 0; k < TRSV_NB; ++k) Ds[k * TRSV_NB + lane] = col[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Forward substitution, diagonal block [k0, k0+kb): one wave per rhs; lane
 // i holds x_{k0+i}; for k increasing, lanes i > k subtract l_ik x_k.
 __global__ __launch_bounds__(64) void k_fwd_diag(const double *__restrict__ LU,
                                                  long long lda, int n, int k0, int kb,
                                                  double *__restrict__ X) {
+    __shared__ double Ds[TRSV_NB * TRSV_NB];
     const int lane = threadIdx.x;
+    load_diag_block(LU, lda, k0, kb, Ds);
     double *x = X + (long long)blockIdx.x * n;
     const int i = k0 + lane;
     double b = lane < kb ? x[i] : 0.0;
     for (int k = 0; k < kb - 1; ++k) {
-        const double xk = __shfl(b, k, 64);
-        if (lane > k && lane < kb) b = b - LU[i + (long long)(k0 + k) * lda] * xk;
+        const double xk = lane_bcast(b, k);
+        if (lane > k && lane < kb) b = b - Ds[k * TRSV_NB + lane] * xk;
     }
     if (lane < kb) x[i] = b;
 }
@@ -249,8 +281,13 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ L
     __syncthreads();
     const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double l[TRSV_NB];
+#pragma unroll
+    for (int k = 0; k < TRSV_NB; ++k) l[k] = k < kb ? LU[i + (long long)(k0 + k) * lda] : 0.0;
     double b = x[i];
-    for (int k = 0; k < kb; ++k) b = b - LU[i + (long long)(k0 + k) * lda] * xs[k];
+#pragma unroll
+    for (int k = 0; k < TRSV_NB; ++k)
+        if (k < kb) b = b - l[k] * xs[k];
     x[i] = b;
 }
 
@@ -259,14 +296,16 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ L
 __global__ __launch_bounds__(64) void k_bwd_diag(const double *__restrict__ LU,
                                                  long long lda, int n, int k0, int kb,
                                                  double *__restrict__ X) {
+    __shared__ double Ds[TRSV_NB * TRSV_NB];
     const int lane = threadIdx.x;
+    load_diag_block(LU, lda, k0, kb, Ds);
     double *x = X + (long long)blockIdx.x * n;
     const int i = k0 + lane;
     double b = lane < kb ? x[i] : 0.0;
     for (int k = kb - 1; k >= 0; --k) {
-        if (lane == k) b = b / LU[i + (long long)i * lda];
-        const double xk = __shfl(b, k, 64);
-        if (lane < k) b = b - LU[i + (long long)(k0 + k) * lda] * xk;
+        if (lane == k) b = b / Ds[k * TRSV_NB + k];
+        const double xk = lane_bcast(b, k);
+        if (lane < k) b = b - Ds[k * TRSV_NB + lane] * xk;
     }
     if (lane < kb) x[i] = b;
 }
@@ -281,18 +320,24 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double *__restrict__ L
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= k0) return;
+    double u[TRSV_NB];
+#pragma unroll
+    for (int k = 0; k < TRSV_NB; ++k) u[k] = k < kb ? LU[i + (long long)(k0 + k) * lda] : 0.0;
     double b = x[i];
-    for (int k = kb - 1; k >= 0; --k) b = b - LU[i + (long long)(k0 + k) * lda] * xs[k];
+#pragma unroll
+    for (int k = TRSV_NB - 1; k >= 0; --k)
+        if (k < kb) b = b - u[k] * xs[k];
     x[i] = b;
 }
 
 int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ipiv,
-                 double *B, long long ldb, int *perm_ws, hipStream_t stream) {
+                 double *B, long long ldb, int *perm_ws, hipStream_t stream, bool perm_ready) {
     if (n <= 0 || nrhs <= 0) return 0;
     int *perm = perm_ws;
     double *X = reinterpret_cast<double *>(
         reinterpret_cast<char *>(perm_ws) + align256((size_t)n * sizeof(int)));
-    hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm);
+    if (!perm_ready)
+        hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm);
     dim3 gcol((n + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_gather_rows, gcol, dim3(256), 0, stream, B, ldb, n, perm, X);
     for (int k0 = 0; k0 < n; k0 += TRSV_NB) {

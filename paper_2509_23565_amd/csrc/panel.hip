@@ -43,16 +43,21 @@ constexpr int LF_MAX_G = 32;                   // workgroups of one leaf (65536 
 constexpr int LF_SPIN_LIMIT = 1 << 20;         // polls of one grid-wide wait
 
 // Cross-workgroup exchange of a multi-workgroup leaf (global scratch).
-// Per column and workgroup one record: [0] best pivot key, [1] its row (as
-// an integer), [4..19] a copy of that row, [20..35] a copy of row c (only
-// workgroup 0, which owns it); the record is published by writing its
-// sequence number after it.  Double-buffered by column parity.
-constexpr int REC = 36;
+// Per column and workgroup one record of 64-bit words, each holding a
+// 32-bit payload in its low half and the column's tag in its high half, so
+// every word is validated on its own and one read of the records follows
+// the last write (no separate flag to poll).  Words: [0] pivot key high,
+// [1] key low, [2] its row, [3] unused, [4 + 2j], [5 + 2j] low and high
+// half of element j of that row, [36 + 2j], [37 + 2j] the same for row c
+// (workgroup 0 only, which owns it).  Double-buffered by column parity;
+// tags count the columns of the panel from 1 (the words are zeroed once
+// per panel).
+constexpr int RW = 68;              // words per record
+constexpr int RW_MAIN = 36;         // words every workgroup publishes
 struct LeafX {
-    double *rec;        // [2][LF_MAX_G][REC]
-    unsigned *seq;      // [2][LF_MAX_G] sequence number of each record
-    int *abort;         // set by a workgroup whose wait exceeded the bound
-    int *status;        // device status word (EMU_STATUS_PANEL_WAIT)
+    unsigned long long *rec;        // [2][LF_MAX_G][RW]
+    int *abort;                     // set by a workgroup whose wait exceeded the bound
+    int *status;                    // device status word (EMU_STATUS_PANEL_WAIT)
 };
 
 __device__ __forceinline__ void st_relaxed(double *p, double v) {
@@ -81,6 +86,7 @@ struct LeafLds {
     double row[2][LF_WAVES][LEAF_W];
     double xrow[2][LEAF_W];
     double grow[2][LF_MAX_G][LEAF_W];   // multi-workgroup: every record's row
+    unsigned gkey[2][LF_MAX_G][3];      // and its key (high, low) and row
     double xr[2][LEAF_W];
     int p[2];
     int abort;
@@ -141,27 +147,69 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     } else {
         const int G = (int)gridDim.x;
         if (wid == 0) {
-            // publish this workgroup's record, then its sequence number
-            const unsigned expect = base + (unsigned)c + 1u;
-            double *mine = x.rec + ((long long)buf * LF_MAX_G + g) * REC;
-            if (lane < LEAF_W) {
-                st_relaxed(mine + 4 + lane, L.row[buf][((wi - base_row) % LF_THREADS) / 64][lane]);
-            } else if (lane < 2 * LEAF_W) {
-                if (g == 0) st_relaxed(mine + 20 + (lane - LEAF_W), L.xrow[buf][lane - LEAF_W]);
-            } else if (lane == 2 * LEAF_W) {
-                st_relaxed(mine, __longlong_as_double(wv));
-            } else if (lane == 2 * LEAF_W + 1) {
-                st_relaxed(mine + 1, (double)wi);
+            const unsigned long long tag = (unsigned long long)(base + (unsigned)c + 1u) << 32;
+            // publish: words 0..35 (and 36..67 from workgroup 0), tagged
+            unsigned long long *mine = x.rec + ((long long)buf * LF_MAX_G + g) * RW;
+            const double *wrow = L.row[buf][((wi - base_row) % LF_THREADS) / 64];
+            for (int e = lane; e < (g == 0 ? RW : RW_MAIN); e += 64) {
+                unsigned pl;
+                if (e == 0) {
+                    pl = (unsigned)((unsigned long long)wv >> 32);
+                } else if (e == 1) {
+                    pl = (unsigned)(unsigned long long)wv;
+                } else if (e == 2) {
+                    pl = (unsigned)wi;
+                } else if (e == 3) {
+                    pl = 0u;
+                } else {
+                    const int j = (e - 4) % 32 / 2, hi = e & 1;
+                    const double d = e < RW_MAIN ? wrow[j] : L.xrow[buf][j];
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
+                    pl = hi ? (unsigned)(bits >> 32) : (unsigned)bits;
+                }
+                __hip_atomic_store(mine + e, tag | pl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            if (lane == 0)
-                __hip_atomic_store(x.seq + buf * LF_MAX_G + g, expect, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            // wait until every workgroup's record of this column is out
-            bool ok = lane >= G;
+            // collect: read every record's words until all carry this tag;
+            // validated payloads go straight to LDS
+            const unsigned long long *recs = x.rec + (long long)buf * LF_MAX_G * RW;
+            unsigned *grow_w = reinterpret_cast<unsigned *>(&L.grow[buf][0][0]);
+            unsigned *xr_w = reinterpret_cast<unsigned *>(&L.xr[buf][0]);
+            const int nw = RW_MAIN * G + 32;            // words to read
             int spins = 0;
             for (;;) {
-                if (!ok) ok = ld_relaxed(x.seq + buf * LF_MAX_G + lane) == expect;
+                bool ok = true;
+                for (int e0 = 0; e0 < nw; e0 += 4 * 64) {
+                    unsigned long long wd[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = e0 + u * 64 + lane;
+                        const int sl = e < RW_MAIN * G ? e / RW_MAIN : 0;
+                        const int k = e < RW_MAIN * G ? e % RW_MAIN : RW_MAIN + (e - RW_MAIN * G);
+                        wd[u] = e < nw ? __hip_atomic_load(recs + (long long)sl * RW + k,
+                                                           __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : tag;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = e0 + u * 64 + lane;
+                        if (e >= nw) continue;
+                        if ((wd[u] & 0xFFFFFFFF00000000ull) != tag) {
+                            ok = false;
+                            continue;
+                        }
+                        const unsigned pl = (unsigned)wd[u];
+                        if (e < RW_MAIN * G) {
+                            const int sl = e / RW_MAIN, k = e % RW_MAIN;
+                            if (k < 3)
+                                L.gkey[buf][sl][k] = pl;
+                            else if (k >= 4)
+                                grow_w[sl * 2 * LEAF_W + (k - 4)] = pl;
+                        } else {
+                            xr_w[e - RW_MAIN * G] = pl;
+                        }
+                    }
+                }
                 if (__ballot(!ok) == 0ull) break;
                 if ((++spins & 63) == 0) {
                     if (ld_relaxed(x.abort) != 0) {
@@ -180,30 +228,20 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            // every record at once: values and rows (no dependent second read)
-            const double *recs = x.rec + (long long)buf * LF_MAX_G * REC;
+            // lanes read what other lanes staged
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            // the grid's winner from the staged keys
             const int l = lane & (LF_MAX_G - 1);
             long long gv = -1;
             int gi = INT_MAX;
             if (l < G) {
-                gv = __double_as_longlong(ld_relaxed(recs + (long long)l * REC));
-                gi = (int)ld_relaxed(recs + (long long)l * REC + 1);
+                gv = (long long)(((unsigned long long)L.gkey[buf][l][0] << 32) |
+                                 L.gkey[buf][l][1]);
+                gi = (int)L.gkey[buf][l][2];
             }
-            double rv[LF_MAX_G * LEAF_W / 64];
-#pragma unroll
-            for (int q = 0; q < LF_MAX_G * LEAF_W / 64; ++q) {
-                const int e = lane + 64 * q, sl = e / LEAF_W, j = e % LEAF_W;
-                rv[q] = sl < G ? ld_relaxed(recs + (long long)sl * REC + 4 + j) : 0.0;
-            }
-            const double rc = lane < LEAF_W ? ld_relaxed(recs + 20 + lane) : 0.0;
             key_best<LF_MAX_G>(gv, gi);
-#pragma unroll
-            for (int q = 0; q < LF_MAX_G * LEAF_W / 64; ++q) {
-                const int e = lane + 64 * q, sl = e / LEAF_W, j = e % LEAF_W;
-                if (sl < G) L.grow[buf][sl][j] = rv[q];
-            }
-            if (lane < LEAF_W) L.xr[buf][lane] = rc;
             if (lane == 0) L.p[buf] = gi;
         }
         __syncthreads();
@@ -398,16 +436,31 @@ __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, 
             const int i = m0 + tr + 16 * r, j = n0 + tc + 16 * s;
             c[r][s] = (i < m && j < n) ? C[i + (long long)j * ldc] : 0.0;
         }
+    constexpr int PA = TM * GS_K / 256, PB = GS_N * GS_K / 256;
     for (int k0 = 0; k0 < k; k0 += GS_K) {
-        for (int e = t; e < TM * GS_K; e += 256) {
-            const int ii = e % TM, kk = e / TM;
+        // the chunk's loads all in flight before the first store
+        double av[PA], bv[PB];
+#pragma unroll
+        for (int r = 0; r < PA; ++r) {
+            const int e = t + 256 * r, ii = e % TM, kk = e / TM;
             const int i = m0 + ii, kx = k0 + kk;
-            As[kk][ii] = (i < m && kx < k) ? A[i + (long long)kx * lda] : 0.0;
+            av[r] = (i < m && kx < k) ? A[i + (long long)kx * lda] : 0.0;
         }
-        for (int e = t; e < GS_N * GS_K; e += 256) {
-            const int kk = e % GS_K, jj = e / GS_K;
+#pragma unroll
+        for (int r = 0; r < PB; ++r) {
+            const int e = t + 256 * r, kk = e % GS_K, jj = e / GS_K;
             const int j = n0 + jj, kx = k0 + kk;
-            Bs[kk][jj] = (j < n && kx < k) ? B[kx + (long long)j * ldb] : 0.0;
+            bv[r] = (j < n && kx < k) ? B[kx + (long long)j * ldb] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < PA; ++r) {
+            const int e = t + 256 * r;
+            As[e / TM][e % TM] = av[r];
+        }
+#pragma unroll
+        for (int r = 0; r < PB; ++r) {
+            const int e = t + 256 * r;
+            Bs[e % GS_K][e / GS_K] = bv[r];
         }
         __syncthreads();
         const int kend = min(GS_K, k - k0);
@@ -464,9 +517,18 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_trsm_lanes(const double *__re
                                                               double *__restrict__ B,
                                                               long long ldb, int ncols) {
     __shared__ double Ls[TR_NB * TR_NB];
-    for (int idx = threadIdx.x; idx < jb * jb; idx += blockDim.x) {
-        const int i = idx % jb, k = idx / jb;
-        Ls[k * TR_NB + i] = L[i + (long long)k * ldl];
+    {
+        // thread (i = t % 64, k = t / 64 + 4 r): all loads before the stores
+        constexpr int PER = TR_NB * TR_NB / (64 * TR_WAVES);
+        double lv[PER];
+        const int i = threadIdx.x & 63, kq = threadIdx.x >> 6;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int k = kq + TR_WAVES * r;
+            lv[r] = (i < jb && k < jb) ? L[i + (long long)k * ldl] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) Ls[(kq + TR_WAVES * r) * TR_NB + i] = lv[r];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -513,8 +575,7 @@ int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B, long lon
 
 // ------------------------------------------------------------ recursion
 static size_t leafx_bytes() {
-    return align256(2 * LF_MAX_G * REC * sizeof(double)) +
-           align256(2 * LF_MAX_G * sizeof(unsigned) + sizeof(int));
+    return align256(2 * LF_MAX_G * RW * sizeof(unsigned long long) + sizeof(int));
 }
 
 size_t panel_scratch_bytes(int rows) {
@@ -524,9 +585,8 @@ size_t panel_scratch_bytes(int rows) {
 
 static LeafX leaf_x(char *ws, int *status) {
     LeafX x;
-    x.rec = reinterpret_cast<double *>(ws);
-    x.seq = reinterpret_cast<unsigned *>(ws + align256(2 * LF_MAX_G * REC * sizeof(double)));
-    x.abort = reinterpret_cast<int *>(x.seq + 2 * LF_MAX_G);
+    x.rec = reinterpret_cast<unsigned long long *>(ws);
+    x.abort = reinterpret_cast<int *>(x.rec + 2 * LF_MAX_G * RW);
     x.status = status;
     return x;
 }
@@ -588,10 +648,11 @@ int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0
                  char *ws, int *status, hipStream_t stream) {
     PanelRun pr{ws, status, 0u};
     if (rows > LF_ROWS) {
-        // sequence numbers and the abort flag start at zero (a fill kernel,
-        // not a memset)
+        // record words (tag 0: not yet written) and the abort flag start at
+        // zero (a fill kernel, not a memset)
         LeafX x = leaf_x(ws, status);
-        EMU_TRY(launch_fill_int(reinterpret_cast<int *>(x.seq), 0, 2 * LF_MAX_G + 1, stream));
+        EMU_TRY(launch_fill_int(reinterpret_cast<int *>(x.rec), 0, 2 * 2 * LF_MAX_G * RW + 1,
+                                stream));
     }
     return panel_rec(A, lda, rows, jb, 0, jb, ipiv, row0, info, pr, stream);
 }
