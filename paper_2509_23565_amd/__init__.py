@@ -291,6 +291,12 @@ class _Batch:
             self.ld[i] = ld
 
 
+def _pivot_views(torch, sizes, dev):
+    """One int32 allocation for all pivot vectors of a batch, as views."""
+    flat = torch.zeros(sum(sizes), dtype=torch.int32, device=dev)
+    return list(torch.split(flat, sizes))
+
+
 def dgesv_batched(As, Bs, nb=32, nslices=5):
     """Factor and solve a batch in place (A_i -> LU_i, B_i -> X_i).
 
@@ -300,9 +306,10 @@ def dgesv_batched(As, Bs, nb=32, nslices=5):
     torch = _torch()
     count = len(As)
     dev = As[0].device
-    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
+    sizes = [int(a.shape[0]) for a in As]
+    n = (ctypes.c_int * count)(*sizes)
     nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
-    ipivs = [torch.zeros(int(a.shape[0]), dtype=torch.int32, device=dev) for a in As]
+    ipivs = _pivot_views(torch, sizes, dev)
     pp = (ctypes.c_void_p * count)(*[p.data_ptr() for p in ipivs])
     info = torch.zeros(count, dtype=torch.int32, device=dev)
     a = _Batch(As, "A")
@@ -318,8 +325,9 @@ def dgetrf_batched(As, nb=32, nslices=5):
     torch = _torch()
     count = len(As)
     dev = As[0].device
-    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
-    ipivs = [torch.zeros(int(a.shape[0]), dtype=torch.int32, device=dev) for a in As]
+    sizes = [int(a.shape[0]) for a in As]
+    n = (ctypes.c_int * count)(*sizes)
+    ipivs = _pivot_views(torch, sizes, dev)
     pp = (ctypes.c_void_p * count)(*[p.data_ptr() for p in ipivs])
     info = torch.zeros(count, dtype=torch.int32, device=dev)
     a = _Batch(As, "A")

@@ -50,11 +50,62 @@ struct BSys {
 // ------------------------------------------------------------------ panel
 // One workgroup per active system: column-by-column over the rows x jb
 // panel at (j0, j0), one row per thread, the row's jb <= 32 values in
-// registers (same operations and order as the single-system panel).
+// registers (same operations and order as the single-system panel).  The
+// column loop is unrolled at compile time, so every register index is fixed.
+struct BPanelLds {
+    double urow[BMAX_NB], xrow[BMAX_NB];
+    long long red_k[16];
+    int red_i[16];
+};
+
+template <int c>
+__device__ __forceinline__ void bpanel_cols(double (&v)[BMAX_NB], BPanelLds &L, int t, int rows,
+                                            int w, const BSys &S, int j0) {
+    if constexpr (c < BMAX_NB) {
+        if (c >= w) return;
+        long long bk = -1;
+        int bi = INT_MAX;
+        if (t >= c && t < rows) {
+            bk = pivot_key(v[c]);
+            bi = t;
+        }
+        block_key_best<16>(bk, bi, L.red_k, L.red_i);
+        const int p = bi;
+        if (t == p)
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) L.urow[j] = v[j];
+        if (t == c)
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) L.xrow[j] = v[j];
+        __syncthreads();
+        const double piv = L.urow[c];
+        if (t == 0) {
+            S.ipiv[j0 + c] = j0 + p + 1;
+            if (piv == 0.0 && *S.info == 0) *S.info = j0 + c + 1;
+        }
+        const bool swap = piv != 0.0 && p != c;
+        const double *ur = (piv != 0.0) ? L.urow : L.xrow;
+        if (swap && t == c) {
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) v[j] = L.urow[j];
+        } else if (swap && t == p) {
+#pragma unroll
+            for (int j = 0; j < BMAX_NB; ++j) v[j] = L.xrow[j];
+        }
+        if (t > c && t < rows) {
+            double l = v[c];
+            if (piv != 0.0) l = (fabs(piv) >= DBL_MIN) ? l * (1.0 / piv) : l / piv;
+            v[c] = l;
+#pragma unroll
+            for (int j = c + 1; j < BMAX_NB; ++j) v[j] = v[j] - l * ur[j];
+        }
+        __syncthreads();
+        bpanel_cols<c + 1>(v, L, t, rows, w, S, j0);
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, int j0, int nb) {
-    __shared__ double urow[BMAX_NB], xrow[BMAX_NB];
-    __shared__ long long red_k[16];
-    __shared__ int red_i[16];
+    __shared__ BPanelLds L;
     const BSys S = sys[blockIdx.x];
     const int rows = S.n - j0;
     if (rows <= 0) return;
@@ -65,105 +116,112 @@ __global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, i
 #pragma unroll
     for (int j = 0; j < BMAX_NB; ++j)
         v[j] = (t < rows && j < w) ? P[t + (long long)j * S.lda] : 0.0;
-#pragma unroll 1
-    for (int c = 0; c < w; ++c) {
-        double vc = 0.0;
-#pragma unroll
-        for (int j = 0; j < BMAX_NB; ++j)
-            if (j == c) vc = v[j];
-        long long bk = -1;
-        int bi = INT_MAX;
-        if (t >= c && t < rows) {
-            bk = pivot_key(vc);
-            bi = t;
-        }
-        block_key_best<16>(bk, bi, red_k, red_i);
-        const int p = bi;
-        if (t == p)
-#pragma unroll
-            for (int j = 0; j < BMAX_NB; ++j) urow[j] = v[j];
-        if (t == c)
-#pragma unroll
-            for (int j = 0; j < BMAX_NB; ++j) xrow[j] = v[j];
-        __syncthreads();
-        const double piv = urow[c];
-        if (t == 0) {
-            S.ipiv[j0 + c] = j0 + p + 1;
-            if (piv == 0.0 && *S.info == 0) *S.info = j0 + c + 1;
-        }
-        const bool swap = piv != 0.0 && p != c;
-        const double *ur = (piv != 0.0) ? urow : xrow;
-        if (swap && t == c) {
-#pragma unroll
-            for (int j = 0; j < BMAX_NB; ++j) v[j] = urow[j];
-        } else if (swap && t == p) {
-#pragma unroll
-            for (int j = 0; j < BMAX_NB; ++j) v[j] = xrow[j];
-        }
-        if (t > c && t < rows) {
-            double l = 0.0;
-#pragma unroll
-            for (int j = 0; j < BMAX_NB; ++j)
-                if (j == c) l = v[j];
-            if (piv != 0.0) l = (fabs(piv) >= DBL_MIN) ? l * (1.0 / piv) : l / piv;
-#pragma unroll
-            for (int j = 0; j < BMAX_NB; ++j) {
-                if (j == c) v[j] = l;
-                if (j > c) v[j] = v[j] - l * ur[j];
-            }
-        }
-        __syncthreads();
-    }
+    bpanel_cols<0>(v, L, t, rows, w, S, j0);
     if (t < rows)
 #pragma unroll
         for (int j = 0; j < BMAX_NB; ++j)
             if (j < w) P[t + (long long)j * S.lda] = v[j];
 }
 
-// Interchanges of step j0 on the columns outside the panel: thread per
-// column, the jb <= 32 swaps in order.
+// Interchanges of step j0 on the columns outside the panel.  Wave 0
+// composes the jb <= 32 interchanges into the rows they move (at most 64);
+// then threads take (moved row, column) pairs, consecutive threads down a
+// column, with all loads of the workgroup's 64 columns before any store.
+constexpr int BSW_COLS = 64;
 __global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, int j0, int nb) {
+    __shared__ int srow_s[2 * BMAX_NB], ssrc_s[2 * BMAX_NB];
+    __shared__ int nslot_s;
     const BSys S = sys[blockIdx.y];
     const int rows = S.n - j0;
     if (rows <= 0) return;
     const int w = nb < rows ? nb : rows;
     const int ncols = S.n - w;                       // [0, j0) and [j0 + w, n)
-    const int tcol = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tcol >= ncols) return;
-    const int col = tcol < j0 ? tcol : tcol + w;
-    double *a = S.A + (long long)col * S.lda;
-    for (int c = j0; c < j0 + w; ++c) {
-        const int p = S.ipiv[c] - 1;
-        if (p > c && p < S.n) {
-            const double t0 = a[c];
-            a[c] = a[p];
-            a[p] = t0;
+    const int c0 = blockIdx.x * BSW_COLS;
+    if (c0 >= ncols) return;                         // uniform per workgroup
+    const int t = threadIdx.x;
+    if (t < 64) {
+        int pk = -1;
+        if (t < w) {
+            pk = S.ipiv[j0 + t] - 1 - j0;
+            if (pk < t || pk >= rows) pk = t;        // no interchange
+        }
+        int srow, src;
+        const int ns = wave_compose32(pk, w, srow, src);
+        srow_s[t] = srow;
+        ssrc_s[t] = src;
+        if (t == 0) nslot_s = ns;
+    }
+    __syncthreads();
+    const int ns = nslot_s;
+    const int x = t & 63;                            // moved row (slot)
+    const bool moves = x < ns && srow_s[x] != ssrc_s[x];
+    const int from = ssrc_s[x], to = srow_s[x];
+    constexpr int PASSES = BSW_COLS / 4;
+    double v[PASSES];
+#pragma unroll
+    for (int r = 0; r < PASSES; ++r) {
+        const int tc = c0 + (t >> 6) + 4 * r;
+        v[r] = 0.0;
+        if (moves && tc < ncols) {
+            const int col = tc < j0 ? tc : tc + w;
+            v[r] = S.A[j0 + from + (long long)col * S.lda];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PASSES; ++r) {
+        const int tc = c0 + (t >> 6) + 4 * r;
+        if (moves && tc < ncols) {
+            const int col = tc < j0 ? tc : tc + w;
+            S.A[j0 + to + (long long)col * S.lda] = v[r];
         }
     }
 }
 
-// U12 = L11^-1 A12 for every active system: thread per column, the column
-// in registers, L11 (jb <= 32) in LDS.
-__global__ __launch_bounds__(256) void k_btrsm(const BSys *__restrict__ sys, int j0, int nb) {
+// U12 = L11^-1 A12 for every active system: one wave per 64 columns; the
+// column tile is staged through LDS (reads and writes run down the
+// columns), each lane then solves one column in registers with L11
+// (jb <= 32) in LDS.
+constexpr int BTR_COLS = 64;
+__global__ __launch_bounds__(64) void k_btrsm(const BSys *__restrict__ sys, int j0, int nb) {
     __shared__ double Ls[BMAX_NB * BMAX_NB];
+    __shared__ double Bt[BMAX_NB][BTR_COLS + 1];
     const BSys S = sys[blockIdx.y];
     const int rows = S.n - j0;
     if (rows <= 0) return;
     const int w = nb < rows ? nb : rows;
     const int ncols = S.n - j0 - w;
-    if (ncols <= 0 || (int)(blockIdx.x * blockDim.x) >= ncols) return;
+    const int c0 = blockIdx.x * BTR_COLS;
+    if (ncols <= 0 || c0 >= ncols) return;
+    const int lane = threadIdx.x;
     const double *L = S.A + j0 + (long long)j0 * S.lda;
-    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
-        const int i = idx % w, k = idx / w;
-        Ls[k * BMAX_NB + i] = L[i + (long long)k * S.lda];
+    double *Bc = S.A + j0 + (long long)(j0 + w + c0) * S.lda;
+    const int nc = ncols - c0 < BTR_COLS ? ncols - c0 : BTR_COLS;
+    {
+        constexpr int PL = BMAX_NB * BMAX_NB / 64;
+        double lv[PL];
+        const int i = lane & 31, kh = lane >> 5;     // row, column parity
+#pragma unroll
+        for (int r = 0; r < PL; ++r) {
+            const int k = kh + 2 * r;
+            lv[r] = (i < w && k < w) ? L[i + (long long)k * S.lda] : 0.0;
+        }
+        constexpr int PB = BMAX_NB * BTR_COLS / 64;
+        double bv[PB];
+#pragma unroll
+        for (int r = 0; r < PB; ++r) {
+            const int c = kh + 2 * r;
+            bv[r] = (i < w && c < nc) ? Bc[i + (long long)c * S.lda] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < PL; ++r) Ls[(kh + 2 * r) * BMAX_NB + i] = lv[r];
+#pragma unroll
+        for (int r = 0; r < PB; ++r) Bt[i][kh + 2 * r] = bv[r];
     }
     __syncthreads();
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncols) return;
-    double *bcol = S.A + j0 + (long long)(j0 + w + col) * S.lda;
     double b[BMAX_NB];
 #pragma unroll
-    for (int i = 0; i < BMAX_NB; ++i) b[i] = i < w ? bcol[i] : 0.0;
+    for (int i = 0; i < BMAX_NB; ++i) b[i] = Bt[i][lane];
 #pragma unroll
     for (int k = 0; k < BMAX_NB - 1; ++k) {
         if (k < w - 1) {
@@ -174,8 +232,16 @@ __global__ __launch_bounds__(256) void k_btrsm(const BSys *__restrict__ sys, int
         }
     }
 #pragma unroll
-    for (int i = 0; i < BMAX_NB; ++i)
-        if (i < w) bcol[i] = b[i];
+    for (int i = 0; i < BMAX_NB; ++i) Bt[i][lane] = b[i];
+    __syncthreads();
+    {
+        const int i = lane & 31, kh = lane >> 5;
+#pragma unroll
+        for (int r = 0; r < BMAX_NB * BTR_COLS / 64; ++r) {
+            const int c = kh + 2 * r;
+            if (i < w && c < nc) Bc[i + (long long)c * S.lda] = Bt[i][c];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ solve
@@ -185,6 +251,7 @@ __global__ __launch_bounds__(256) void k_btrsm(const BSys *__restrict__ sys, int
 // same per-element order as the single-system solve.  B lives in LDS.
 __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
     __shared__ double X[BMAX_N * BMAX_RHS];
+    __shared__ int piv[BMAX_N];
     const BSys S = sys[blockIdx.x];
     const int n = S.n, nr = S.nrhs;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -192,11 +259,12 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
         const int i = e % n, r = e / n;
         X[r * BMAX_N + i] = S.B[i + (long long)r * S.ldb];
     }
+    for (int c = t; c < n; c += blockDim.x) piv[c] = S.ipiv[c];
     __syncthreads();
     if (t < nr) {
         double *x = X + t * BMAX_N;
         for (int c = 0; c < n; ++c) {
-            const int p = S.ipiv[c] - 1;
+            const int p = piv[c] - 1;
             if (p > c && p < n) {
                 const double q = x[c];
                 x[c] = x[p];
@@ -213,9 +281,22 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
             double *x = X + wid * BMAX_N;
             const int i = k0 + lane;
             double b = lane < kb ? x[i] : 0.0;
-            for (int k = 0; k < kb - 1; ++k) {
-                const double xk = __shfl(b, k, 64);
-                if (lane > k && lane < kb) b = b - LU[i + (long long)(k0 + k) * lda] * xk;
+            // row i of the block in chunks of 16, each chunk's loads up front
+#pragma unroll
+            for (int kc = 0; kc < 64; kc += 16) {
+                double lrow[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    lrow[u] = (kc + u < kb && lane < kb)
+                                  ? LU[i + (long long)(k0 + kc + u) * lda] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int k = kc + u;
+                    if (k < kb - 1) {
+                        const double xk = __shfl(b, k, 64);
+                        if (lane > k && lane < kb) b = b - lrow[u] * xk;
+                    }
+                }
             }
             if (lane < kb) x[i] = b;
         }
@@ -224,7 +305,16 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
             const int i = k0 + kb + e % (n - k0 - kb), r = e / (n - k0 - kb);
             double *x = X + r * BMAX_N;
             double b = x[i];
-            for (int k = 0; k < kb; ++k) b = b - LU[i + (long long)(k0 + k) * lda] * x[k0 + k];
+#pragma unroll
+            for (int kc = 0; kc < 64; kc += 16) {
+                double l[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    l[u] = kc + u < kb ? LU[i + (long long)(k0 + kc + u) * lda] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (kc + u < kb) b = b - l[u] * x[k0 + kc + u];
+            }
             x[i] = b;
         }
         __syncthreads();
@@ -236,10 +326,22 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
             double *x = X + wid * BMAX_N;
             const int i = k0 + lane;
             double b = lane < kb ? x[i] : 0.0;
-            for (int k = kb - 1; k >= 0; --k) {
-                if (lane == k) b = b / LU[i + (long long)i * lda];
-                const double xk = __shfl(b, k, 64);
-                if (lane < k) b = b - LU[i + (long long)(k0 + k) * lda] * xk;
+#pragma unroll
+            for (int kc = 48; kc >= 0; kc -= 16) {
+                double urow[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    urow[u] = (kc + u < kb && lane < kb)
+                                  ? LU[i + (long long)(k0 + kc + u) * lda] : 0.0;
+#pragma unroll
+                for (int u = 15; u >= 0; --u) {
+                    const int k = kc + u;
+                    if (k < kb) {
+                        if (lane == k) b = b / urow[u];
+                        const double xk = __shfl(b, k, 64);
+                        if (lane < k) b = b - urow[u] * xk;
+                    }
+                }
             }
             if (lane < kb) x[i] = b;
         }
@@ -248,7 +350,16 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
             const int i = e % k0, r = e / k0;
             double *x = X + r * BMAX_N;
             double b = x[i];
-            for (int k = kb - 1; k >= 0; --k) b = b - LU[i + (long long)(k0 + k) * lda] * x[k0 + k];
+#pragma unroll
+            for (int kc = 48; kc >= 0; kc -= 16) {
+                double u[16];
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    u[v] = kc + v < kb ? LU[i + (long long)(k0 + kc + v) * lda] : 0.0;
+#pragma unroll
+                for (int v = 15; v >= 0; --v)
+                    if (kc + v < kb) b = b - u[v] * x[k0 + kc + v];
+            }
             x[i] = b;
         }
         __syncthreads();
@@ -432,20 +543,32 @@ static void plan_fill(BatchPlan &pl, const int *n, const int *nrhs, double *cons
     }
 }
 
+// Host staging of the descriptor tables: one pinned buffer (grown on
+// demand, guarded by g_bmu) mirroring the device layout [0, o_planes), so a
+// call uploads all tables with a single DMA instead of many staged copies
+// from pageable memory.
+static void *g_pinned = nullptr;
+static size_t g_pinned_bytes = 0;
+
 static int plan_upload(const BatchPlan &pl, char *base, hipStream_t st) {
-    EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_sys, pl.sys.data(), pl.sys.size() * sizeof(BSys),
-                               hipMemcpyHostToDevice, st));
-    if (!pl.gemm.empty()) {
-        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_gemm, pl.gemm.data(),
-                                   pl.gemm.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
-        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_gpre, pl.gprefix.data(),
-                                   pl.gprefix.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_jobs, pl.jobs.data(),
-                                   pl.jobs.size() * sizeof(SliceJob), hipMemcpyHostToDevice, st));
-        EMU_TRY_HIP(hipMemcpyAsync(base + pl.o_jpre, pl.jprefix.data(),
-                                   pl.jprefix.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    const size_t bytes = pl.o_planes;
+    if (bytes > g_pinned_bytes) {
+        if (g_pinned) EMU_TRY_HIP(hipHostFree(g_pinned));
+        g_pinned = nullptr;
+        g_pinned_bytes = 0;
+        EMU_TRY_HIP(hipHostMalloc(&g_pinned, bytes, hipHostMallocDefault));
+        g_pinned_bytes = bytes;
     }
-    // the host vectors are refilled on the next call: wait for the copies
+    char *h = static_cast<char *>(g_pinned);
+    std::memcpy(h + pl.o_sys, pl.sys.data(), pl.sys.size() * sizeof(BSys));
+    if (!pl.gemm.empty()) {
+        std::memcpy(h + pl.o_gemm, pl.gemm.data(), pl.gemm.size() * sizeof(GemmArgs));
+        std::memcpy(h + pl.o_gpre, pl.gprefix.data(), pl.gprefix.size() * sizeof(int));
+        std::memcpy(h + pl.o_jobs, pl.jobs.data(), pl.jobs.size() * sizeof(SliceJob));
+        std::memcpy(h + pl.o_jpre, pl.jprefix.data(), pl.jprefix.size() * sizeof(int));
+    }
+    EMU_TRY_HIP(hipMemcpyAsync(base, h, bytes, hipMemcpyHostToDevice, st));
+    // the staging buffer is refilled on the next call: wait for the copy
     EMU_TRY_HIP(hipStreamSynchronize(st));
     return 0;
 }
@@ -459,9 +582,10 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
         const int j0 = stp * pl.nb;
         const int act = pl.nact[stp];
         hipLaunchKernelGGL(k_bpanel, dim3(act), dim3(1024), 0, st, sys, j0, pl.nb);
-        const int cblocks = (pl.nmax + 255) / 256;
-        hipLaunchKernelGGL(k_blaswp, dim3(cblocks, act), dim3(256), 0, st, sys, j0, pl.nb);
-        hipLaunchKernelGGL(k_btrsm, dim3(cblocks, act), dim3(256), 0, st, sys, j0, pl.nb);
+        hipLaunchKernelGGL(k_blaswp, dim3((pl.nmax + BSW_COLS - 1) / BSW_COLS, act), dim3(256),
+                           0, st, sys, j0, pl.nb);
+        hipLaunchKernelGGL(k_btrsm, dim3((pl.nmax + BTR_COLS - 1) / BTR_COLS, act), dim3(64), 0,
+                           st, sys, j0, pl.nb);
         EMU_TRY_HIP(hipGetLastError());
         if (pl.g_cnt[stp] > 0) {
             const SliceJob *jobs = reinterpret_cast<const SliceJob *>(base + pl.o_jobs) +

@@ -77,4 +77,43 @@ __device__ __forceinline__ void block_key_best(long long &k, int &i, long long *
     key_best<NWAVES>(k, i);
 }
 
+// Composition of w <= 32 row interchanges k <-> p_k (k = 0..w-1 in order,
+// p_k >= k; rows relative to the first) by one wave: lane k holds pk = p_k
+// (any value for lanes >= w).  The rows they touch, at most 2w, get a lane
+// ("slot") each: slots 0..w-1 are rows 0..w-1, the others the distinct
+// pivot rows below them in order of first use.  The swaps are replayed on
+// the slot contents with lane broadcasts.  Returns the slot count; lane x
+// (x < count) gets srow, the row of slot x, and src, the row whose old
+// contents end up there.
+__device__ __forceinline__ int wave_compose32(int pk, int w, int &srow, int &src) {
+    const int lane = threadIdx.x & 63;
+    bool first = lane < w && pk >= w;            // first use of a row below the block
+    for (int k2 = 0; k2 < w; ++k2) {
+        const int pk2 = __builtin_amdgcn_readlane(pk, k2);
+        if (k2 < lane && pk2 == pk) first = false;
+    }
+    const unsigned long long fm = __ballot(first);
+    const int nslot = w + __popcll(fm);
+    const int myslot = w + __popcll(fm & ((1ull << lane) - 1ull));
+    int pslot = pk;                              // slot of row pk
+    srow = lane < w ? lane : -1;
+    for (int k2 = 0; k2 < w; ++k2) {
+        if (!((fm >> k2) & 1ull)) continue;      // uniform
+        const int r = __builtin_amdgcn_readlane(pk, k2);
+        const int sl = __builtin_amdgcn_readlane(myslot, k2);
+        if (lane < w && pk == r) pslot = sl;
+        if (lane == sl) srow = r;
+    }
+    int content = srow;
+    for (int k = 0; k < w; ++k) {
+        const int b = __builtin_amdgcn_readlane(pslot, k);
+        const int va = __builtin_amdgcn_readlane(content, k);
+        const int vb = __builtin_amdgcn_readlane(content, b);
+        if (lane == k) content = vb;
+        if (lane == b) content = va;
+    }
+    src = content;
+    return nslot;
+}
+
 }  // namespace emu

@@ -7,6 +7,7 @@
 // each element in increasing elimination order, so the solutions are
 // identical bit for bit to plain column-oriented substitution.
 #include "common.h"
+#include "devutil.h"
 
 namespace emu {
 
@@ -40,31 +41,8 @@ __device__ void compose_interchanges(int *pm, int R, int J, const int *__restric
             if (pk < lane || pk >= R - k0) pk = lane;
         }
         raw = lane < 32 && k0 + 32 + lane < J ? piv[k0 + 32 + lane] : 0;
-        bool first = lane < w && pk >= w;            // first use of a row below the block
-        for (int k2 = 0; k2 < w; ++k2) {
-            const int pk2 = __builtin_amdgcn_readlane(pk, k2);
-            if (k2 < lane && pk2 == pk) first = false;
-        }
-        const unsigned long long fm = __ballot(first);
-        const int nslot = w + __popcll(fm);
-        const int myslot = w + __popcll(fm & ((1ull << lane) - 1ull));
-        int pslot = pk;
-        int srow = lane < w ? lane : -1;
-        for (int k2 = 0; k2 < w; ++k2) {
-            if (!((fm >> k2) & 1ull)) continue;
-            const int r = __builtin_amdgcn_readlane(pk, k2);
-            const int sl = __builtin_amdgcn_readlane(myslot, k2);
-            if (lane < w && pk == r) pslot = sl;
-            if (lane == sl) srow = r;
-        }
-        int content = srow;
-        for (int k = 0; k < w; ++k) {
-            const int b = __builtin_amdgcn_readlane(pslot, k);
-            const int va = __builtin_amdgcn_readlane(content, k);
-            const int vb = __builtin_amdgcn_readlane(content, b);
-            if (lane == k) content = vb;
-            if (lane == b) content = va;
-        }
+        int srow, content;
+        const int nslot = wave_compose32(pk, w, srow, content);
         int v = 0;
         if (lane < nslot) v = pm[k0 + content];
         wave_sync_mem();

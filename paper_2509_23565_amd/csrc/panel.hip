@@ -310,34 +310,8 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
     const int t = threadIdx.x, lane = t & 63;
     __syncthreads();
     if (t < 64) {
-        const int pk = lane < w ? L.piv[lane] : -1;
-        // lane k: is pk (a row below the leaf's top w) seen here first?
-        bool first = lane < w && pk >= w;
-        for (int k2 = 0; k2 < w; ++k2) {
-            const int pk2 = __builtin_amdgcn_readlane(pk, k2);
-            if (k2 < lane && pk2 == pk) first = false;
-        }
-        const unsigned long long fm = __ballot(first);
-        const int nslot = w + __popcll(fm);
-        const int myslot = w + __popcll(fm & ((1ull << lane) - 1ull));
-        int pslot = pk;                          // slot of row pk
-        int srow = lane < w ? lane : -1;         // row of slot `lane`
-        for (int k2 = 0; k2 < w; ++k2) {
-            if (!((fm >> k2) & 1ull)) continue;  // uniform
-            const int r = __builtin_amdgcn_readlane(pk, k2);
-            const int sl = __builtin_amdgcn_readlane(myslot, k2);
-            if (lane < w && pk == r) pslot = sl;
-            if (lane == sl) srow = r;
-        }
-        // the interchanges in order on the slot contents
-        int content = srow;
-        for (int k = 0; k < w; ++k) {
-            const int b = __builtin_amdgcn_readlane(pslot, k);
-            const int va = __builtin_amdgcn_readlane(content, k);
-            const int vb = __builtin_amdgcn_readlane(content, b);
-            if (lane == k) content = vb;
-            if (lane == b) content = va;
-        }
+        int srow, content;
+        const int nslot = wave_compose32(lane < w ? L.piv[lane] : -1, w, srow, content);
         if (lane < 2 * LEAF_W) {
             L.srow[lane] = srow;
             L.ssrc[lane] = content;
