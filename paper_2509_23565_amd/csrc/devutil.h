@@ -50,12 +50,42 @@ __device__ __forceinline__ void key_xor_step(long long &k, int &i, int off) {
 // uniform); the levels across rows use lane shuffles.
 template <int W>
 __device__ __forceinline__ void key_best(long long &k, int &i) {
-    key_dpp_step<0xB1>(k, i);    // quad_perm [1, 0, 3, 2]
-    key_dpp_step<0x4E>(k, i);    // quad_perm [2, 3, 0, 1]
-    key_dpp_step<0x141>(k, i);   // row_half_mirror
-    key_dpp_step<0x140>(k, i);   // row_mirror
+    key_dpp_step<0xB1>(k, i);                                // quad_perm [1, 0, 3, 2]
+    if constexpr (W >= 4) key_dpp_step<0x4E>(k, i);          // quad_perm [2, 3, 0, 1]
+    if constexpr (W >= 8) key_dpp_step<0x141>(k, i);         // row_half_mirror
+    if constexpr (W >= 16) key_dpp_step<0x140>(k, i);        // row_mirror
     if constexpr (W >= 32) key_xor_step(k, i, 16);
     if constexpr (W >= 64) key_xor_step(k, i, 32);
+}
+
+// One level in which only the rows of ROWS (a 4-bit row mask) take a
+// partner through the DPP control CTRL; the other rows keep their value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void key_dpp_rows(long long &k, int &i) {
+    const int lo = __builtin_amdgcn_update_dpp((int)k, (int)k, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(k >> 32), (int)(k >> 32), CTRL, ROWS, 0xF,
+                                               false);
+    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWS, 0xF, false);
+    const long long ok = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    if (key_better(ok, oi, k, i)) {
+        k = ok;
+        i = oi;
+    }
+}
+
+// Best (key, row) of the whole wave, returned as wave-uniform values: the
+// four levels inside rows of 16 lanes, then lane 15 of rows 0 and 2 joins
+// rows 1 and 3 (row_bcast:15) and lane 31 joins rows 2 and 3
+// (row_bcast:31), which leaves the wave's best in lane 63.  No lane
+// shuffles through LDS.
+__device__ __forceinline__ void key_best_wave(long long &k, int &i) {
+    key_best<16>(k, i);
+    key_dpp_rows<0x142, 0xA>(k, i);
+    key_dpp_rows<0x143, 0xC>(k, i);
+    const int lo = __builtin_amdgcn_readlane((int)k, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(k >> 32), 63);
+    i = __builtin_amdgcn_readlane(i, 63);
+    k = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // Best (key, row) over a workgroup of NWAVES waves (a power of two up to 16,

@@ -16,8 +16,8 @@
 //     order-preserving FP64 tile kernel (k_gemm_seq: for each k in order,
 //     c = c - a_ik b_kj), factors the right part, and moves the left part's
 //     rows by the right part's interchanges;
-//   * leaves of at most 16 columns, the block in registers (2 rows x 16
-//     columns per thread, 2048 rows per 1024-thread workgroup).  Each column
+//   * leaves of at most 16 columns, the block in registers (4 rows x 16
+//     columns per thread, 2048 rows per 512-thread workgroup).  Each column
 //     costs one workgroup barrier: every wave publishes its pivot candidate
 //     together with a copy of the candidate row (and the owner of row c a
 //     copy of row c) into a double-buffered LDS slot, so after the barrier
@@ -35,9 +35,9 @@
 namespace emu {
 
 constexpr int LEAF_W = 16;
-constexpr int LF_THREADS = 1024;
+constexpr int LF_THREADS = 512;
 constexpr int LF_WAVES = LF_THREADS / 64;
-constexpr int LF_R = 2;                        // rows per thread
+constexpr int LF_R = 4;                        // rows per thread
 constexpr int LF_ROWS = LF_THREADS * LF_R;     // rows per workgroup
 constexpr int LF_MAX_G = 32;                   // workgroups of one leaf (65536 rows)
 constexpr int LF_SPIN_LIMIT = 1 << 20;         // polls of one grid-wide wait
@@ -96,48 +96,59 @@ struct LeafLds {
     int nslot;
 };
 
+// Wave-uniform copy of a double held in a VGPR.
+__device__ __forceinline__ double uniform_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
 // Column c of a leaf: pivot search, interchange, scaling, rank-1 update of
 // this thread's rows.  Returns false when a multi-workgroup wait aborted.
+// Every decision that depends on the pivot is taken on wave-uniform values,
+// so the branches are scalar and each wave issues only the work of its rows.
 template <bool MULTI, int c>
 __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows,
                                          int base_row, int g, int *ipiv, int grow0, int *info,
                                          const LeafX &x, unsigned base) {
-    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(t >> 6);
     constexpr int buf = c & 1;
-    // this thread's and this wave's candidate for column c
-    long long bv = -1;
+    // this thread's candidate (rows c <= i < rows), then the wave's
+    long long bk = -1;
     int bi = INT_MAX;
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * LF_THREADS;
-        if (i >= c && i < rows) {
-            const long long kq = pivot_key(v[q][c]);
-            if (key_better(kq, i, bv, bi)) {
-                bv = kq;
-                bi = i;
-            }
+        const long long kq = (i >= c && i < rows) ? pivot_key(v[q][c]) : -1;
+        if (key_better(kq, i, bk, bi)) {
+            bk = kq;
+            bi = i;
         }
     }
-    key_best<64>(bv, bi);
+    key_best_wave(bk, bi);
+    // the wave's candidate row, and row c (thread c of workgroup 0), to LDS
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
-        const int i = base_row + t + q * LF_THREADS;
-        if (i == bi)
+        if (base_row + t + q * LF_THREADS == bi)
 #pragma unroll
             for (int j = 0; j < LEAF_W; ++j) L.row[buf][wid][j] = v[q][j];
-        if (i == c)
-#pragma unroll
-            for (int j = 0; j < LEAF_W; ++j) L.xrow[buf][j] = v[q][j];
     }
+    if (g == 0 && wid == 0 && lane == c)
+#pragma unroll
+        for (int j = 0; j < LEAF_W; ++j) L.xrow[buf][j] = v[0][j];
     if (lane == 0) {
-        L.val[buf][wid] = bv;
+        L.val[buf][wid] = bk;
         L.idx[buf][wid] = bi;
     }
     __syncthreads();
     // the workgroup's winner (every wave computes it)
-    long long wv = L.val[buf][lane & (LF_WAVES - 1)];
+    long long wk = L.val[buf][lane & (LF_WAVES - 1)];
     int wi = L.idx[buf][lane & (LF_WAVES - 1)];
-    key_best<LF_WAVES>(wv, wi);
+    key_best<LF_WAVES>(wk, wi);
+    wi = __builtin_amdgcn_readfirstlane(wi);
     int p;
     const double *ur, *xr;
     if constexpr (!MULTI) {
@@ -147,6 +158,10 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     } else {
         const int G = (int)gridDim.x;
         if (wid == 0) {
+            const long long wkv = (long long)(((unsigned long long)(unsigned)
+                                                   __builtin_amdgcn_readfirstlane((int)(wk >> 32))
+                                               << 32) |
+                                              (unsigned)__builtin_amdgcn_readfirstlane((int)wk));
             const unsigned long long tag = (unsigned long long)(base + (unsigned)c + 1u) << 32;
             // publish: words 0..35 (and 36..67 from workgroup 0), tagged
             unsigned long long *mine = x.rec + ((long long)buf * LF_MAX_G + g) * RW;
@@ -154,9 +169,9 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
             for (int e = lane; e < (g == 0 ? RW : RW_MAIN); e += 64) {
                 unsigned pl;
                 if (e == 0) {
-                    pl = (unsigned)((unsigned long long)wv >> 32);
+                    pl = (unsigned)((unsigned long long)wkv >> 32);
                 } else if (e == 1) {
-                    pl = (unsigned)(unsigned long long)wv;
+                    pl = (unsigned)(unsigned long long)wkv;
                 } else if (e == 2) {
                     pl = (unsigned)wi;
                 } else if (e == 3) {
@@ -246,39 +261,52 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         }
         __syncthreads();
         if (L.abort) return false;
-        p = L.p[buf];
+        p = __builtin_amdgcn_readfirstlane(L.p[buf]);
         const int gp = (p >= 0 && p < G * LF_ROWS) ? p / LF_ROWS : 0;
         ur = L.grow[buf][gp];
         xr = L.xr[buf];
     }
-    const double piv = ur[c];
+    // the pivot row (every lane reads the same LDS words)
+    double pr[LEAF_W];
+#pragma unroll
+    for (int j = 0; j < LEAF_W; ++j) pr[j] = ur[j];
+    const double piv = uniform_f64(pr[c]);
     if (t == 0) L.piv[c] = p;
     if (g == 0 && t == 0) {
         ipiv[c] = grow0 + p + 1;
         if (piv == 0.0 && *info == 0) *info = grow0 + c + 1;
     }
-    const bool swap = piv != 0.0 && p != c;
+    if (piv != 0.0 && p != c) {
+        // interchange: row c receives the pivot row, row p the old row c
+        if (g == 0 && wid == 0 && lane == c)
+#pragma unroll
+            for (int j = 0; j < LEAF_W; ++j) v[0][j] = pr[j];
+        const int tp = p - base_row;
+        if (tp >= 0 && tp < LF_ROWS && wid == (tp % LF_THREADS) / 64) {
+#pragma unroll
+            for (int q = 0; q < LF_R; ++q) {
+                if (base_row + t + q * LF_THREADS == p)
+#pragma unroll
+                    for (int j = 0; j < LEAF_W; ++j) v[q][j] = xr[j];
+            }
+        }
+    }
     // row c after the interchange (the old row c when the pivot is zero)
-    const double *u = (piv != 0.0) ? ur : xr;
+    if (piv == 0.0) {
+#pragma unroll
+        for (int j = c + 1; j < LEAF_W; ++j) pr[j] = xr[j];
+    }
     const bool recip = fabs(piv) >= DBL_MIN;
     const double rp = 1.0 / piv;
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * LF_THREADS;
-        if (i < c || i >= rows) continue;
-        if (swap && i == c) {
-#pragma unroll
-            for (int j = 0; j < LEAF_W; ++j) v[q][j] = ur[j];
-        } else if (swap && i == p) {
-#pragma unroll
-            for (int j = 0; j < LEAF_W; ++j) v[q][j] = xr[j];
-        }
-        if (i > c) {
+        if (q > 0 || i > c) {
             double l = v[q][c];
             if (piv != 0.0) l = recip ? l * rp : l / piv;
             v[q][c] = l;
 #pragma unroll
-            for (int j = c + 1; j < LEAF_W; ++j) v[q][j] = v[q][j] - l * u[j];
+            for (int j = c + 1; j < LEAF_W; ++j) v[q][j] = v[q][j] - l * pr[j];
         }
     }
     return true;
@@ -304,7 +332,7 @@ __device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L,
 // into one permutation of at most 2w rows by wave 0 (lane x = slot x);
 // then every workgroup moves its share of the columns, all reads of a round
 // before any write.  Called after the leaf's last column (L.piv complete).
-constexpr int SWAP_ROUND = 8;       // 32-column passes per read/write round
+constexpr int SWAP_ROUND = 8;       // passes per read/write round
 __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int ncr,
                                  LeafLds &L, int g, int G) {
     const int t = threadIdx.x, lane = t & 63;
@@ -320,16 +348,17 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
     }
     __syncthreads();
     const int nslot = L.nslot;
-    const int x = t & 31, jj = t >> 5;           // slot, column within a 32-column pass
+    constexpr int CPP = LF_THREADS / 32;        // columns per pass
+    const int x = t & 31, jj = t >> 5;           // slot, column within a pass
     const int nc = ncl + ncr;
     const int srow = x < nslot ? L.srow[x] : 0;
     const int ssrc = x < nslot ? L.ssrc[x] : 0;
     const bool moves = x < nslot && srow != ssrc;
-    for (int j0 = g * 32; j0 < nc; j0 += 32 * G * SWAP_ROUND) {
+    for (int j0 = g * CPP; j0 < nc; j0 += CPP * G * SWAP_ROUND) {
         double vals[SWAP_ROUND];
 #pragma unroll
         for (int r = 0; r < SWAP_ROUND; ++r) {
-            const int j = j0 + r * 32 * G + jj;
+            const int j = j0 + r * CPP * G + jj;
             vals[r] = 0.0;
             if (moves && j < nc) {
                 const double *col = j < ncl ? P + (long long)(j - ncl) * lda
@@ -340,7 +369,7 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < SWAP_ROUND; ++r) {
-            const int j = j0 + r * 32 * G + jj;
+            const int j = j0 + r * CPP * G + jj;
             if (moves && j < nc) {
                 double *col = j < ncl ? P + (long long)(j - ncl) * lda
                                       : P + (long long)(w + j - ncl) * lda;
@@ -353,7 +382,7 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
 
 // P: top-left of the leaf (global row grow0), rows x w, w <= 16, rows >= w.
 // Workgroup g owns rows [2048 g, 2048 g + 2048): thread t rows
-// 2048 g + t and 2048 g + t + 1024.  MULTI: launched cooperatively; the
+// 2048 g + t + 512 q, q = 0..3.  MULTI: launched cooperatively; the
 // records of column c carry sequence number base + c + 1.
 template <bool MULTI>
 __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, long long lda,
