@@ -94,6 +94,7 @@ struct LeafLds {
     int srow[2 * LEAF_W];     // panel-row interchanges: row of each slot
     int ssrc[2 * LEAF_W];     // and the row whose old values it receives
     int nslot;
+    int zc;                   // first column with a zero pivot (w if none)
 };
 
 // Wave-uniform copy of a double held in a VGPR.
@@ -105,34 +106,104 @@ __device__ __forceinline__ double uniform_f64(double v) {
                                             (unsigned)lo));
 }
 
+// x of the lane that the DPP control CTRL names (rows outside ROWS keep x).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROWS, 0xF,
+                                               false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
+// Largest x of the wave, NaN ignored (fmax), as a wave-uniform value: four
+// butterfly levels inside rows of 16 lanes, then the row broadcasts that
+// leave the maximum in lane 63.
+__device__ __forceinline__ double wave_max_f64(double x) {
+    x = fmax(x, dpp_f64<0xB1, 0xF>(x));      // quad_perm [1, 0, 3, 2]
+    x = fmax(x, dpp_f64<0x4E, 0xF>(x));      // quad_perm [2, 3, 0, 1]
+    x = fmax(x, dpp_f64<0x141, 0xF>(x));     // row_half_mirror
+    x = fmax(x, dpp_f64<0x140, 0xF>(x));     // row_mirror
+    x = fmax(x, dpp_f64<0x142, 0xA>(x));     // row_bcast:15 into rows 1, 3
+    x = fmax(x, dpp_f64<0x143, 0xC>(x));     // row_bcast:31 into rows 2, 3
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
+// Double j (0..15) of the 16-double row r (0..7) of an LDS block that lane l
+// holds as doubles 2l and 2l + 1 (see leaf_col): wave-uniform.
+__device__ __forceinline__ double row_elem(double e0, double e1, int r, int j) {
+    const double e = (j & 1) ? e1 : e0;
+    const long long b = __double_as_longlong(e);
+    const int src = r * (LEAF_W / 2) + (j >> 1);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
 // Column c of a leaf: pivot search, interchange, scaling, rank-1 update of
 // this thread's rows.  Returns false when a multi-workgroup wait aborted.
 // Every decision that depends on the pivot is taken on wave-uniform values,
 // so the branches are scalar and each wave issues only the work of its rows.
-template <bool MULTI, int c>
+//
+// Pivot search inside a wave: the largest magnitude M by a DPP maximum over
+// doubles, then one ballot per row slot q for "valid and |x| == M" (and one
+// for NaN, which ranks first); rows are numbered q-major, so the smallest
+// row is the lowest set bit of the first non-empty mask.  The wave's
+// candidate is published with the key of the pivot order (the magnitude's
+// bits, NaN above +inf, -1 for none).
+template <bool MULTI, int k>
 __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows,
-                                         int base_row, int g, int *ipiv, int grow0, int *info,
-                                         const LeafX &x, unsigned base) {
+                                         int base_row, int g, const LeafX &x, unsigned base,
+                                         int b) {
+    const int c = b + k;                  // column of the leaf, at position k of v
+    const int lim = LEAF_W - b;           // positions [lim, 16) hold finished columns
     const int t = threadIdx.x, lane = t & 63;
     const int wid = __builtin_amdgcn_readfirstlane(t >> 6);
-    constexpr int buf = c & 1;
-    // this thread's candidate (rows c <= i < rows), then the wave's
-    long long bk = -1;
-    int bi = INT_MAX;
+    constexpr int buf = k & 1;
+    // this wave's candidate
+    double m = -1.0;
+    bool valid[LF_R];
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * LF_THREADS;
-        const long long kq = (i >= c && i < rows) ? pivot_key(v[q][c]) : -1;
-        if (key_better(kq, i, bk, bi)) {
-            bk = kq;
-            bi = i;
-        }
+        valid[q] = i >= c && i < rows;
+        if (valid[q]) m = fmax(m, fabs(v[q][k]));
     }
-    key_best_wave(bk, bi);
-    // the wave's candidate row, and row c (thread c of workgroup 0), to LDS
+    const double M = wave_max_f64(m);
+    int qb = -1;
+    unsigned long long mask = 0ull;
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
-        if (base_row + t + q * LF_THREADS == bi)
+        const unsigned long long nm = __ballot(valid[q] && __builtin_isnan(v[q][k]));
+        if (qb < 0 && nm != 0ull) {
+            qb = q;
+            mask = nm;
+        }
+    }
+    const bool wnan = qb >= 0;
+    if (!wnan) {
+#pragma unroll
+        for (int q = 0; q < LF_R; ++q) {
+            const unsigned long long mm = __ballot(valid[q] && fabs(v[q][k]) == M);
+            if (qb < 0 && mm != 0ull) {
+                qb = q;
+                mask = mm;
+            }
+        }
+    }
+    const int lb = qb >= 0 ? __builtin_ctzll(mask) : 0;
+    const long long bk = qb < 0 ? -1ll : wnan ? 0x7FF8000000000000ll : __double_as_longlong(M);
+    const int bi = qb < 0 ? INT_MAX : base_row + qb * LF_THREADS + wid * 64 + lb;
+    // the candidate row, and row c (thread c of workgroup 0), to LDS
+#pragma unroll
+    for (int q = 0; q < LF_R; ++q) {
+        if (q == qb && lane == lb)
 #pragma unroll
             for (int j = 0; j < LEAF_W; ++j) L.row[buf][wid][j] = v[q][j];
     }
@@ -144,16 +215,27 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         L.idx[buf][wid] = bi;
     }
     __syncthreads();
-    // the workgroup's winner (every wave computes it)
+    // the workgroup's winner, and with it (single workgroup) the pivot row:
+    // lane l reads doubles 2l, 2l + 1 of the candidate rows, the winner's
+    // are then taken with lane reads into scalar registers
     long long wk = L.val[buf][lane & (LF_WAVES - 1)];
     int wi = L.idx[buf][lane & (LF_WAVES - 1)];
+    double pr[LEAF_W];
+    double e0 = 0.0, e1 = 0.0;
+    if constexpr (!MULTI) {
+        const double *flat = &L.row[buf][0][0];
+        e0 = flat[2 * lane];
+        e1 = flat[2 * lane + 1];
+    }
     key_best<LF_WAVES>(wk, wi);
     wi = __builtin_amdgcn_readfirstlane(wi);
     int p;
-    const double *ur, *xr;
+    const double *xr;
     if constexpr (!MULTI) {
         p = wi;
-        ur = L.row[buf][((p - base_row) % LF_THREADS) / 64];
+        const int wr = ((p - base_row) % LF_THREADS) / 64;
+#pragma unroll
+        for (int j = 0; j < LEAF_W; ++j) pr[j] = row_elem(e0, e1, wr, j);
         xr = L.xrow[buf];
     } else {
         const int G = (int)gridDim.x;
@@ -166,6 +248,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
             // publish: words 0..35 (and 36..67 from workgroup 0), tagged
             unsigned long long *mine = x.rec + ((long long)buf * LF_MAX_G + g) * RW;
             const double *wrow = L.row[buf][((wi - base_row) % LF_THREADS) / 64];
+#pragma unroll 1
             for (int e = lane; e < (g == 0 ? RW : RW_MAIN); e += 64) {
                 unsigned pl;
                 if (e == 0) {
@@ -193,14 +276,15 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
             int spins = 0;
             for (;;) {
                 bool ok = true;
+#pragma unroll 1
                 for (int e0 = 0; e0 < nw; e0 += 4 * 64) {
                     unsigned long long wd[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int e = e0 + u * 64 + lane;
                         const int sl = e < RW_MAIN * G ? e / RW_MAIN : 0;
-                        const int k = e < RW_MAIN * G ? e % RW_MAIN : RW_MAIN + (e - RW_MAIN * G);
-                        wd[u] = e < nw ? __hip_atomic_load(recs + (long long)sl * RW + k,
+                        const int wo = e < RW_MAIN * G ? e % RW_MAIN : RW_MAIN + (e - RW_MAIN * G);
+                        wd[u] = e < nw ? __hip_atomic_load(recs + (long long)sl * RW + wo,
                                                            __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT)
                                        : tag;
@@ -215,11 +299,11 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                         }
                         const unsigned pl = (unsigned)wd[u];
                         if (e < RW_MAIN * G) {
-                            const int sl = e / RW_MAIN, k = e % RW_MAIN;
-                            if (k < 3)
-                                L.gkey[buf][sl][k] = pl;
-                            else if (k >= 4)
-                                grow_w[sl * 2 * LEAF_W + (k - 4)] = pl;
+                            const int sl = e / RW_MAIN, wo = e % RW_MAIN;
+                            if (wo < 3)
+                                L.gkey[buf][sl][wo] = pl;
+                            else if (wo >= 4)
+                                grow_w[sl * 2 * LEAF_W + (wo - 4)] = pl;
                         } else {
                             xr_w[e - RW_MAIN * G] = pl;
                         }
@@ -263,18 +347,21 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         if (L.abort) return false;
         p = __builtin_amdgcn_readfirstlane(L.p[buf]);
         const int gp = (p >= 0 && p < G * LF_ROWS) ? p / LF_ROWS : 0;
-        ur = L.grow[buf][gp];
+        // the grid winner's row: lane l < 32 reads word l, lane reads make
+        // it wave-uniform (scalar registers)
+        const unsigned ew = reinterpret_cast<const unsigned *>(L.grow[buf][gp])[lane & 31];
+#pragma unroll
+        for (int j = 0; j < LEAF_W; ++j) {
+            const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)ew, 2 * j);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)ew, 2 * j + 1);
+            pr[j] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+        }
         xr = L.xr[buf];
     }
-    // the pivot row (every lane reads the same LDS words)
-    double pr[LEAF_W];
-#pragma unroll
-    for (int j = 0; j < LEAF_W; ++j) pr[j] = ur[j];
-    const double piv = uniform_f64(pr[c]);
-    if (t == 0) L.piv[c] = p;
-    if (g == 0 && t == 0) {
-        ipiv[c] = grow0 + p + 1;
-        if (piv == 0.0 && *info == 0) *info = grow0 + c + 1;
+    const double piv = pr[k];
+    if (t == 0) {
+        L.piv[c] = p;
+        if (piv == 0.0 && L.zc > c) L.zc = c;
     }
     if (piv != 0.0 && p != c) {
         // interchange: row c receives the pivot row, row p the old row c
@@ -294,36 +381,85 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     // row c after the interchange (the old row c when the pivot is zero)
     if (piv == 0.0) {
 #pragma unroll
-        for (int j = c + 1; j < LEAF_W; ++j) pr[j] = xr[j];
+        for (int j = k + 1; j < LEAF_W; ++j) pr[j] = xr[j];
     }
+    // multipliers (rows below c), then the rank-1 update of positions
+    // k + 1 .. lim - 1 (rows at or above c keep theirs: l = 0 is not used,
+    // so that signed zeros and non-finite pivots rows stay untouched)
     const bool recip = fabs(piv) >= DBL_MIN;
     const double rp = 1.0 / piv;
+    double lq[LF_R];
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
-        const int i = base_row + t + q * LF_THREADS;
-        if (q > 0 || i > c) {
-            double l = v[q][c];
-            if (piv != 0.0) l = recip ? l * rp : l / piv;
-            v[q][c] = l;
+        double l = v[q][k];
+        if (piv != 0.0) l = recip ? l * rp : l / piv;
+        lq[q] = l;
+    }
+    const bool upd0 = base_row + t > c;    // rows of q = 0 below c (q > 0: always)
+    if (upd0) v[0][k] = lq[0];
 #pragma unroll
-            for (int j = c + 1; j < LEAF_W; ++j) v[q][j] = v[q][j] - l * pr[j];
+    for (int q = 1; q < LF_R; ++q) v[q][k] = lq[q];
+#pragma unroll
+    for (int j = k + 1; j < LEAF_W; ++j) {
+        if (j < lim) {
+            const double u = pr[j];
+            if (upd0) v[0][j] = v[0][j] - lq[0] * u;
+#pragma unroll
+            for (int q = 1; q < LF_R; ++q) v[q][j] = v[q][j] - lq[q] * u;
         }
     }
     return true;
 }
 
-template <bool MULTI, int c>
-__device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows,
-                                          int w, int base_row, int g, int *ipiv, int grow0,
-                                          int *info, const LeafX &x, unsigned base) {
-    if constexpr (c < LEAF_W) {
-        if (c >= w) return true;
-        if (!leaf_col<MULTI, c>(v, L, rows, base_row, g, ipiv, grow0, info, x, base))
-            return false;
-        return leaf_cols<MULTI, c + 1>(v, L, rows, w, base_row, g, ipiv, grow0, info, x, base);
+// The four columns b..b+3 of a group (positions 0..3 of v).
+template <bool MULTI, int k>
+__device__ __forceinline__ bool leaf_group(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows,
+                                           int w, int base_row, int g, const LeafX &x,
+                                           unsigned base, int b) {
+    if constexpr (k < 4) {
+        if (b + k >= w) return true;
+        if (!leaf_col<MULTI, k>(v, L, rows, base_row, g, x, base, b)) return false;
+        return leaf_group<MULTI, k + 1>(v, L, rows, w, base_row, g, x, base, b);
     } else {
         return true;
     }
+}
+
+// All columns of a leaf: a loop over groups of four columns, each followed
+// by a rotation of every row by four positions, so that the loop body names
+// its columns by fixed positions (registers) and stays small enough to run
+// from the instruction cache; four rotations restore the order.
+template <bool MULTI>
+__device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows, int w,
+                                          int base_row, int g, const LeafX &x, unsigned base) {
+    bool ok = true;
+#pragma unroll 1
+    for (int b = 0; b < LEAF_W; b += 4) {
+        if (b > 0) {
+#pragma unroll
+            for (int q = 0; q < LF_R; ++q) {
+                const double r0 = v[q][0], r1 = v[q][1], r2 = v[q][2], r3 = v[q][3];
+#pragma unroll
+                for (int j = 0; j < LEAF_W - 4; ++j) v[q][j] = v[q][j + 4];
+                v[q][LEAF_W - 4] = r0;
+                v[q][LEAF_W - 3] = r1;
+                v[q][LEAF_W - 2] = r2;
+                v[q][LEAF_W - 1] = r3;
+            }
+        }
+        if (ok && b < w) ok = leaf_group<MULTI, 0>(v, L, rows, w, base_row, g, x, base, b);
+    }
+#pragma unroll
+    for (int q = 0; q < LF_R; ++q) {
+        const double r0 = v[q][0], r1 = v[q][1], r2 = v[q][2], r3 = v[q][3];
+#pragma unroll
+        for (int j = 0; j < LEAF_W - 4; ++j) v[q][j] = v[q][j + 4];
+        v[q][LEAF_W - 4] = r0;
+        v[q][LEAF_W - 3] = r1;
+        v[q][LEAF_W - 2] = r2;
+        v[q][LEAF_W - 1] = r3;
+    }
+    return ok;
 }
 
 // The leaf's interchanges applied to the other columns of its panel: ncl
@@ -393,7 +529,10 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
     const int t = threadIdx.x;
     const int g = MULTI ? (int)blockIdx.x : 0;
     const int base_row = g * LF_ROWS;
-    if (t == 0) L.abort = 0;
+    if (t == 0) {
+        L.abort = 0;
+        L.zc = w;
+    }
     double v[LF_R][LEAF_W];
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
@@ -402,7 +541,7 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
         for (int j = 0; j < LEAF_W; ++j)
             v[q][j] = (i < rows && j < w) ? P[i + (long long)j * lda] : 0.0;
     }
-    if (!leaf_cols<MULTI, 0>(v, L, rows, w, base_row, g, ipiv, grow0, info, x, base)) return;
+    if (!leaf_cols<MULTI>(v, L, rows, w, base_row, g, x, base)) return;
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * LF_THREADS;
@@ -410,6 +549,12 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
 #pragma unroll
             for (int j = 0; j < LEAF_W; ++j)
                 if (j < w) P[i + (long long)j * lda] = v[q][j];
+    }
+    // pivot indices and the first zero pivot, once per leaf
+    __syncthreads();
+    if (g == 0) {
+        if (t < w) ipiv[t] = grow0 + L.piv[t] + 1;
+        if (t == 0 && L.zc < w && *info == 0) *info = grow0 + L.zc + 1;
     }
     if (ncl + ncr > 0) leaf_panel_swaps(P, lda, w, ncl, ncr, L, g, MULTI ? (int)gridDim.x : 1);
 }
