@@ -162,6 +162,11 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
  *   library-owned side stream of the device while that panel is factored;
  *   the caller's stream waits for it, so the call stays ordered on the
  *   caller's stream.  The factors are identical either way.
+ *   "leaf_cooperative" (0 or 1, default 0): panel leaves taller than 2048
+ *   rows (several workgroups that wait for each other) are launched with
+ *   hipLaunchCooperativeKernel instead of a plain launch.  The factors are
+ *   identical either way; the plain launch avoids the cooperative launch's
+ *   fixed cost.
  * Returns -1 for an unknown key, -2 for an invalid value.
  */
 int emu_set_param(const char *key, long long value);

@@ -528,6 +528,11 @@ int emu_set_param(const char *key, long long value) {
         g_ir_force_fail = (int)value;
         return 0;
     }
+    if (std::strcmp(key, "leaf_cooperative") == 0) {
+        if (value != 0 && value != 1) return -2;
+        set_leaf_cooperative((int)value);
+        return 0;
+    }
     if (std::strcmp(key, "lu_lookahead") == 0) {
         if (value != 0 && value != 1) return -2;
         g_lu_lookahead = (int)value;

@@ -154,6 +154,8 @@ int launch_fill_int(int *p, int v, int count, hipStream_t stream);
 // A (global row/column row0); ws: panel_scratch_bytes(rows) bytes; status:
 // the device status word (EMU_STATUS_PANEL_WAIT on an aborted tall leaf).
 size_t panel_scratch_bytes(int rows);
+// Launch multi-workgroup panel leaves cooperatively (process-wide switch).
+void set_leaf_cooperative(int on);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
                  int row0, int *info, char *ws, int *status, hipStream_t stream);
 // Interchanges ipiv[k1..k2) on columns [0, ncols_left) and [col_right,

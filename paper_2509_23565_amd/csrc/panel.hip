@@ -22,11 +22,10 @@
 //     together with a copy of the candidate row (and the owner of row c a
 //     copy of row c) into a double-buffered LDS slot, so after the barrier
 //     every wave picks the winner and reads both rows without a second
-//     round.  Leaves taller than 2048 rows run as one cooperative launch of
-//     up to 32 workgroups that exchange their candidates the same way
-//     through global memory, with one grid-wide wait per column (bounded:
-//     a wait that exceeds its bound aborts the leaf and raises
-//     EMU_STATUS_PANEL_WAIT).
+//     round.  Leaves taller than 2048 rows run as one launch of up to 32
+//     workgroups that exchange their candidates the same way through global
+//     memory, with one grid-wide wait per column (bounded: a wait that
+//     exceeds its bound aborts the leaf and raises EMU_STATUS_PANEL_WAIT).
 #include "common.h"
 #include "devutil.h"
 
@@ -518,8 +517,8 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
 
 // P: top-left of the leaf (global row grow0), rows x w, w <= 16, rows >= w.
 // Workgroup g owns rows [2048 g, 2048 g + 2048): thread t rows
-// 2048 g + t + 512 q, q = 0..3.  MULTI: launched cooperatively; the
-// records of column c carry sequence number base + c + 1.
+// 2048 g + t + 512 q, q = 0..3.  MULTI: the workgroups of one leaf run
+// together; the records of column c carry sequence number base + c + 1.
 template <bool MULTI>
 __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, long long lda,
                                                      int rows, int w, int *ipiv, int grow0,
@@ -748,6 +747,15 @@ struct PanelRun {
     unsigned arrivals;
 };
 
+// Multi-workgroup leaves are plain launches unless this is set.  Their
+// G <= 32 workgroups need G compute units at once; work that already holds
+// compute units (the look-ahead updates on the side stream) runs to its end
+// without them, so a workgroup that waits for one not yet started waits at
+// most that long, well inside the bounded wait.  A cooperative launch gives
+// the same guarantee at a cost of tens of microseconds per launch.
+static bool g_leaf_cooperative = false;
+void set_leaf_cooperative(int on) { g_leaf_cooperative = on != 0; }
+
 static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0, int *info,
                 int ncl, int ncr, PanelRun &pr, hipStream_t st) {
     LeafX x = leaf_x(pr.ws, pr.status);
@@ -763,9 +771,15 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
         return EMU_ERR_UNSUPPORTED;
     }
     unsigned base = pr.arrivals;
-    void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
-    EMU_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_leaf<true>),
-                                           dim3(G), dim3(LF_THREADS), args, 0, st));
+    if (g_leaf_cooperative) {
+        void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
+        EMU_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_leaf<true>),
+                                               dim3(G), dim3(LF_THREADS), args, 0, st));
+    } else {
+        hipLaunchKernelGGL(k_leaf<true>, dim3(G), dim3(LF_THREADS), 0, st, P, lda, rows, w, ipiv,
+                           grow0, info, x, base, ncl, ncr);
+        EMU_TRY_HIP(hipGetLastError());
+    }
     pr.arrivals += (unsigned)w;
     return 0;
 }

@@ -47,6 +47,22 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // s_waitcnt immediate for gfx9: vmcnt(0), expcnt/lgkmcnt unconstrained.
 constexpr int WAIT_VMCNT0 = 0x0F70;
 
+// One 1 KB fragment global -> LDS by the calling wave (16 bytes per lane,
+// lane l's bytes at lds + 16 l).  Written as inline assembly so that the
+// compiler's wait-count bookkeeping does not see an LDS-writing memory
+// operation: with one in a loop it waits for every outstanding LDS read
+// before each MFMA group.  The kernels wait for these loads explicitly
+// (vmcnt(0) before the barrier that publishes the buffer).
+__device__ __forceinline__ void dma_frag(const int8_t *gsrc, int8_t *lds) {
+    const unsigned dst = (unsigned)(uintptr_t)(__attribute__((address_space(3))) int8_t *)lds;
+    asm volatile("s_mov_b32 m0, %1\n\t"
+                 "s_nop 0\n\t"
+                 "global_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(gsrc), "s"(__builtin_amdgcn_readfirstlane(dst))
+                 : "memory", "m0");
+}
+
 // ------------------------------------------------------------- diagonals
 __host__ __device__ constexpr int diag_pairs(int s, int g) {
     int lo = g - s > 1 ? g - s : 1;
@@ -152,9 +168,7 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
         for (int q = 0; q < (FR + NW - 1) / NW; ++q) {
             const int f = q * NW + w;
             if (f < FR)
-                __builtin_amdgcn_global_load_lds(
-                    (const void *)(src[q] + (size_t)kb * FRAG_BYTES),
-                    (void *)(buf + f * FRAG_BYTES), 16, 0, 0);
+                dma_frag(src[q] + (size_t)kb * FRAG_BYTES, buf + f * FRAG_BYTES);
         }
     };
 

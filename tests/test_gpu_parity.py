@@ -225,6 +225,24 @@ def test_getrf_lookahead_changes_no_bit(m, n, nb, s):
     assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
 
 
+def test_getrf_cooperative_leaves_change_no_bit():
+    # tall leaves (several workgroups) launched cooperatively against the
+    # plain launch; both with the look-ahead running beside them
+    m, n, nb, s = 6000, 700, 128, 3
+    A = emu.colmajor(matgen.phi_matrix(m, n, 1.0, seed=23))
+    A0 = A.clone()
+    try:
+        emu.set_param("leaf_cooperative", 1)
+        ip0, inf0 = emu.dgetrf(A0, nb=nb, nslices=s)
+    finally:
+        emu.set_param("leaf_cooperative", 0)
+    assert emu.status() == 0
+    ip1, inf1 = emu.dgetrf(A, nb=nb, nslices=s)
+    assert emu.status() == 0
+    assert torch.equal(ip0, ip1) and torch.equal(inf0, inf1)
+    assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
+
+
 def _same_or_both_nan(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
