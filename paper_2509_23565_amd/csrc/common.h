@@ -80,6 +80,27 @@ inline Planes plane_geom(int lines, int k) {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Last q in [0, n) with prefix[q] <= x, for a non-decreasing prefix with
+// prefix[0] <= x (so entries of empty items are skipped): a 64-ary search by
+// the calling wave (all lanes active, x and n wave-uniform).  Each level reads
+// 64 entries at once and keeps the interval after the last one <= x, so n
+// up to 4096 takes two dependent reads instead of twelve.
+__device__ __forceinline__ int wave_search(const int *prefix, int n, int x) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int step = (hi - lo + 64) / 64;          // 64 lanes cover [lo, hi]
+        const int q = lo + lane * step;
+        const bool le = q <= hi && prefix[q] <= x;
+        const unsigned long long m = __ballot(le);      // lane 0 always set
+        const int last = 63 - __builtin_clzll(m);
+        lo = lo + last * step;
+        const int h = lo + step - 1;
+        hi = h < hi ? h : hi;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------- launchers
 // Exponent scan + slicing of one operand into packed planes.
 //   by_rows = 1: X is lines x k (rows of A are lines), element (l, kk) at

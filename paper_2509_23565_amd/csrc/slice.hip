@@ -254,12 +254,7 @@ __global__ __launch_bounds__(256) void k_slice_small_grouped(const SliceJob *__r
     const int wave = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (wave >= total) return;
-    int lo = 0, hi = nj - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= wave) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = __builtin_amdgcn_readfirstlane(wave_search(prefix, nj, wave));
     const SliceJob J = jobs[lo];
     const int lb = wave - prefix[lo];
     const int line = lb * 32 + (lane & 31);

@@ -52,15 +52,20 @@ constexpr int WAIT_VMCNT0 = 0x0F70;
 // compiler's wait-count bookkeeping does not see an LDS-writing memory
 // operation: with one in a loop it waits for every outstanding LDS read
 // before each MFMA group.  The kernels wait for these loads explicitly
-// (vmcnt(0) before the barrier that publishes the buffer).
+// (vmcnt(0) before the barrier that publishes the buffer).  M0 (a register
+// the compiler reserves, so it cannot be named as clobbered) is set here;
+// the compiled kernels of this file use M0 nowhere else (no LDS DMA or
+// message instructions of their own), which the generated code shows.
 __device__ __forceinline__ void dma_frag(const int8_t *gsrc, int8_t *lds) {
-    const unsigned dst = (unsigned)(uintptr_t)(__attribute__((address_space(3))) int8_t *)lds;
+    // a flat (generic) address of LDS holds the LDS byte offset in its low
+    // 32 bits (the shared aperture is in the high half)
+    const unsigned dst = (unsigned)(uintptr_t)lds;
     asm volatile("s_mov_b32 m0, %1\n\t"
                  "s_nop 0\n\t"
                  "global_load_lds_dwordx4 %0, off"
                  :
                  : "v"(gsrc), "s"(__builtin_amdgcn_readfirstlane(dst))
-                 : "memory", "m0");
+                 : "memory");
 }
 
 // ------------------------------------------------------------- diagonals
@@ -133,10 +138,14 @@ __device__ __forceinline__ void tile_of(int L, int tiles_m, int tiles_n, int *tm
 
 // One output tile (tm, tn) over K blocks [kb0, kb1) of problem p.
 // MODE 0: recombine into C.  MODE 2: write the INT32 D_g of chunk `chunk`.
-template <int S, int T, bool SPLIT, int MODE>
+// PF: read this wave's C block (beta != 0) before the K loop, so that its
+// latency overlaps the first fragment copies; for short K (the grouped
+// launches of small updates, one K step) the C read is most of a tile's time.
+template <int S, int T, bool SPLIT, int MODE, bool PF = false>
 __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, int kb0,
                                            int kb1, int chunk, int8_t *lds0, int8_t *lds1) {
     using CF = Cfg<S, T, SPLIT>;
+    static_assert(!PF || (MODE == 0 && CF::WM * CF::WN == 1), "C prefetch: one block per wave");
     static_assert(CF::THREADS == 512, "launch bounds assume 8 waves");
     constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
     constexpr int NSLOT = CF::NSLOT;
@@ -182,6 +191,16 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][g][r] = 0;
 
+    double cpre[16];
+    if constexpr (PF) {
+        const int m = (mb0 + wm) * 32 + (lane & 31);
+        const int nbase = (nb0 + wn) * 32 + 4 * (lane >> 5);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = nbase + 8 * (r >> 2) + (r & 3);
+            cpre[r] = (p.beta != 0.0 && m < p.M && n < p.N) ? p.C[(size_t)n * p.ldc + m] : 0.0;
+        }
+    }
     if (kb0 < kb1) issue(lds0, kb0);
     for (int kb = kb0; kb < kb1; ++kb) {
         const int it = kb - kb0;
@@ -248,7 +267,10 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
             // all C reads of the block before any store, so the 16 loads are
             // in flight together instead of one round trip per element
             double cin[16];
-            if (MODE != 2) {
+            if constexpr (PF) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) cin[r] = cpre[r];
+            } else if (MODE != 2) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int n = nbase + 8 * (r >> 2) + (r & 3);
@@ -315,17 +337,12 @@ __global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__res
     __shared__ __attribute__((aligned(1024))) int8_t lds0[CF::FR * FRAG_BYTES];
     __shared__ __attribute__((aligned(1024))) int8_t lds1[CF::FR * FRAG_BYTES];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        int lo = 0, hi = nprob - 1;               // last q with prefix[q] <= tile
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_prefix[mid] <= tile) lo = mid;
-            else hi = mid - 1;
-        }
+        const int lo = __builtin_amdgcn_readfirstlane(wave_search(tile_prefix, nprob, tile));
         const GemmArgs p = probs[lo];
         const int local = tile - tile_prefix[lo];
         const int tm = local % p.tiles_m, tn = local / p.tiles_m;
         __syncthreads();                          // LDS of the previous tile is free
-        sgemm_tile<S, T, false, 0>(p, tm, tn, 0, p.KB, 0, lds0, lds1);
+        sgemm_tile<S, T, false, 0, Cfg<S, T, false>::WN == 1>(p, tm, tn, 0, p.KB, 0, lds0, lds1);
     }
 }
 
