@@ -597,7 +597,7 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
                                     pl.g_off[stp];
             const int *gpre = reinterpret_cast<const int *>(base + pl.o_gpre) + pl.gp_off[stp];
             EMU_TRY(launch_slicegemm_grouped(probs, gpre, pl.g_cnt[stp], pl.g_tiles[stp], ggrid,
-                                             pl.s, st));
+                                             pl.s, st, /*one_kstep=*/true));
         }
     }
     if (pl.solve) {

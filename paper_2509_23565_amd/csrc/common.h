@@ -166,8 +166,11 @@ bool gemm_supported(int s, int t);
 // K of every problem must not need chunking (K <= 32 * 462 for s = 9).
 void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n);
 int gemm_grouped_blocks_per_cu(int s);
+// one_kstep: every problem has K <= 32 (one K step); selects the
+// pipelined kernel for s >= 6.
 int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
-                             int total_tiles, int grid, int s, hipStream_t stream);
+                             int total_tiles, int grid, int s, hipStream_t stream,
+                             bool one_kstep = false);
 
 // FP64 LU pieces.
 int launch_fill_int(int *p, int v, int count, hipStream_t stream);

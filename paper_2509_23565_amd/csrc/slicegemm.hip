@@ -346,6 +346,160 @@ __global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__res
     }
 }
 
+// Grouped form for problems of one K step (K <= 32: the updates of the
+// batched LU), software-pipelined across the tiles a workgroup walks.  A
+// tile of one K step is a chain of latencies (fragment copy, C read, a few
+// MFMAs, the recombination and the C write), so tile t + 1's fragments are
+// copied into the other LDS buffer while tile t is multiplied and
+// recombined, the problem of tile t + 2 is looked up, and tile t + 1's C
+// block and exponents are read, all before the barrier that starts t + 1.
+// One 32x32 block per wave (the slot counts of s >= 6).
+template <int S>
+__global__ __launch_bounds__(512) void k_slicegemm_grouped1(const GemmArgs *__restrict__ probs,
+                                                            const int *__restrict__ tile_prefix,
+                                                            int nprob, int total) {
+    constexpr int T = S + 1;
+    using CF = Cfg<S, T, false>;
+    static_assert(CF::WM == 1 && CF::WN == 1 && CF::THREADS == 512, "one block per wave");
+    constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
+    constexpr int NSLOT = CF::NSLOT, NQ = (FR + NW - 1) / NW;
+    __shared__ __attribute__((aligned(1024))) int8_t lds0[FR * FRAG_BYTES];
+    __shared__ __attribute__((aligned(1024))) int8_t lds1[FR * FRAG_BYTES];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = w % CF::WAVES_M, wn = w / CF::WAVES_M;
+
+    // problem and tile coordinates of a tile
+    auto locate = [&](int tile, GemmArgs &q, int &tm, int &tn) {
+        const int lo = __builtin_amdgcn_readfirstlane(wave_search(tile_prefix, nprob, tile));
+        q = probs[lo];
+        const int local = tile - tile_prefix[lo];
+        tm = local % q.tiles_m;
+        tn = local / q.tiles_m;
+    };
+    // this wave's share of the tile's fragments (one K step) into buf
+    auto issue = [&](const GemmArgs &q, int tm, int tn, int8_t *buf) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int f = k * NW + w;
+            if (f < FRA) {
+                const int d = f / TM, i = f % TM;
+                dma_frag(q.Ap + d * q.a_plane + (size_t)(tm * TM + i) * FRAG_BYTES + lane * 16,
+                         buf + f * FRAG_BYTES);
+            } else if (f < FR) {
+                const int g = f - FRA;
+                const int d = g / TN, j = g % TN;
+                dma_frag(q.Bp + d * q.b_plane + (size_t)(tn * TN + j) * FRAG_BYTES + lane * 16,
+                         buf + f * FRAG_BYTES);
+            }
+        }
+    };
+    // this lane's C elements (beta != 0) and exponent codes of the tile
+    double cin[16];
+    int ca, cb[16];
+    auto prefetch = [&](const GemmArgs &q, int tm, int tn) {
+        const int m = (tm * TM + wm) * 32 + (lane & 31);
+        const int nbase = (tn * TN + wn) * 32 + 4 * (lane >> 5);
+        ca = m < q.M ? q.codeA[m] : 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = nbase + 8 * (r >> 2) + (r & 3);
+            const bool in = m < q.M && n < q.N;
+            cin[r] = (q.beta != 0.0 && in) ? q.C[(size_t)n * q.ldc + m] : 0.0;
+            cb[r] = n < q.N ? q.codeB[n] : 0;
+        }
+    };
+
+    int tile = blockIdx.x;
+    if (tile >= total) return;                    // uniform per workgroup
+    GemmArgs p, pn;
+    int tm, tn, tmn = 0, tnn = 0;
+    locate(tile, p, tm, tn);
+    issue(p, tm, tn, lds0);
+    prefetch(p, tm, tn);
+    int next = tile + (int)gridDim.x;
+    if (next < total) locate(next, pn, tmn, tnn);
+    for (int it = 0;; ++it) {
+        int8_t *cur = (it & 1) ? lds1 : lds0;
+        int8_t *nxt = (it & 1) ? lds0 : lds1;
+        // tile's fragments are in cur for every wave, its C block and
+        // exponents in registers, the next tile's problem in pn
+        __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+        __syncthreads();
+        if (next < total) issue(pn, tmn, tnn, nxt);
+
+        v16i acc[NSLOT];
+#pragma unroll
+        for (int g = 0; g < NSLOT; ++g)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+        {
+            const int8_t *pa = cur + wm * FRAG_BYTES + lane * 16;
+            const int8_t *pb = cur + (FRA + wn) * FRAG_BYTES + lane * 16;
+            v4i b[S];
+            v4i a = *reinterpret_cast<const v4i *>(pa + (S - 1) * TM * FRAG_BYTES);
+            b[0] = *reinterpret_cast<const v4i *>(pb);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+            for (int ii = S; ii >= 1; --ii) {
+                v4i an = a;
+                if (ii > 1) {
+                    an = *reinterpret_cast<const v4i *>(pa + (ii - 2) * TM * FRAG_BYTES);
+                    b[S + 1 - ii] = *reinterpret_cast<const v4i *>(pb + (S + 1 - ii) * TN * FRAG_BYTES);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                }
+#pragma unroll
+                for (int jj = 1; jj <= S; ++jj)
+                    if (ii + jj <= T) {
+                        const int sl = CF::slot(ii, jj);
+                        acc[sl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b[jj - 1], a, acc[sl], 0, 0, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    }
+                a = an;
+            }
+        }
+
+        // recombination of the tile (fixed order, as in sgemm_tile)
+        {
+            const int m = (tm * TM + wm) * 32 + (lane & 31);
+            const int nbase = (tn * TN + wn) * 32 + 4 * (lane >> 5);
+            const bool badA = ca == CODE_NONFINITE;
+            const int ea = (ca == CODE_ZERO || badA) ? 0 : ca;
+            if (m < p.M) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int n = nbase + 8 * (r >> 2) + (r & 3);
+                    if (n >= p.N) continue;
+                    const bool badB = cb[r] == CODE_NONFINITE;
+                    const int eb = (cb[r] == CODE_ZERO || badB) ? 0 : cb[r];
+                    double Ssum = 0.0;
+#pragma unroll
+                    for (int g = T - 2; g >= 0; --g) {
+                        const double wgt =
+                            __longlong_as_double((long long)(1023 - 7 * (g + 2)) << 52);
+                        Ssum = Ssum + (double)acc[g][r] * wgt;
+                    }
+                    const double X = ldexp(Ssum, ea + eb);
+                    double out = (p.beta == 0.0) ? fma(p.alpha, X, 0.0)
+                                                 : fma(p.alpha, X, p.beta * cin[r]);
+                    if (badA || badB) out = __builtin_nan("");
+                    p.C[(size_t)n * p.ldc + m] = out;
+                }
+            }
+        }
+        if (next >= total) break;
+        // advance: tile <- next; look up the one after it and read the new
+        // tile's C block and exponents (both land before the next barrier)
+        tile = next;
+        p = pn;
+        tm = tmn;
+        tn = tnn;
+        next = tile + (int)gridDim.x;
+        if (next < total) locate(next, pn, tmn, tnn);
+        prefetch(p, tm, tn);
+    }
+}
+
 // Chunk combine: D_g = sum over chunks (INT64), then either the raw sums
 // (debug, Dout != null) or the recombination into C.
 template <int T>
@@ -518,9 +672,25 @@ int gemm_grouped_blocks_per_cu(int s) {
 }
 
 int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
-                             int total_tiles, int grid, int s, hipStream_t stream) {
+                             int total_tiles, int grid, int s, hipStream_t stream,
+                             bool one_kstep) {
     if (total_tiles <= 0 || nprob <= 0) return 0;
     if (grid > total_tiles) grid = total_tiles;
+    if (one_kstep && s >= 6 && s <= 9) {
+#define EMU_G1CASE(S_)                                                                   \
+    case S_:                                                                             \
+        hipLaunchKernelGGL((k_slicegemm_grouped1<S_>), dim3(grid), dim3(512), 0, stream, \
+                           probs, tile_prefix, nprob, total_tiles);                      \
+        break;
+        switch (s) {
+            EMU_G1CASE(6) EMU_G1CASE(7) EMU_G1CASE(8) EMU_G1CASE(9)
+            default:
+                break;
+        }
+#undef EMU_G1CASE
+        EMU_TRY_HIP(hipGetLastError());
+        return 0;
+    }
 #define EMU_GCASE(S_)                                                                  \
     case S_:                                                                           \
         hipLaunchKernelGGL((k_slicegemm_grouped<S_, S_ + 1>), dim3(grid), dim3(512), 0, \
