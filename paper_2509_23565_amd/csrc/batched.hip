@@ -123,10 +123,11 @@ __global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, i
             if (j < w) P[t + (long long)j * S.lda] = v[j];
 }
 
-// Interchanges of step j0 on the columns outside the panel.  Wave 0
-// composes the jb <= 32 interchanges into the rows they move (at most 64);
-// then threads take (moved row, column) pairs, consecutive threads down a
-// column, with all loads of the workgroup's 64 columns before any store.
+// Interchanges of step j0 on the columns right of the panel (the columns
+// left of it receive theirs at the end, k_blaswp_left).  Wave 0 composes the
+// jb <= 32 interchanges into the rows they move (at most 64); then threads
+// take (moved row, column) pairs, consecutive threads down a column, with
+// all loads of the workgroup's 64 columns before any store.
 constexpr int BSW_COLS = 64;
 __global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, int j0, int nb) {
     __shared__ int srow_s[2 * BMAX_NB], ssrc_s[2 * BMAX_NB];
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, in
     const int rows = S.n - j0;
     if (rows <= 0) return;
     const int w = nb < rows ? nb : rows;
-    const int ncols = S.n - w;                       // [0, j0) and [j0 + w, n)
+    const int ncols = S.n - j0 - w;                  // [j0 + w, n)
     const int c0 = blockIdx.x * BSW_COLS;
     if (c0 >= ncols) return;                         // uniform per workgroup
     const int t = threadIdx.x;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, in
         const int tc = c0 + (t >> 6) + 4 * r;
         v[r] = 0.0;
         if (moves && tc < ncols) {
-            const int col = tc < j0 ? tc : tc + w;
+            const int col = j0 + w + tc;
             v[r] = S.A[j0 + from + (long long)col * S.lda];
         }
     }
@@ -172,8 +173,81 @@ __global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, in
     for (int r = 0; r < PASSES; ++r) {
         const int tc = c0 + (t >> 6) + 4 * r;
         if (moves && tc < ncols) {
-            const int col = tc < j0 ? tc : tc + w;
+            const int col = j0 + w + tc;
             S.A[j0 + to + (long long)col * S.lda] = v[r];
+        }
+    }
+}
+
+// The interchanges of every step applied to the columns left of its panel,
+// once, after the factorization: block b (columns [b nb, b nb + nb)) must
+// receive those of steps b + 1, b + 2, ... in that order, i.e. column
+// out[i] = in[pi_b(i)] with pi_b = sigma_{b+1} o pi_{b+1} (sigma_s: the
+// row map of step s's interchanges).  One workgroup per system keeps
+// Q = pi_b^-1 over the rows in LDS, walking b downwards (each step's
+// interchanges composed by one wave into at most 64 moved rows update Q in
+// one parallel round), and moves each row v of block b's columns to Q[v]:
+// reads run down the columns, all reads of a pass before its writes.  The
+// factors are those of applying the interchanges step by step.
+constexpr int BSL_COLS = 8;        // columns per read/write pass
+__global__ __launch_bounds__(256) void k_blaswp_left(const BSys *__restrict__ sys, int nb) {
+    __shared__ int Q[BMAX_N];
+    __shared__ int srow_s[2 * BMAX_NB], ssrc_s[2 * BMAX_NB];
+    __shared__ int nslot_s;
+    const BSys S = sys[blockIdx.x];
+    const int n = S.n, t = threadIdx.x;
+    const int steps = (n + nb - 1) / nb;
+    if (steps < 2) return;                           // uniform per workgroup
+    for (int v = t; v < n; v += 256) Q[v] = v;
+    constexpr int RPT = BMAX_N / 256;                // rows per thread and column
+    for (int b = steps - 2; b >= 0; --b) {
+        const int j0 = (b + 1) * nb;                 // step b + 1
+        const int rows = n - j0;
+        const int w = nb < rows ? nb : rows;
+        __syncthreads();                             // Q and the slots are free
+        if (t < 64) {
+            int pk = -1;
+            if (t < w) {
+                pk = S.ipiv[j0 + t] - 1 - j0;
+                if (pk < t || pk >= rows) pk = t;    // no interchange
+            }
+            int srow, src;
+            const int ns = wave_compose32(pk, w, srow, src);
+            srow_s[t] = srow;
+            ssrc_s[t] = src;
+            if (t == 0) nslot_s = ns;
+        }
+        __syncthreads();
+        // Q_b[src] = Q_{b+1}[srow] for the moved rows (reads before writes)
+        const int ns = nslot_s;
+        int qv = 0;
+        const bool mv = t < ns && srow_s[t] != ssrc_s[t];
+        if (mv) qv = Q[j0 + srow_s[t]];
+        __syncthreads();
+        if (mv) Q[j0 + ssrc_s[t]] = qv;
+        __syncthreads();
+        // block b's columns: row v (v >= j0) moves to row Q[v]
+        const int cb = b * nb, ce = cb + nb;         // ce <= j0 < n
+        for (int c0 = cb; c0 < ce; c0 += BSL_COLS) {
+            double val[BSL_COLS][RPT];
+#pragma unroll
+            for (int cc = 0; cc < BSL_COLS; ++cc)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int v = j0 + t + 256 * k;
+                    val[cc][k] = (c0 + cc < ce && v < n)
+                                     ? S.A[v + (long long)(c0 + cc) * S.lda] : 0.0;
+                }
+            __syncthreads();                         // all reads of the pass first
+#pragma unroll
+            for (int cc = 0; cc < BSL_COLS; ++cc)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int v = j0 + t + 256 * k;
+                    if (c0 + cc < ce && v < n && Q[v] != v)
+                        S.A[Q[v] + (long long)(c0 + cc) * S.lda] = val[cc][k];
+                }
+            __syncthreads();
         }
     }
 }
@@ -600,6 +674,8 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
                                              pl.s, st, /*one_kstep=*/true));
         }
     }
+    hipLaunchKernelGGL(k_blaswp_left, dim3(pl.count), dim3(256), 0, st, sys, pl.nb);
+    EMU_TRY_HIP(hipGetLastError());
     if (pl.solve) {
         hipLaunchKernelGGL(k_bgetrs, dim3(pl.count), dim3(1024), 0, st, sys);
         EMU_TRY_HIP(hipGetLastError());
