@@ -5,7 +5,9 @@
 // Systems are sorted by size, so the systems still active at block step j
 // (n_i > j nb) are a prefix of the list.  Each step issues one launch per
 // phase for all active systems: panel (one workgroup per system, the panel in
-// registers), interchanges, triangular solve, slicing of every L21 and U12
+// registers), interchanges right of the panel with the triangular solve
+// (interchanges left of the panels: once, after the last step), slicing of
+// every L21 and U12
 // (one pass each: K = nb <= 32 is a single fragment block), and one
 // persistent grouped slice-product GEMM over the concatenated tile lists of
 // all systems.  The whole sequence (and the solves) is captured once per
@@ -123,23 +125,31 @@ __global__ __launch_bounds__(1024) void k_bpanel(const BSys *__restrict__ sys, i
             if (j < w) P[t + (long long)j * S.lda] = v[j];
 }
 
-// Interchanges of step j0 on the columns right of the panel (the columns
-// left of it receive theirs at the end, k_blaswp_left).  Wave 0 composes the
-// jb <= 32 interchanges into the rows they move (at most 64); then threads
-// take (moved row, column) pairs, consecutive threads down a column, with
-// all loads of the workgroup's 64 columns before any store.
-constexpr int BSW_COLS = 64;
-__global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, int j0, int nb) {
-    __shared__ int srow_s[2 * BMAX_NB], ssrc_s[2 * BMAX_NB];
+// Interchanges of step j0 on the columns right of the panel, fused with
+// U12 = L11^-1 A12 on them (the columns left of the panel receive their
+// interchanges at the end, k_blaswp_left).  Per 64 columns: wave 0 composes
+// the jb <= 32 interchanges into the rows they move (at most 64); the top jb
+// rows after the interchanges are gathered into an LDS tile (a row that
+// comes from below reads its source row) and the moved rows below the top
+// are read, all before any write; then those are written, one wave solves
+// the tile (a lane per column, L11 in LDS, same order as the single-system
+// TRSM) and the top rows are written back down the columns.
+constexpr int BST_COLS = 64;
+__global__ __launch_bounds__(256) void k_bswap_trsm(const BSys *__restrict__ sys, int j0, int nb) {
+    __shared__ double Ls[BMAX_NB * BMAX_NB];
+    __shared__ double Bt[BMAX_NB][BST_COLS + 1];
+    __shared__ int srow_s[2 * BMAX_NB], ssrc_s[2 * BMAX_NB], topsrc[BMAX_NB];
     __shared__ int nslot_s;
     const BSys S = sys[blockIdx.y];
     const int rows = S.n - j0;
     if (rows <= 0) return;
     const int w = nb < rows ? nb : rows;
-    const int ncols = S.n - j0 - w;                  // [j0 + w, n)
-    const int c0 = blockIdx.x * BSW_COLS;
-    if (c0 >= ncols) return;                         // uniform per workgroup
+    const int ncols = S.n - j0 - w;                  // columns [j0 + w, n)
+    const int c0 = blockIdx.x * BST_COLS;
+    if (ncols <= 0 || c0 >= ncols) return;           // uniform per workgroup
     const int t = threadIdx.x;
+    const int nc = ncols - c0 < BST_COLS ? ncols - c0 : BST_COLS;
+    double *Ac = S.A + j0 + (long long)(j0 + w + c0) * S.lda;   // row j0 of the first column
     if (t < 64) {
         int pk = -1;
         if (t < w) {
@@ -151,30 +161,77 @@ __global__ __launch_bounds__(256) void k_blaswp(const BSys *__restrict__ sys, in
         srow_s[t] = srow;
         ssrc_s[t] = src;
         if (t == 0) nslot_s = ns;
+        // source row of every top row (the wave's LDS writes stay in order)
+        if (t < BMAX_NB) topsrc[t] = t;
+        if (t < ns && srow < w) topsrc[srow] = src;
     }
-    __syncthreads();
-    const int ns = nslot_s;
-    const int x = t & 63;                            // moved row (slot)
-    const bool moves = x < ns && srow_s[x] != ssrc_s[x];
-    const int from = ssrc_s[x], to = srow_s[x];
-    constexpr int PASSES = BSW_COLS / 4;
-    double v[PASSES];
+    {
+        const double *L = S.A + j0 + (long long)j0 * S.lda;
+        const int i = t & 31;
 #pragma unroll
-    for (int r = 0; r < PASSES; ++r) {
-        const int tc = c0 + (t >> 6) + 4 * r;
-        v[r] = 0.0;
-        if (moves && tc < ncols) {
-            const int col = j0 + w + tc;
-            v[r] = S.A[j0 + from + (long long)col * S.lda];
+        for (int r = 0; r < BMAX_NB * BMAX_NB / 256; ++r) {
+            const int k = (t >> 5) + 8 * r;
+            Ls[k * BMAX_NB + i] = (i < w && k < w) ? L[i + (long long)k * S.lda] : 0.0;
         }
     }
     __syncthreads();
+    const int ns = nslot_s;
+    // the top tile after the interchanges (row i = t % 32, 8 columns apart)
+    double tv[BMAX_NB * BST_COLS / 256];
+    {
+        const int i = t & 31;
+        const int src = topsrc[i];
 #pragma unroll
-    for (int r = 0; r < PASSES; ++r) {
-        const int tc = c0 + (t >> 6) + 4 * r;
-        if (moves && tc < ncols) {
-            const int col = j0 + w + tc;
-            S.A[j0 + to + (long long)col * S.lda] = v[r];
+        for (int r = 0; r < BMAX_NB * BST_COLS / 256; ++r) {
+            const int c = (t >> 5) + 8 * r;
+            tv[r] = (i < w && c < nc) ? Ac[src + (long long)c * S.lda] : 0.0;
+        }
+    }
+    // moved rows below the top (slot x = t % 64, 4 columns apart)
+    const int x = t & 63;
+    const int to = srow_s[x], from = ssrc_s[x];
+    const bool below = x < ns && to >= w && to != from;
+    double bv[BST_COLS / 4];
+#pragma unroll
+    for (int r = 0; r < BST_COLS / 4; ++r) {
+        const int c = (t >> 6) + 4 * r;
+        bv[r] = (below && c < nc) ? Ac[from + (long long)c * S.lda] : 0.0;
+    }
+    {
+        const int i = t & 31;
+#pragma unroll
+        for (int r = 0; r < BMAX_NB * BST_COLS / 256; ++r) Bt[i][(t >> 5) + 8 * r] = tv[r];
+    }
+    __syncthreads();                                 // every read precedes any write
+#pragma unroll
+    for (int r = 0; r < BST_COLS / 4; ++r) {
+        const int c = (t >> 6) + 4 * r;
+        if (below && c < nc) Ac[to + (long long)c * S.lda] = bv[r];
+    }
+    if (t < 64) {
+        const int lane = t;
+        double b[BMAX_NB];
+#pragma unroll
+        for (int i = 0; i < BMAX_NB; ++i) b[i] = Bt[i][lane];
+#pragma unroll
+        for (int k = 0; k < BMAX_NB - 1; ++k) {
+            if (k < w - 1) {
+                const double bk = b[k];
+#pragma unroll
+                for (int i = k + 1; i < BMAX_NB; ++i)
+                    if (i < w) b[i] = b[i] - Ls[k * BMAX_NB + i] * bk;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BMAX_NB; ++i) Bt[i][lane] = b[i];
+    }
+    __syncthreads();
+    {
+        const int i = t & 31;
+#pragma unroll
+        for (int r = 0; r < BMAX_NB * BST_COLS / 256; ++r) {
+            const int c = (t >> 5) + 8 * r;
+            if (i < w && c < nc) Ac[i + (long long)c * S.lda] = Bt[i][c];
         }
     }
 }
@@ -252,71 +309,6 @@ __global__ __launch_bounds__(256) void k_blaswp_left(const BSys *__restrict__ sy
     }
 }
 
-// U12 = L11^-1 A12 for every active system: one wave per 64 columns; the
-// column tile is staged through LDS (reads and writes run down the
-// columns), each lane then solves one column in registers with L11
-// (jb <= 32) in LDS.
-constexpr int BTR_COLS = 64;
-__global__ __launch_bounds__(64) void k_btrsm(const BSys *__restrict__ sys, int j0, int nb) {
-    __shared__ double Ls[BMAX_NB * BMAX_NB];
-    __shared__ double Bt[BMAX_NB][BTR_COLS + 1];
-    const BSys S = sys[blockIdx.y];
-    const int rows = S.n - j0;
-    if (rows <= 0) return;
-    const int w = nb < rows ? nb : rows;
-    const int ncols = S.n - j0 - w;
-    const int c0 = blockIdx.x * BTR_COLS;
-    if (ncols <= 0 || c0 >= ncols) return;
-    const int lane = threadIdx.x;
-    const double *L = S.A + j0 + (long long)j0 * S.lda;
-    double *Bc = S.A + j0 + (long long)(j0 + w + c0) * S.lda;
-    const int nc = ncols - c0 < BTR_COLS ? ncols - c0 : BTR_COLS;
-    {
-        constexpr int PL = BMAX_NB * BMAX_NB / 64;
-        double lv[PL];
-        const int i = lane & 31, kh = lane >> 5;     // row, column parity
-#pragma unroll
-        for (int r = 0; r < PL; ++r) {
-            const int k = kh + 2 * r;
-            lv[r] = (i < w && k < w) ? L[i + (long long)k * S.lda] : 0.0;
-        }
-        constexpr int PB = BMAX_NB * BTR_COLS / 64;
-        double bv[PB];
-#pragma unroll
-        for (int r = 0; r < PB; ++r) {
-            const int c = kh + 2 * r;
-            bv[r] = (i < w && c < nc) ? Bc[i + (long long)c * S.lda] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < PL; ++r) Ls[(kh + 2 * r) * BMAX_NB + i] = lv[r];
-#pragma unroll
-        for (int r = 0; r < PB; ++r) Bt[i][kh + 2 * r] = bv[r];
-    }
-    __syncthreads();
-    double b[BMAX_NB];
-#pragma unroll
-    for (int i = 0; i < BMAX_NB; ++i) b[i] = Bt[i][lane];
-#pragma unroll
-    for (int k = 0; k < BMAX_NB - 1; ++k) {
-        if (k < w - 1) {
-            const double bk = b[k];
-#pragma unroll
-            for (int i = k + 1; i < BMAX_NB; ++i)
-                if (i < w) b[i] = b[i] - Ls[k * BMAX_NB + i] * bk;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < BMAX_NB; ++i) Bt[i][lane] = b[i];
-    __syncthreads();
-    {
-        const int i = lane & 31, kh = lane >> 5;
-#pragma unroll
-        for (int r = 0; r < BMAX_NB * BTR_COLS / 64; ++r) {
-            const int c = kh + 2 * r;
-            if (i < w && c < nc) Bc[i + (long long)c * S.lda] = Bt[i][c];
-        }
-    }
-}
 
 // ------------------------------------------------------------------ solve
 // One workgroup per system: interchanges (one thread per right-hand side),
@@ -656,10 +648,8 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
         const int j0 = stp * pl.nb;
         const int act = pl.nact[stp];
         hipLaunchKernelGGL(k_bpanel, dim3(act), dim3(1024), 0, st, sys, j0, pl.nb);
-        hipLaunchKernelGGL(k_blaswp, dim3((pl.nmax + BSW_COLS - 1) / BSW_COLS, act), dim3(256),
-                           0, st, sys, j0, pl.nb);
-        hipLaunchKernelGGL(k_btrsm, dim3((pl.nmax + BTR_COLS - 1) / BTR_COLS, act), dim3(64), 0,
-                           st, sys, j0, pl.nb);
+        hipLaunchKernelGGL(k_bswap_trsm, dim3((pl.nmax + BST_COLS - 1) / BST_COLS, act),
+                           dim3(256), 0, st, sys, j0, pl.nb);
         EMU_TRY_HIP(hipGetLastError());
         if (pl.g_cnt[stp] > 0) {
             const SliceJob *jobs = reinterpret_cast<const SliceJob *>(base + pl.o_jobs) +
