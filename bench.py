@@ -14,7 +14,9 @@ Printed on one JSON line, beside value: the slice-product kernel's roofline
 (INT8 MFMA operations per launch over its event-timed duration, against the
 dense INT8 peak), the CPU oracle timed on a bounded sample of the same
 product (and the sampled block checked bit for bit), the normwise error of
-that block against a double-double reference, native FP64 DGEMM and LU
+that block against a double-double reference, the slice-count sweep (s = 3..8
+on the same inputs: kernel time, INT8 rate, and each count's error on the
+double-double block), native FP64 DGEMM and LU
 (torch / ROCm libraries) on the same GPU, and the LU solves: the plain
 method (n = 1024, 7 slices), the precision form (n = 8192, reduced slices
 plus FP64 refinement to a backward error of 1e-15, against native FP64 with
@@ -247,9 +249,11 @@ def main():
                     help="size of the precision-form solve (0 skips it)")
     ap.add_argument("--batch-count", type=int, default=2000,
                     help="systems in the batched solve (0 skips it)")
-    ap.add_argument("--sweep-s", type=str, default="",
+    ap.add_argument("--sweep-s", type=str, default="3,4,5,6,7,8",
                     help="comma-separated slice counts to time on the same inputs "
-                         "(adds a 'sweep' list to the JSON line)")
+                         "(adds a 'sweep' list to the JSON line, with each count's "
+                         "error against the double-double product on the sampled "
+                         "block unless --no-cpu; '' skips it)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
@@ -385,6 +389,17 @@ def main():
         },
     }
 
+    # sampled block of C for the oracle leg (the sweep keeps its rows of each
+    # slice count's result for the error against the double-double product)
+    g = matgen.rng(args.seed, 99)
+    rows = np.sort(g.choice(n, size=min(args.sample_rows, n), replace=False))
+    cols = np.sort(g.choice(n, size=min(args.sample_cols, n), replace=False))
+    r2 = rows[:16]
+    rows_d = torch.as_tensor(rows, device="cuda")
+    cols_d = torch.as_tensor(cols, device="cuda")
+    r2_d = torch.as_tensor(r2, device="cuda")
+    sweep_blocks = []
+
     # ------------------------------------------------- slice-count sweep
     if args.sweep_s:
         sweep = []
@@ -406,6 +421,7 @@ def main():
             gm, gc = emu.profile_read(emu.PROF_GEMM)
             gavg = gm / max(gc, 1)
             ach = 2.0 * n * n * n * P2 / (gavg * 1e-3) / 1e12
+            sweep_blocks.append(Cg[r2_d][:, cols_d].cpu().numpy())
             sweep.append({"s": s2, "products": P2, "ms_per_step": round(step2, 3),
                           "tflops_equiv": round(flops_equiv / (step2 * 1e-3) / 1e12, 2),
                           "gemm_ms": round(gavg, 3), "int8_tops": round(ach, 1),
@@ -417,11 +433,7 @@ def main():
         torch.cuda.synchronize()
 
     # ---------------------------------------------------- sampled oracle leg
-    g = matgen.rng(args.seed, 99)
-    rows = np.sort(g.choice(n, size=min(args.sample_rows, n), replace=False))
-    cols = np.sort(g.choice(n, size=min(args.sample_cols, n), replace=False))
-    Cblock = Cg[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")]
-    Cblock = Cblock.cpu().numpy()
+    Cblock = Cg[rows_d][:, cols_d].cpu().numpy()
     if not args.no_cpu:
         import oracle
         from threadpoolctl import threadpool_info
@@ -446,7 +458,6 @@ def main():
             "seconds": round(t_cpu, 2),
         }
         # accuracy of a smaller block against the double-double product
-        r2 = rows[:16]
         ref_dd = oracle.dgemm_dd(np.asfortranarray(A[r2, :]), Bs)
         Cnat = (torch.as_tensor(A[r2, :], device="cuda") @ torch.as_tensor(Bs, device="cuda")).cpu().numpy()
         result["parity"] = {
@@ -458,6 +469,10 @@ def main():
         }
         log(f"oracle block {t_cpu:.1f} s, bit-exact={exact}, "
             f"eta_F={result['parity']['eta_F_vs_dd']:.2e}")
+        for ent, blk in zip(result.get("sweep", []), sweep_blocks):
+            ent["eta_F_vs_dd"] = oracle.rel_err_fro(blk, ref_dd)
+            ent["meets_1e-15"] = bool(ent["eta_F_vs_dd"] <= 1e-15)
+            log(f"sweep s={ent['s']}: eta_F={ent['eta_F_vs_dd']:.2e}")
         del As, Bs, ref
 
     # ---------------------------------------------------------- native FP64

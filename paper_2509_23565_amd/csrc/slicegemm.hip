@@ -12,7 +12,8 @@
 //   - the digit planes are stored in MFMA fragment order (1 KB per 32 lines
 //     x 32 k), so a K step of the workgroup tile is a list of whole
 //     fragments; they are copied global -> LDS with 16-byte direct-to-LDS
-//     loads (no VGPR staging), double buffered, one barrier per K step;
+//     loads (no VGPR staging) into two to four LDS stages (more for the
+//     short K steps of few digits), one barrier per K step;
 //   - each wave reads its own A and B fragments of every digit from LDS and
 //     issues all pairs (i, j) with i + j <= t on 32x32x32 INT8 MFMA;
 //   - workgroups are numbered so that each of the 8 XCDs receives one
@@ -52,7 +53,7 @@ constexpr int WAIT_VMCNT0 = 0x0F70;
 // compiler's wait-count bookkeeping does not see an LDS-writing memory
 // operation: with one in a loop it waits for every outstanding LDS read
 // before each MFMA group.  The kernels wait for these loads explicitly
-// (vmcnt(0) before the barrier that publishes the buffer).  M0 (a register
+// (a vmcnt wait before the barrier that publishes an LDS stage).  M0 (a register
 // the compiler reserves, so it cannot be named as clobbered) is set here;
 // the compiled kernels of this file use M0 nowhere else (no LDS DMA or
 // message instructions of their own), which the generated code shows.
@@ -109,6 +110,15 @@ struct Cfg {
     static constexpr int FRA = S * TM;
     static constexpr int FRB = S * TN;
     static constexpr int FR = FRA + FRB;        // fragments per K step
+    // LDS stages (K steps in flight).  With S <= 3 a K step is too short
+    // (12 MFMAs per wave at S = 3) to cover the latency of its fragment
+    // copies with one step of look-ahead: four stages (96 KB at S = 3) run
+    // the 16384^3 product 10% faster.  From S = 4 on two stages measure as
+    // fast as three or four (S = 6, 7 slower with more).
+    static constexpr int STAGE = FR * FRAG_BYTES;
+    static constexpr int NST = (S <= 3) ? 4 : 2;
+    // copies each wave issues per K step, at least
+    static constexpr int NQ_MIN = FR / NW;
     // slot of pair (i, j): diagonal g = i + j -> g - 2; with SPLIT the
     // upper half of the longest diagonal goes to the extra slot.
     static constexpr int slot(int i, int j) {
@@ -143,7 +153,7 @@ __device__ __forceinline__ void tile_of(int L, int tiles_m, int tiles_n, int *tm
 // launches of small updates, one K step) the C read is most of a tile's time.
 template <int S, int T, bool SPLIT, int MODE, bool PF = false>
 __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, int kb0,
-                                           int kb1, int chunk, int8_t *lds0, int8_t *lds1) {
+                                           int kb1, int chunk, int8_t *lds) {
     using CF = Cfg<S, T, SPLIT>;
     static_assert(!PF || (MODE == 0 && CF::WM * CF::WN == 1), "C prefetch: one block per wave");
     static_assert(CF::THREADS == 512, "launch bounds assume 8 waves");
@@ -201,13 +211,29 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
             cpre[r] = (p.beta != 0.0 && m < p.M && n < p.N) ? p.C[(size_t)n * p.ldc + m] : 0.0;
         }
     }
-    if (kb0 < kb1) issue(lds0, kb0);
+    // Stage (kb - kb0) % NST holds K step kb.  Before the barrier that
+    // publishes step kb, each wave waits for its own copies of that step:
+    // the copies of the NST - 2 later steps already issued may stay in
+    // flight (loads complete in order), near the end of K all of them.
+    constexpr int NST = CF::NST;
+    constexpr int AHEAD = (NST - 2) * CF::NQ_MIN;
+    static_assert(AHEAD < 64, "vmcnt field");
+    constexpr int WAIT_AHEAD = (AHEAD & 15) | ((AHEAD >> 4) << 14) | 0x0F70;
+#pragma unroll
+    for (int q = 0; q < NST - 1; ++q)
+        if (kb0 + q < kb1) issue(lds + q * CF::STAGE, kb0 + q);
+    int st = 0;                                   // stage of step kb
     for (int kb = kb0; kb < kb1; ++kb) {
-        const int it = kb - kb0;
-        __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+        if (NST > 2 && kb + NST - 2 < kb1)
+            __builtin_amdgcn_s_waitcnt(WAIT_AHEAD);
+        else
+            __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
         __syncthreads();
-        const int8_t *cur = (it & 1) ? lds1 : lds0;
-        if (kb + 1 < kb1) issue((it & 1) ? lds0 : lds1, kb + 1);
+        const int8_t *cur = lds + st * CF::STAGE;
+        // the stage read in the previous step is free for step kb + NST - 1
+        const int fs = (st == 0) ? NST - 1 : st - 1;
+        if (kb + NST - 1 < kb1) issue(lds + fs * CF::STAGE, kb + NST - 1);
+        st = (st == NST - 1) ? 0 : st + 1;
 #pragma unroll
         for (int i = 0; i < CF::WM; ++i) {
 #pragma unroll
@@ -315,8 +341,7 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
 template <int S, int T, bool SPLIT, int MODE>
 __global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
     using CF = Cfg<S, T, SPLIT>;
-    __shared__ __attribute__((aligned(1024))) int8_t lds0[CF::FR * FRAG_BYTES];
-    __shared__ __attribute__((aligned(1024))) int8_t lds1[CF::FR * FRAG_BYTES];
+    __shared__ __attribute__((aligned(1024))) int8_t lds[CF::NST * CF::STAGE];
     int tm, tn;
     tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
     int kb0 = 0, kb1 = p.KB;
@@ -324,7 +349,7 @@ __global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
         kb0 = blockIdx.y * p.chunk_kb;
         kb1 = min(p.KB, kb0 + p.chunk_kb);
     }
-    sgemm_tile<S, T, SPLIT, MODE>(p, tm, tn, kb0, kb1, blockIdx.y, lds0, lds1);
+    sgemm_tile<S, T, SPLIT, MODE>(p, tm, tn, kb0, kb1, blockIdx.y, lds);
 }
 
 // Persistent grouped form: every workgroup walks the concatenated tile list
@@ -334,15 +359,14 @@ __global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__res
                                                            const int *__restrict__ tile_prefix,
                                                            int nprob, int total) {
     using CF = Cfg<S, T, false>;
-    __shared__ __attribute__((aligned(1024))) int8_t lds0[CF::FR * FRAG_BYTES];
-    __shared__ __attribute__((aligned(1024))) int8_t lds1[CF::FR * FRAG_BYTES];
+    __shared__ __attribute__((aligned(1024))) int8_t lds[CF::NST * CF::STAGE];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int lo = __builtin_amdgcn_readfirstlane(wave_search(tile_prefix, nprob, tile));
         const GemmArgs p = probs[lo];
         const int local = tile - tile_prefix[lo];
         const int tm = local % p.tiles_m, tn = local / p.tiles_m;
         __syncthreads();                          // LDS of the previous tile is free
-        sgemm_tile<S, T, false, 0, Cfg<S, T, false>::WN == 1>(p, tm, tn, 0, p.KB, 0, lds0, lds1);
+        sgemm_tile<S, T, false, 0, Cfg<S, T, false>::WN == 1>(p, tm, tn, 0, p.KB, 0, lds);
     }
 }
 
