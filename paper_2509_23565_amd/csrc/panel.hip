@@ -17,7 +17,10 @@
 //     c = c - a_ik b_kj), factors the right part, and moves the left part's
 //     rows by the right part's interchanges;
 //   * leaves of at most 16 columns, the block in registers (4 rows x 16
-//     columns per thread, 2048 rows per 512-thread workgroup).  Each column
+//     columns per thread: 1024 rows per 256-thread workgroup, 2048 per
+//     512-thread one; a leaf of at most 1024 rows takes the smaller one,
+//     one wave per SIMD, whose per-column instruction chain then has its
+//     SIMD to itself: an n = 1024 factorization runs 6% faster).  Each column
 //     costs one workgroup barrier: every wave publishes its pivot candidate
 //     together with a copy of the candidate row (and the owner of row c a
 //     copy of row c) into a double-buffered LDS slot, so after the barrier
@@ -156,7 +159,7 @@ __device__ __forceinline__ double row_elem(double e0, double e1, int r, int j) {
 // row is the lowest set bit of the first non-empty mask.  The wave's
 // candidate is published with the key of the pivot order (the magnitude's
 // bits, NaN above +inf, -1 for none).
-template <bool MULTI, int k>
+template <bool MULTI, int NT, int k>
 __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows,
                                          int base_row, int g, const LeafX &x, unsigned base,
                                          int b) {
@@ -170,7 +173,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     bool valid[LF_R];
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
-        const int i = base_row + t + q * LF_THREADS;
+        const int i = base_row + t + q * NT;
         valid[q] = i >= c && i < rows;
         if (valid[q]) m = fmax(m, fabs(v[q][k]));
     }
@@ -198,7 +201,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     }
     const int lb = qb >= 0 ? __builtin_ctzll(mask) : 0;
     const long long bk = qb < 0 ? -1ll : wnan ? 0x7FF8000000000000ll : __double_as_longlong(M);
-    const int bi = qb < 0 ? INT_MAX : base_row + qb * LF_THREADS + wid * 64 + lb;
+    const int bi = qb < 0 ? INT_MAX : base_row + qb * NT + wid * 64 + lb;
     // the candidate row, and row c (thread c of workgroup 0), to LDS
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
@@ -217,8 +220,8 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
     // the workgroup's winner, and with it (single workgroup) the pivot row:
     // lane l reads doubles 2l, 2l + 1 of the candidate rows, the winner's
     // are then taken with lane reads into scalar registers
-    long long wk = L.val[buf][lane & (LF_WAVES - 1)];
-    int wi = L.idx[buf][lane & (LF_WAVES - 1)];
+    long long wk = L.val[buf][lane & (NT / 64 - 1)];
+    int wi = L.idx[buf][lane & (NT / 64 - 1)];
     double pr[LEAF_W];
     double e0 = 0.0, e1 = 0.0;
     if constexpr (!MULTI) {
@@ -226,13 +229,13 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         e0 = flat[2 * lane];
         e1 = flat[2 * lane + 1];
     }
-    key_best<LF_WAVES>(wk, wi);
+    key_best<NT / 64>(wk, wi);
     wi = __builtin_amdgcn_readfirstlane(wi);
     int p;
     const double *xr;
     if constexpr (!MULTI) {
         p = wi;
-        const int wr = ((p - base_row) % LF_THREADS) / 64;
+        const int wr = ((p - base_row) % NT) / 64;
 #pragma unroll
         for (int j = 0; j < LEAF_W; ++j) pr[j] = row_elem(e0, e1, wr, j);
         xr = L.xrow[buf];
@@ -246,7 +249,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
             const unsigned long long tag = (unsigned long long)(base + (unsigned)c + 1u) << 32;
             // publish: words 0..35 (and 36..67 from workgroup 0), tagged
             unsigned long long *mine = x.rec + ((long long)buf * LF_MAX_G + g) * RW;
-            const double *wrow = L.row[buf][((wi - base_row) % LF_THREADS) / 64];
+            const double *wrow = L.row[buf][((wi - base_row) % NT) / 64];
 #pragma unroll 1
             for (int e = lane; e < (g == 0 ? RW : RW_MAIN); e += 64) {
                 unsigned pl;
@@ -345,7 +348,7 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         __syncthreads();
         if (L.abort) return false;
         p = __builtin_amdgcn_readfirstlane(L.p[buf]);
-        const int gp = (p >= 0 && p < G * LF_ROWS) ? p / LF_ROWS : 0;
+        const int gp = (p >= 0 && p < G * (NT * LF_R)) ? p / (NT * LF_R) : 0;
         // the grid winner's row: lane l < 32 reads word l, lane reads make
         // it wave-uniform (scalar registers)
         const unsigned ew = reinterpret_cast<const unsigned *>(L.grow[buf][gp])[lane & 31];
@@ -368,10 +371,10 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
 #pragma unroll
             for (int j = 0; j < LEAF_W; ++j) v[0][j] = pr[j];
         const int tp = p - base_row;
-        if (tp >= 0 && tp < LF_ROWS && wid == (tp % LF_THREADS) / 64) {
+        if (tp >= 0 && tp < (NT * LF_R) && wid == (tp % NT) / 64) {
 #pragma unroll
             for (int q = 0; q < LF_R; ++q) {
-                if (base_row + t + q * LF_THREADS == p)
+                if (base_row + t + q * NT == p)
 #pragma unroll
                     for (int j = 0; j < LEAF_W; ++j) v[q][j] = xr[j];
             }
@@ -411,14 +414,14 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
 }
 
 // The four columns b..b+3 of a group (positions 0..3 of v).
-template <bool MULTI, int k>
+template <bool MULTI, int NT, int k>
 __device__ __forceinline__ bool leaf_group(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows,
                                            int w, int base_row, int g, const LeafX &x,
                                            unsigned base, int b) {
     if constexpr (k < 4) {
         if (b + k >= w) return true;
-        if (!leaf_col<MULTI, k>(v, L, rows, base_row, g, x, base, b)) return false;
-        return leaf_group<MULTI, k + 1>(v, L, rows, w, base_row, g, x, base, b);
+        if (!leaf_col<MULTI, NT, k>(v, L, rows, base_row, g, x, base, b)) return false;
+        return leaf_group<MULTI, NT, k + 1>(v, L, rows, w, base_row, g, x, base, b);
     } else {
         return true;
     }
@@ -428,7 +431,7 @@ __device__ __forceinline__ bool leaf_group(double (&v)[LF_R][LEAF_W], LeafLds &L
 // by a rotation of every row by four positions, so that the loop body names
 // its columns by fixed positions (registers) and stays small enough to run
 // from the instruction cache; four rotations restore the order.
-template <bool MULTI>
+template <bool MULTI, int NT>
 __device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L, int rows, int w,
                                           int base_row, int g, const LeafX &x, unsigned base) {
     bool ok = true;
@@ -446,7 +449,7 @@ __device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L,
                 v[q][LEAF_W - 1] = r3;
             }
         }
-        if (ok && b < w) ok = leaf_group<MULTI, 0>(v, L, rows, w, base_row, g, x, base, b);
+        if (ok && b < w) ok = leaf_group<MULTI, NT, 0>(v, L, rows, w, base_row, g, x, base, b);
     }
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
@@ -468,6 +471,7 @@ __device__ __forceinline__ bool leaf_cols(double (&v)[LF_R][LEAF_W], LeafLds &L,
 // then every workgroup moves its share of the columns, all reads of a round
 // before any write.  Called after the leaf's last column (L.piv complete).
 constexpr int SWAP_ROUND = 8;       // passes per read/write round
+template <int NT>
 __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int ncr,
                                  LeafLds &L, int g, int G) {
     const int t = threadIdx.x, lane = t & 63;
@@ -483,7 +487,7 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
     }
     __syncthreads();
     const int nslot = L.nslot;
-    constexpr int CPP = LF_THREADS / 32;        // columns per pass
+    constexpr int CPP = NT / 32;        // columns per pass
     const int x = t & 31, jj = t >> 5;           // slot, column within a pass
     const int nc = ncl + ncr;
     const int srow = x < nslot ? L.srow[x] : 0;
@@ -516,18 +520,19 @@ __device__ void leaf_panel_swaps(double *P, long long lda, int w, int ncl, int n
 }
 
 // P: top-left of the leaf (global row grow0), rows x w, w <= 16, rows >= w.
-// Workgroup g owns rows [2048 g, 2048 g + 2048): thread t rows
-// 2048 g + t + 512 q, q = 0..3.  MULTI: the workgroups of one leaf run
-// together; the records of column c carry sequence number base + c + 1.
-template <bool MULTI>
-__global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, long long lda,
+// NT threads per workgroup; workgroup g owns rows [4 NT g, 4 NT (g + 1)):
+// thread t rows 4 NT g + t + NT q, q = 0..3.  MULTI (NT = 512): the
+// workgroups of one leaf run together; the records of column c carry
+// sequence number base + c + 1.
+template <bool MULTI, int NT>
+__global__ __launch_bounds__(NT) void k_leaf(double *__restrict__ P, long long lda,
                                                      int rows, int w, int *ipiv, int grow0,
                                                      int *info, LeafX x, unsigned base,
                                                      int ncl, int ncr) {
     __shared__ LeafLds L;
     const int t = threadIdx.x;
     const int g = MULTI ? (int)blockIdx.x : 0;
-    const int base_row = g * LF_ROWS;
+    const int base_row = g * (NT * LF_R);
     if (t == 0) {
         L.abort = 0;
         L.zc = w;
@@ -535,15 +540,15 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
     double v[LF_R][LEAF_W];
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
-        const int i = base_row + t + q * LF_THREADS;
+        const int i = base_row + t + q * NT;
 #pragma unroll
         for (int j = 0; j < LEAF_W; ++j)
             v[q][j] = (i < rows && j < w) ? P[i + (long long)j * lda] : 0.0;
     }
-    if (!leaf_cols<MULTI>(v, L, rows, w, base_row, g, x, base)) return;
+    if (!leaf_cols<MULTI, NT>(v, L, rows, w, base_row, g, x, base)) return;
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
-        const int i = base_row + t + q * LF_THREADS;
+        const int i = base_row + t + q * NT;
         if (i < rows)
 #pragma unroll
             for (int j = 0; j < LEAF_W; ++j)
@@ -555,7 +560,7 @@ __global__ __launch_bounds__(LF_THREADS) void k_leaf(double *__restrict__ P, lon
         if (t < w) ipiv[t] = grow0 + L.piv[t] + 1;
         if (t == 0 && L.zc < w && *info == 0) *info = grow0 + L.zc + 1;
     }
-    if (ncl + ncr > 0) leaf_panel_swaps(P, lda, w, ncl, ncr, L, g, MULTI ? (int)gridDim.x : 1);
+    if (ncl + ncr > 0) leaf_panel_swaps<NT>(P, lda, w, ncl, ncr, L, g, MULTI ? (int)gridDim.x : 1);
 }
 
 // --------------------------------------------- order-preserving FP64 tiles
@@ -759,9 +764,15 @@ void set_leaf_cooperative(int on) { g_leaf_cooperative = on != 0; }
 static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0, int *info,
                 int ncl, int ncr, PanelRun &pr, hipStream_t st) {
     LeafX x = leaf_x(pr.ws, pr.status);
+    if (rows <= LF_ROWS / 2) {
+        hipLaunchKernelGGL((k_leaf<false, LF_THREADS / 2>), dim3(1), dim3(LF_THREADS / 2), 0, st,
+                           P, lda, rows, w, ipiv, grow0, info, x, 0u, ncl, ncr);
+        EMU_TRY_HIP(hipGetLastError());
+        return 0;
+    }
     if (rows <= LF_ROWS) {
-        hipLaunchKernelGGL(k_leaf<false>, dim3(1), dim3(LF_THREADS), 0, st, P, lda, rows, w,
-                           ipiv, grow0, info, x, 0u, ncl, ncr);
+        hipLaunchKernelGGL((k_leaf<false, LF_THREADS>), dim3(1), dim3(LF_THREADS), 0, st, P, lda,
+                           rows, w, ipiv, grow0, info, x, 0u, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
         return 0;
     }
@@ -773,11 +784,11 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
     unsigned base = pr.arrivals;
     if (g_leaf_cooperative) {
         void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
-        EMU_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_leaf<true>),
+        EMU_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_leaf<true, LF_THREADS>),
                                                dim3(G), dim3(LF_THREADS), args, 0, st));
     } else {
-        hipLaunchKernelGGL(k_leaf<true>, dim3(G), dim3(LF_THREADS), 0, st, P, lda, rows, w, ipiv,
-                           grow0, info, x, base, ncl, ncr);
+        hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G), dim3(LF_THREADS), 0, st, P, lda,
+                           rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
     }
     pr.arrivals += (unsigned)w;

@@ -195,9 +195,11 @@ def test_full_slice_count_normwise_error(phi):
                                       (257, 257, 128, 3), (2600, 300, 64, 5),
                                       (2300, 2300, 128, 4), (4100, 96, 96, 3),
                                       (700, 700, 200, 6), (9000, 40, 32, 3),
-                                      (4096, 48, 48, 3)])
+                                      (4096, 48, 48, 3), (1040, 48, 16, 3)])
 def test_getrf_bit_exact(m, n, nb, s):
-    # tall cases run the multi-workgroup panel leaf (more than 2048 rows)
+    # tall cases run the multi-workgroup panel leaf (more than 2048 rows);
+    # 1040 rows: leaves of 1040, 1024 and 1008 rows cross the boundary
+    # between the 512- and the 256-thread single-workgroup leaf
     A = matgen.phi_matrix(m, n, 1.0, seed=13)
     Ag = emu.colmajor(A)
     emu.status()
