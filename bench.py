@@ -110,9 +110,11 @@ def _native_refined(torch, At, bt, tol, maxiter=5):
 def bench_solvers(args, emu, torch, matgen):
     """Plain-method LU, precision form and batched form, each next to native
     FP64 on the same GPU; backward errors from the oracle's double-double
-    residual when the CPU leg is enabled."""
+    residual only in the CPU (oracle) leg, which --no-cpu turns off."""
     out = {}
-    import oracle
+    oracle = None
+    if not args.no_cpu:
+        import oracle
     tol = 1e-15
     # plain method, small: n = 1024, U(-1,1), 1 RHS, nb = 64, s = 7, seed 0
     nl = 1024
@@ -139,12 +141,13 @@ def bench_solvers(args, emu, torch, matgen):
     out["plain_n1024"] = {
         "workload": "n=1024 U(-1,1), 1 RHS, nb=64, s=7, seed 0",
         "emulated_ms": round(t_plain, 3),
-        "eta": oracle.backward_error(Al, x.cpu().numpy(), bl),
         "emulated_ir_ms": round(t_ir, 3), "ir_iters": X[1]["iters"],
-        "ir_eta": oracle.backward_error(Al, X[0].cpu().numpy(), bl),
         "native_ms": round(t_nat, 3),
-        "native_eta": oracle.backward_error(Al, xn.cpu().numpy(), bl),
     }
+    if oracle is not None:
+        out["plain_n1024"]["eta"] = oracle.backward_error(Al, x.cpu().numpy(), bl)
+        out["plain_n1024"]["ir_eta"] = oracle.backward_error(Al, X[0].cpu().numpy(), bl)
+        out["plain_n1024"]["native_eta"] = oracle.backward_error(Al, xn.cpu().numpy(), bl)
     log(f"plain n=1024: emu {t_plain:.2f} ms, emu+IR {t_ir:.2f} ms, native {t_nat:.2f} ms")
 
     # precision form: n = lu_n, phi = 1 entries, diagonal scaling for kappa,
@@ -169,7 +172,7 @@ def bench_solvers(args, emu, torch, matgen):
                      "s_final": inf["s_final"], "berr_fp64": inf["berr"],
                      "native_ms": round(t_n, 2), "native_refined_ms": round(t_nr, 2),
                      "speedup_vs_native_refined": round(t_nr / t_e, 3)}
-            if not args.no_cpu:
+            if oracle is not None:
                 entry["eta_dd"] = oracle.backward_error(A, X.cpu().numpy(), b)
                 entry["native_eta_dd"] = oracle.backward_error(A, xn.cpu().numpy(), b)
                 entry["native_refined_eta_dd"] = oracle.backward_error(A, xr.cpu().numpy(), b)
