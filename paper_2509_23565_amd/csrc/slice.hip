@@ -15,21 +15,26 @@
 //   (1-based) is bits 7(s-i)..7(s-i)+6 of Z with the sign of x.  This equals
 //   the truncated base-128 expansion of x 2^-e digit by digit.
 // Both passes read the operand once (8 bytes per element each); pass 2
-// writes s bytes per element in MFMA fragment order.
+// writes s bytes per element in MFMA fragment order.  For K <= 128 (the
+// panels of an LU's trailing updates) one launch does both: each slicing
+// wave first takes the exponents of its 32 lines over all of K (reading
+// the line K / 32 times in all, from cache), and the wave of the first K
+// block stores them; no fill and no scan launch precede it.
 #include "common.h"
 
 namespace emu {
 
+// Selects, no branches, so that loads of several elements can be in flight
+// before the first code is formed.
 __device__ __forceinline__ int exp_code(double x) {
-    unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    int eb = (int)((b >> 52) & 0x7ff);
-    unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
-    if (eb == 0x7ff) return CODE_NONFINITE;
-    if (eb == 0) {
-        if (fr == 0) return CODE_ZERO;
-        return (63 - __clzll((long long)fr)) - 1073;   // subnormal
-    }
-    return eb - 1022;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int eb = (int)((b >> 52) & 0x7ff);
+    const unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
+    // subnormal: the exponent of the leading fraction bit (fr | 1 has the
+    // same leading bit whenever fr != 0)
+    const int sub = (63 - __clzll((long long)(fr | 1ull))) - 1073;
+    const int fin = eb == 0 ? (fr == 0 ? CODE_ZERO : sub) : eb - 1022;
+    return eb == 0x7ff ? CODE_NONFINITE : fin;
 }
 
 __device__ __forceinline__ int code_to_exp(int c) {
@@ -105,13 +110,12 @@ __global__ __launch_bounds__(256) void k_scan_cols(const double *__restrict__ X,
 // lanes reading 32 different columns directly would each touch their own
 // cache line 16 times.
 constexpr int SL_TILE_LD = 33;     // doubles per column of the LDS tile (padded)
-template <int S, bool ROWS>
+template <int S, bool ROWS, bool FUSED>
 __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
                                                long long ldx, int lines, int k,
-                                               int LB, int KB,
-                                               const int *__restrict__ code,
+                                               int LB, int KB, int *__restrict__ code,
                                                int8_t *__restrict__ planes,
-                                               size_t plane_bytes) {
+                                               size_t plane_bytes, int *status) {
     long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (wave >= (long long)LB * KB) return;
@@ -119,7 +123,45 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
     int kb = (int)(wave % KB);
     int line = lb * 32 + (lane & 31);
     int kbase = kb * 32 + (lane >> 5) * 16;
-    int c = line < lines ? code[line] : CODE_ZERO;
+    int c;
+    if constexpr (FUSED) {
+        // the exponent code of this lane's line: lanes l and l + 32 share
+        // the line and take alternate (rows) or half (columns) of K
+        int m = CODE_ZERO;
+        if (line < lines) {
+            // eight loads in flight per round (a zero stands in past K)
+            if constexpr (ROWS) {
+                for (int kx0 = lane >> 5; kx0 < k; kx0 += 16) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int kx = kx0 + 2 * u;
+                        xv[u] = kx < k ? X[line + (long long)kx * ldx] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) m = max(m, exp_code(xv[u]));
+                }
+            } else {
+                const double *xl = X + (long long)line * ldx;
+                const int half = (k + 1) / 2;
+                const int k0 = (lane >> 5) * half, k1 = min(k, k0 + half);
+                for (int kx0 = k0; kx0 < k1; kx0 += 8) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = kx0 + u < k1 ? xl[kx0 + u] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) m = max(m, exp_code(xv[u]));
+                }
+            }
+        }
+        c = max(m, __shfl_xor(m, 32, 64));
+        if (kb == 0 && lane < 32 && line < lines) {
+            code[line] = c;
+            if (c == CODE_NONFINITE) atomicOr(status, EMU_STATUS_NONFINITE);
+        }
+    } else {
+        c = line < lines ? code[line] : CODE_ZERO;
+    }
     bool ok = line < lines && c != CODE_NONFINITE;
     int e = code_to_exp(c);
 
@@ -176,20 +218,33 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
     }
 }
 
-template <int S>
+template <int S, bool FUSED>
 static void launch_slice_s(const double *X, long long ldx, int by_rows,
-                           const Planes &g, const int *code, int8_t *planes,
+                           const Planes &g, int *code, int8_t *planes, int *status,
                            hipStream_t stream) {
     long long waves = (long long)g.LB * g.KB;
     if (waves == 0) return;
     dim3 grid((unsigned)((waves + 3) / 4));
     if (by_rows)
-        hipLaunchKernelGGL((k_slice<S, true>), grid, dim3(256), 0, stream, X, ldx,
-                           g.lines, g.k, g.LB, g.KB, code, planes, g.plane_bytes);
+        hipLaunchKernelGGL((k_slice<S, true, FUSED>), grid, dim3(256), 0, stream, X, ldx,
+                           g.lines, g.k, g.LB, g.KB, code, planes, g.plane_bytes, status);
     else
-        hipLaunchKernelGGL((k_slice<S, false>), grid, dim3(256), 0, stream, X, ldx,
-                           g.lines, g.k, g.LB, g.KB, code, planes, g.plane_bytes);
+        hipLaunchKernelGGL((k_slice<S, false, FUSED>), grid, dim3(256), 0, stream, X, ldx,
+                           g.lines, g.k, g.LB, g.KB, code, planes, g.plane_bytes, status);
 }
+
+template <int S>
+static void launch_slice_s(const double *X, long long ldx, int by_rows, const Planes &g,
+                           int *code, int8_t *planes, int *status, bool fused,
+                           hipStream_t stream) {
+    if (fused)
+        launch_slice_s<S, true>(X, ldx, by_rows, g, code, planes, status, stream);
+    else
+        launch_slice_s<S, false>(X, ldx, by_rows, g, code, planes, status, stream);
+}
+
+// K up to which one launch scans and slices (each wave rereads its lines)
+constexpr int FUSED_MAX_K = 128;
 
 int launch_fill_int(int *p, int v, int count, hipStream_t stream) {
     if (count <= 0) return 0;
@@ -202,8 +257,13 @@ int launch_fill_int(int *p, int v, int count, hipStream_t stream) {
 int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
                  int s, int *code, int8_t *planes, int *status,
                  hipStream_t stream) {
-    EMU_TRY(launch_fill_int(code, CODE_ZERO, g.lines, stream));
-    if (g.k > 0 && g.lines > 0) {
+    if (s < 1 || s > EMU_MAX_SLICES) {
+        set_error("slice count %d outside 1..%d", s, EMU_MAX_SLICES);
+        return EMU_ERR_UNSUPPORTED;
+    }
+    const bool fused = g.k > 0 && g.k <= FUSED_MAX_K;
+    if (!fused) EMU_TRY(launch_fill_int(code, CODE_ZERO, g.lines, stream));
+    if (!fused && g.k > 0 && g.lines > 0) {
         if (by_rows) {
             // enough workgroups to cover the chip when the panel is narrow
             // (an LU's L21 has k = nb): split k so that about 2048
@@ -226,15 +286,15 @@ int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
         EMU_TRY_HIP(hipGetLastError());
     }
     switch (s) {
-        case 1: launch_slice_s<1>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 2: launch_slice_s<2>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 3: launch_slice_s<3>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 4: launch_slice_s<4>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 5: launch_slice_s<5>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 6: launch_slice_s<6>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 7: launch_slice_s<7>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 8: launch_slice_s<8>(X, ldx, by_rows, g, code, planes, stream); break;
-        case 9: launch_slice_s<9>(X, ldx, by_rows, g, code, planes, stream); break;
+        case 1: launch_slice_s<1>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 2: launch_slice_s<2>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 3: launch_slice_s<3>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 4: launch_slice_s<4>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 5: launch_slice_s<5>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 6: launch_slice_s<6>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 7: launch_slice_s<7>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 8: launch_slice_s<8>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 9: launch_slice_s<9>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
         default:
             set_error("slice count %d outside 1..%d", s, EMU_MAX_SLICES);
             return EMU_ERR_UNSUPPORTED;

@@ -43,8 +43,10 @@ def _special_rows(A):
 
 @pytest.mark.parametrize("s", [1, 3, 7, 9])
 @pytest.mark.parametrize("phi", [0.0, 4.0, 12.0])
-def test_slices_bit_exact(s, phi):
-    X = _special_rows(matgen.phi_matrix(203, 141, phi, seed=1))
+@pytest.mark.parametrize("shape", [(203, 141), (203, 100), (70, 33)])
+def test_slices_bit_exact(s, phi, shape):
+    # K = 141: exponent scan and slicing as two passes; K <= 128: one pass
+    X = _special_rows(matgen.phi_matrix(*shape, phi, seed=1))
     Xt = np.asfortranarray(X.T)
     for by_rows, M in ((True, X), (False, Xt)):
         e_g, bad_g, q_g = emu.debug_slices(emu.colmajor(M), by_rows, s)
@@ -60,11 +62,13 @@ def test_slices_flag_nonfinite_lines():
     X = np.array(matgen.uniform(70, 40, seed=2), order="F")
     X[5, 3] = np.inf
     X[9, 0] = np.nan
-    e_g, bad_g, q_g = emu.debug_slices(emu.colmajor(X), True, 4)
-    e_o, bad_o = O.line_exponents(X, 1)
-    assert np.array_equal(_host(bad_g).astype(bool), bad_o)
-    assert np.array_equal(_host(e_g), e_o)
-    assert np.array_equal(_host(q_g), O.slice_digits(X, e_o, bad_o, 4, 1))
+    for by_rows, M in ((True, X), (False, np.asfortranarray(X.T))):
+        axis = 1 if by_rows else 0
+        e_g, bad_g, q_g = emu.debug_slices(emu.colmajor(M), by_rows, 4)
+        e_o, bad_o = O.line_exponents(M, axis)
+        assert np.array_equal(_host(bad_g).astype(bool), bad_o)
+        assert np.array_equal(_host(e_g), e_o)
+        assert np.array_equal(_host(q_g), O.slice_digits(M, e_o, bad_o, 4, axis))
 
 
 # ---------------------------------------------------------- slice products
