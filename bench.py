@@ -234,6 +234,94 @@ def bench_solvers(args, emu, torch, matgen):
     return out
 
 
+def bench_learned(args, emu, torch, matgen):
+    """Learned slice count: train the MLP on tiles of emulated LUs of
+    n = 8192 (three matrices) and n = 16384 (one) with phi ~ U(0, 12), then
+    solve one n = 16384 system (phi ~ U(0, 12)) with the adaptive LU plus
+    FP64 refinement to 1e-15, falling back to the full count (s = 9) when
+    the refinement fails; next to the same solve at the full count and
+    native FP64."""
+    from paper_2509_23565_amd import learned
+    g = matgen.rng(args.seed, 77)
+    specs = [(8192, float(g.uniform(0.0, 12.0))) for _ in range(3)]
+    specs.append((16384, float(g.uniform(0.0, 12.0))))
+    t0 = time.perf_counter()
+    mats = [emu.colmajor(matgen.phi_matrix(n, n, phi, seed=args.seed, substream=2000 + i))
+            for i, (n, phi) in enumerate(specs)]
+    log(f"learned: {len(mats)} training matrices generated ({time.perf_counter() - t0:.0f} s)")
+    t0 = time.perf_counter()
+    X, y = learned.training_set(mats, nb=256)
+    torch.cuda.synchronize()
+    t_set = time.perf_counter() - t0
+    del mats
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    params, hist = learned.train(X, y, steps=400)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    counts = torch.bincount(y.long(), minlength=7).tolist()
+    log(f"learned: {X.shape[0]} tiles labelled in {t_set:.1f} s, trained in {t_train:.1f} s, "
+        f"loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+
+    n, tol = 16384, 1e-15
+    phi_e = float(g.uniform(0.0, 12.0))
+    A = matgen.phi_matrix(n, n, phi_e, seed=args.seed, substream=3000)
+    b = matgen.uniform(n, 1, seed=args.seed, substream=3001)
+    Ag, bg = emu.colmajor(A), emu.colmajor(b)
+    del A
+    info_l = {}
+
+    def learned_solve():
+        LU = Ag.clone()
+        ipiv, _, _, (used, full) = emu.dgetrf_adaptive(LU, params, nb=256, s_full=9)
+        x = bg.clone()
+        emu.dgetrs(LU, ipiv, x)
+        rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
+        info_l.update(used=used, full=full, rc_learned=rc, iters=iters, berr=berr,
+                      fallback=False)
+        if rc != 0:
+            LU = Ag.clone()
+            ipiv, _ = emu.dgetrf(LU, nb=256, nslices=9)
+            x = bg.clone()
+            emu.dgetrs(LU, ipiv, x)
+            rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
+            info_l.update(fallback=True, rc=rc, iters_fallback=iters, berr=berr)
+        return x
+
+    info_f = {}
+
+    def full_solve():
+        LU = Ag.clone()
+        ipiv, _ = emu.dgetrf(LU, nb=256, nslices=9)
+        x = bg.clone()
+        emu.dgetrs(LU, ipiv, x)
+        rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
+        info_f.update(rc=rc, iters=iters, berr=berr)
+        return x
+
+    t_l = _time(torch, learned_solve, reps=2)
+    t_f = _time(torch, full_solve, reps=2)
+    At, bt = Ag.contiguous(), bg.contiguous()
+    t_n = _time(torch, lambda: _native_refined(torch, At, bt, tol), reps=2)
+    out = {
+        "train": {"matrices": [{"n": n_, "phi": round(p_, 3)} for n_, p_ in specs],
+                  "tiles": int(X.shape[0]), "label_counts_s3_to_s9": counts,
+                  "labelling_s": round(t_set, 2), "training_s": round(t_train, 2),
+                  "loss_first": hist[0], "loss_last": hist[-1]},
+        "eval": {"n": n, "phi": round(phi_e, 3), "nb": 256, "tol": tol,
+                 "products_used": info_l["used"], "products_full": info_l["full"],
+                 "product_ratio": round(info_l["used"] / max(info_l["full"], 1), 4),
+                 "learned_refined": info_l["rc_learned"] == 0, "fallback": info_l["fallback"],
+                 "berr_fp64": info_l["berr"], "learned_ms": round(t_l, 2),
+                 "full_count_ms": round(t_f, 2), "full_count_berr_fp64": info_f["berr"],
+                 "native_refined_ms": round(t_n, 2)},
+    }
+    log(f"learned: n={n} phi={phi_e:.2f}: {out['eval']['product_ratio']:.3f} of the products, "
+        f"fallback={info_l['fallback']}, {t_l:.1f} ms vs full count {t_f:.1f} ms, "
+        f"native+IR {t_n:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +348,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
+    ap.add_argument("--learned", action="store_true",
+                    help="add the learned slice-count leg (training on n = 8192 and "
+                         "16384 emulated LUs, evaluation on an n = 16384 solve)")
     ap.add_argument("--lu-trace", type=str, default="",
                     help="N,NB,S[,ir|,batch]: only factor one N x N phi=1 matrix twice "
                          "with emu_dgetrf (block NB, S slices); with ',ir' solve the "
@@ -508,6 +599,8 @@ def main():
     # ------------------------------------------------------------ solvers
     if not args.no_lu:
         result["lu_solve"] = bench_solvers(args, emu, torch, matgen)
+    if args.learned:
+        result["learned_form"] = bench_learned(args, emu, torch, matgen)
 
     print(json.dumps(result), flush=True)
 

@@ -886,10 +886,22 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     off += align256((size_t)nt0 * 7 * sizeof(float));
     const size_t o_smap = off;
     off += align256((size_t)nt0 * sizeof(int));
+    // per-count problem lists (built on the device; part 0: the tile
+    // columns of the next panel, part 1: the rest), the maps of all steps
     const size_t o_prob2 = off;
-    off += align256((size_t)nt0 * sizeof(GemmArgs));
+    off += align256((size_t)2 * 9 * nt0 * sizeof(GemmArgs));
     const size_t o_pre = off;
-    off += align256((size_t)(nt0 + 1) * sizeof(int));
+    off += align256((size_t)2 * 9 * (nt0 + 1) * sizeof(int));
+    const size_t o_cnt = off;
+    off += align256(2 * 18 * sizeof(int));
+    long long rec_total = 0;
+    for (int j0 = 0; j0 < mn; j0 += nb) {
+        const int j1 = j0 + (nb < mn - j0 ? nb : mn - j0);
+        if (j1 >= n || j1 >= m) continue;
+        rec_total += (long long)((m - j1 + 255) / 256) * ((n - j1 + 255) / 256);
+    }
+    const size_t o_rec = off;
+    off += align256((size_t)(rec_total > 0 ? rec_total : 1) * sizeof(int));
     EMU_TRY(reserve(dev, st, off));
     char *ws = static_cast<char *>(dev->ws);
     char *lws = ws + o_lu;
@@ -900,88 +912,129 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     int *smap = reinterpret_cast<int *>(ws + o_smap);
     GemmArgs *dprob = reinterpret_cast<GemmArgs *>(ws + o_prob2);
     int *dpre = reinterpret_cast<int *>(ws + o_pre);
+    int *dcnt = reinterpret_cast<int *>(ws + o_cnt);
+    int *drec = reinterpret_cast<int *>(ws + o_rec);
     EMU_TRY(launch_fill_int(info, 0, 1, st));
-    long long used = 0, full = 0, rec = 0;
-    std::vector<int> hs(nt0);
-    std::vector<GemmArgs> probs;
-    std::vector<int> pre;
+    // The whole factorization is enqueued without a host round trip: the
+    // slice map of a step goes from the MLP straight into the device-built
+    // problem lists, the operands are sliced once at s_full (a tile of
+    // count s reads the first s digit planes: truncated digits are prefixes
+    // of each other), and one grouped launch per count s runs its tiles
+    // (an empty list ends at once).  Look-ahead as in the plain LU: the
+    // tiles over the next panel's columns are updated first, the others on
+    // the side stream while the next panel is factored (each tile receives
+    // the same operations either way).  The maps are copied back at the end.
+    struct StepTiles {
+        int M, N, tm, nt;
+        long long rec;
+    };
+    std::vector<StepTiles> steps;
+    long long rec = 0;
     int cus = 0, did = 0;
     (void)hipGetDevice(&did);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, did);
     if (cus <= 0) cus = 256;
     const long long ld = lda;
+    const bool la_on = g_lu_lookahead != 0 && mn > nb;
+    if (la_on) EMU_TRY(side_stream(dev));
+    auto panel = [&](int j0) -> int {
+        const int jb = nb < mn - j0 ? nb : mn - j0;
+        return launch_panel(A + j0 + (long long)j0 * ld, ld, m - j0, jb, ipiv + j0, j0, info,
+                            pws, dev->status, st);
+    };
+    // The grouped launches are persistent (a grid of resident workgroups
+    // walks the tile list); on the side stream they take three quarters of
+    // the compute units, so that the next panel's kernels, which run
+    // meanwhile, find free ones.
+    auto gemms = [&](int part, int nt, hipStream_t sx) -> int {
+        GemmArgs *pp = dprob + (size_t)part * 9 * nt0;
+        int *pr = dpre + (size_t)part * 9 * (nt0 + 1);
+        int *pc = dcnt + part * 18;
+        // the network predicts s = 3..9 (clamped to s_full)
+        for (int s = 3; s <= s_full; ++s) {
+            int grid = cus * gemm_grouped_blocks_per_cu(s);
+            if (part == 1) grid = grid * 3 / 4 > 0 ? grid * 3 / 4 : 1;
+            EMU_TRY(launch_slicegemm_grouped_dev(pp + (size_t)(s - 1) * nt,
+                                                 pr + (size_t)(s - 1) * (nt + 1),
+                                                 pc + 2 * (s - 1), grid, s, sx));
+        }
+        return 0;
+    };
+    if (mn > 0) EMU_TRY(panel(0));
     for (int j0 = 0; j0 < mn; j0 += nb) {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
+        const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
         double *Ajj = A + j0 + (long long)j0 * ld;
-        EMU_TRY(launch_panel(Ajj, ld, m - j0, jb, ipiv + j0, j0, info, pws, dev->status, st));
         EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
-        if (j1 >= n) continue;
+        if (j1 >= n) {
+            if (jn > 0) EMU_TRY(panel(j1));
+            continue;
+        }
         double *U12 = A + j0 + (long long)j1 * ld;
         EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));
-        if (j1 >= m) continue;
+        if (j1 >= m) {                 // no rows below the panel (then jn = 0)
+            if (jn > 0) EMU_TRY(panel(j1));
+            continue;
+        }
         const int M = m - j1, N = n - j1;
         const double *L21 = A + j1 + (long long)j0 * ld;
         const int tm = (M + 255) / 256, tn = (N + 255) / 256, nt = tm * tn;
         EMU_TRY(launch_features(L21, ld, U12, ld, M, N, jb, feat, ws + o_fs, st));
         EMU_TRY(launch_mlp_infer(params, feat, nt, prob, smap, conf, st));
-        EMU_TRY_HIP(hipMemcpyAsync(hs.data(), smap, nt * sizeof(int), hipMemcpyDeviceToHost, st));
-        EMU_TRY_HIP(hipStreamSynchronize(st));
-        int smax = 1;
-        for (int q = 0; q < nt; ++q) {
-            if (hs[q] > s_full) hs[q] = s_full;
-            if (hs[q] > smax) smax = hs[q];
-        }
-        if (smaps && rec + nt <= smaps_cap)
-            for (int q = 0; q < nt; ++q) smaps[rec + q] = hs[q];
+        EMU_TRY_HIP(hipMemcpyAsync(drec + rec, smap, nt * sizeof(int), hipMemcpyDeviceToDevice,
+                                   st));
+        steps.push_back({M, N, tm, nt, rec});
         rec += nt;
-        // one slicing at the largest count: every smaller count uses the
-        // leading digit planes (truncated digits are prefixes of each other)
-        GemmScratch g = gemm_scratch(M, N, jb, smax, smax + 1);
+        GemmScratch g = gemm_scratch(M, N, jb, s_full, s_full + 1);
         int *codeA = reinterpret_cast<int *>(lws + g.off_codeA);
         int *codeB = reinterpret_cast<int *>(lws + g.off_codeB);
         int8_t *pa = reinterpret_cast<int8_t *>(lws + g.off_pa);
         int8_t *pb = reinterpret_cast<int8_t *>(lws + g.off_pb);
-        EMU_TRY(launch_slice(L21, ld, 1, g.ga, smax, codeA, pa, dev->status, st));
-        EMU_TRY(launch_slice(U12, ld, 0, g.gb, smax, codeB, pb, dev->status, st));
-        for (int s = 1; s <= smax; ++s) {
-            probs.clear();
-            pre.assign(1, 0);
-            for (int q = 0; q < nt; ++q) {
-                const long long area = (long long)((q % tm == tm - 1) ? M - (q % tm) * 256 : 256) *
-                                       ((q / tm == tn - 1) ? N - (q / tm) * 256 : 256);
-                if (s == smax) full += area * (long long)(s_full * (s_full + 1) / 2);
-                if (hs[q] != s) continue;
-                used += area * (long long)(s * (s + 1) / 2);
-                const int I = q % tm, J = q / tm;
-                GemmArgs a{};
-                a.Ap = pa + (size_t)I * 8 * g.ga.KB * FRAG_BYTES;
-                a.Bp = pb + (size_t)J * 8 * g.gb.KB * FRAG_BYTES;
-                a.a_plane = g.ga.plane_bytes;
-                a.b_plane = g.gb.plane_bytes;
-                a.codeA = codeA + I * 256;
-                a.codeB = codeB + J * 256;
-                a.M = M - I * 256 < 256 ? M - I * 256 : 256;
-                a.N = N - J * 256 < 256 ? N - J * 256 : 256;
-                a.KB = g.ga.KB;
-                a.alpha = -1.0;
-                a.beta = 1.0;
-                a.C = A + (j1 + I * 256) + (long long)(j1 + J * 256) * ld;
-                a.ldc = ld;
-                gemm_tile_counts(s, a.M, a.N, &a.tiles_m, &a.tiles_n);
-                probs.push_back(a);
-                pre.push_back(pre.back() + a.tiles_m * a.tiles_n);
-            }
-            if (probs.empty()) continue;
-            EMU_TRY_HIP(hipMemcpyAsync(dprob, probs.data(), probs.size() * sizeof(GemmArgs),
-                                       hipMemcpyHostToDevice, st));
-            EMU_TRY_HIP(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int),
-                                       hipMemcpyHostToDevice, st));
-            EMU_TRY(launch_slicegemm_grouped(dprob, dpre, (int)probs.size(), pre.back(),
-                                             cus * gemm_grouped_blocks_per_cu(s), s, st));
-            // the host tables are reused by the next launch
-            EMU_TRY_HIP(hipStreamSynchronize(st));
+        EMU_TRY(launch_slice(L21, ld, 1, g.ga, s_full, codeA, pa, dev->status, st));
+        EMU_TRY(launch_slice(U12, ld, 0, g.gb, s_full, codeB, pb, dev->status, st));
+        AdaptiveTiles at{pa, pb, g.ga.plane_bytes, g.gb.plane_bytes, g.ga.KB, codeA, codeB,
+                         A + j1 + (long long)j1 * ld, ld, M, N, tm};
+        // tile columns holding the next panel's columns
+        const int jla = (jn + 255) / 256;
+        const bool la = la_on && jn > 0 && jla < tn;
+        const int jsplit = la ? jla : tn;
+        EMU_TRY(launch_adaptive_lists(smap, nt, s_full, at, 0, jsplit, dprob, dpre, dcnt, st));
+        if (la)
+            EMU_TRY(launch_adaptive_lists(smap, nt, s_full, at, jsplit, tn,
+                                          dprob + (size_t)9 * nt0, dpre + (size_t)9 * (nt0 + 1),
+                                          dcnt + 18, st));
+        EMU_TRY(gemms(0, nt, st));
+        if (la) {
+            EMU_TRY_HIP(hipEventRecord(dev->ev_go, st));
+            EMU_TRY_HIP(hipStreamWaitEvent(dev->side, dev->ev_go, 0));
+            EMU_TRY(gemms(1, nt, dev->side));
+            EMU_TRY_HIP(hipEventRecord(dev->ev_done, dev->side));
         }
+        if (jn > 0) EMU_TRY(panel(j1));
+        if (la) EMU_TRY_HIP(hipStreamWaitEvent(st, dev->ev_done, 0));
+    }
+    std::vector<int> hs((size_t)(rec > 0 ? rec : 1));
+    if (rec > 0) {
+        EMU_TRY_HIP(hipMemcpyAsync(hs.data(), drec, (size_t)rec * sizeof(int),
+                                   hipMemcpyDeviceToHost, st));
+        EMU_TRY_HIP(hipStreamSynchronize(st));
+    }
+    long long used = 0, full = 0;
+    const long long pfull = (long long)s_full * (s_full + 1) / 2;
+    for (const StepTiles &sp : steps) {
+        for (int q = 0; q < sp.nt; ++q) {
+            int sq = hs[sp.rec + q];
+            if (sq > s_full) sq = s_full;
+            hs[sp.rec + q] = sq;
+            const int I = q % sp.tm, J = q / sp.tm;
+            const long long area = (long long)(sp.M - I * 256 < 256 ? sp.M - I * 256 : 256) *
+                                   (sp.N - J * 256 < 256 ? sp.N - J * 256 : 256);
+            used += area * ((long long)sq * (sq + 1) / 2);
+            full += area * pfull;
+        }
+        if (smaps && sp.rec + sp.nt <= smaps_cap)
+            for (int q = 0; q < sp.nt; ++q) smaps[sp.rec + q] = hs[sp.rec + q];
     }
     products[0] = used;
     products[1] = full;

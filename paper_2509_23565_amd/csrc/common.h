@@ -165,12 +165,20 @@ bool gemm_supported(int s, int t);
 // tile_prefix (device, nprob + 1) is the running sum of tiles_m * tiles_n.
 // K of every problem must not need chunking (K <= 32 * 462 for s = 9).
 void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n);
+// Output tile of the slice GEMM at t = s + 1: tile_rows(s) x GEMM_TILE_COLS.
+__host__ __device__ constexpr int gemm_tile_rows(int s) { return s <= 5 ? 128 : 64; }
+constexpr int GEMM_TILE_COLS = 128;
 int gemm_grouped_blocks_per_cu(int s);
 // one_kstep: every problem has K <= 32 (one K step); selects the
 // pipelined kernel for s >= 6.
 int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
                              int total_tiles, int grid, int s, hipStream_t stream,
                              bool one_kstep = false);
+// The same with the problem count and the tile total read on the device
+// (counts[0], counts[1]), so the list can be built by a kernel; no launch
+// work is skipped on the host when the list is empty.
+int launch_slicegemm_grouped_dev(const GemmArgs *probs, const int *tile_prefix,
+                                 const int *counts, int grid, int s, hipStream_t stream);
 
 // FP64 LU pieces.
 int launch_fill_int(int *p, int v, int count, hipStream_t stream);
@@ -225,5 +233,22 @@ int launch_tile_err(const double *Xs, const double *Xr, long long ld, int m, int
                     double *err2, double *ref2, hipStream_t st);
 int launch_tile_label(const double *err2, const double *ref2, int ntiles, int s, double tau,
                       int *label, hipStream_t st);
+// Adaptive LU: the 256 x 256 tiles of one Schur update C -= L21 U12 and the
+// digit planes of L21 and U12 (sliced once at the largest count).
+struct AdaptiveTiles {
+    const int8_t *pa, *pb;
+    size_t a_plane, b_plane;
+    int KB;
+    const int *codeA, *codeB;
+    double *C;
+    long long ldc;
+    int M, N, tm;        // update size; tile rows tm = ceil(M / 256)
+};
+// For every count s = 1..9 the grouped-GEMM problem list of the tiles in
+// tile columns [jlo, jhi) whose slice count min(smap[q], s_cap) is s, in
+// tile order: probs[(s-1) nt + i], prefix[(s-1) (nt+1) + i],
+// counts[2 (s-1)] = problems, counts[2 (s-1) + 1] = GEMM tiles.
+int launch_adaptive_lists(const int *smap, int nt, int s_cap, const AdaptiveTiles &t, int jlo,
+                          int jhi, GemmArgs *probs, int *prefix, int *counts, hipStream_t st);
 
 }  // namespace emu

@@ -36,23 +36,28 @@ struct Stat {            // integer statistics of rho over one line block
 };
 
 __device__ __forceinline__ int fexp(double x) {   // frexp exponent (x != 0, finite)
-    unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    int eb = (int)((b >> 52) & 0x7ff);
-    unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
-    if (eb == 0) return (63 - __clzll((long long)fr)) - 1073;
-    return eb - 1022;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int eb = (int)((b >> 52) & 0x7ff);
+    const unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
+    // subnormal: the exponent of the leading fraction bit (selects, no branch)
+    const int sub = (63 - __clzll((long long)(fr | 1ull))) - 1073;
+    return eb == 0 ? sub : eb - 1022;
 }
 
 __device__ __forceinline__ bool usable(double x) { return x != 0.0 && isfinite(x); }
 
 // Statistics of one block of up to 256 lines of an operand.  by_rows: lines
-// are rows of X (rows x k), else columns of X (k x cols).  One thread per line.
-__global__ __launch_bounds__(FT) void k_feat_lines(const double *__restrict__ X, long long ldx,
-                                                   int lines, int k, int by_rows,
-                                                   Stat *__restrict__ out) {
+// are rows of X (rows x k), else columns of X (k x cols).  Four threads per
+// line, each over a quarter of K with eight loads in flight: the line's
+// largest exponent first (combined through LDS), then the integer sums.
+constexpr int FQ = 4;
+__global__ __launch_bounds__(FT * FQ) void k_feat_lines(const double *__restrict__ X,
+                                                        long long ldx, int lines, int k,
+                                                        int by_rows, Stat *__restrict__ out) {
     __shared__ long long s_cnt, s_sum, s_sq;
     __shared__ int s_mn, s_mx, s_hist[NBIN];
-    const int t = threadIdx.x;
+    __shared__ int s_e[FQ][FT];
+    const int t = threadIdx.x, tl = t % FT, qk = t / FT;
     if (t == 0) {
         s_cnt = 0;
         s_sum = 0;
@@ -61,32 +66,54 @@ __global__ __launch_bounds__(FT) void k_feat_lines(const double *__restrict__ X,
         s_mx = INT_MIN;
     }
     if (t < NBIN) s_hist[t] = 0;
+    const int line = blockIdx.x * FT + tl;
+    const int kq = (k + FQ - 1) / FQ, k0 = qk * kq, k1 = min(k, k0 + kq);
+    auto load8 = [&](int kk0, double (&xv)[8]) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kk = kk0 + u;
+            xv[u] = kk < k1 ? (by_rows ? X[line + (long long)kk * ldx]
+                                       : X[kk + (long long)line * ldx])
+                            : 0.0;
+        }
+    };
+    int e = INT_MIN;
+    if (line < lines) {
+        for (int kk0 = k0; kk0 < k1; kk0 += 8) {
+            double xv[8];
+            load8(kk0, xv);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (usable(xv[u])) e = max(e, fexp(xv[u]));
+        }
+    }
+    s_e[qk][tl] = e;
     __syncthreads();
-    const int line = blockIdx.x * FT + t;
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) e = max(e, s_e[q][tl]);
     long long cnt = 0, sum = 0, sq = 0;
     int mn = INT_MAX, mx = INT_MIN;
     int hist[NBIN];
 #pragma unroll
     for (int b = 0; b < NBIN; ++b) hist[b] = 0;
     if (line < lines) {
-        int e = INT_MIN;
-        for (int kk = 0; kk < k; ++kk) {
-            const double x = by_rows ? X[line + (long long)kk * ldx] : X[kk + (long long)line * ldx];
-            if (usable(x)) e = max(e, fexp(x));
-        }
-        for (int kk = 0; kk < k; ++kk) {
-            const double x = by_rows ? X[line + (long long)kk * ldx] : X[kk + (long long)line * ldx];
-            if (!usable(x)) continue;
-            const int rho = fexp(x) - e;
-            ++cnt;
-            sum += rho;
-            sq += (long long)rho * rho;
-            mn = min(mn, rho);
-            mx = max(mx, rho);
-            const int bin = min(NBIN - 1, (-rho) / 7);
+        for (int kk0 = k0; kk0 < k1; kk0 += 8) {
+            double xv[8];
+            load8(kk0, xv);
 #pragma unroll
-            for (int b = 0; b < NBIN; ++b)
-                if (b == bin) ++hist[b];
+            for (int u = 0; u < 8; ++u) {
+                if (!usable(xv[u])) continue;
+                const int rho = fexp(xv[u]) - e;
+                ++cnt;
+                sum += rho;
+                sq += (long long)rho * rho;
+                mn = min(mn, rho);
+                mx = max(mx, rho);
+                const int bin = min(NBIN - 1, (-rho) / 7);
+#pragma unroll
+                for (int b = 0; b < NBIN; ++b)
+                    if (b == bin) ++hist[b];
+            }
         }
     }
     atomicAdd((unsigned long long *)&s_cnt, (unsigned long long)cnt);
@@ -352,13 +379,83 @@ __global__ void k_tile_label(const double *__restrict__ err2, const double *__re
 // ------------------------------------------------------------- launchers
 int learned_nparam() { return NPARAM; }
 
+// Problem lists of the adaptive update, one per slice count, over the tiles
+// of tile columns [jlo, jhi): wave s - 1 walks the tiles in order, 64 at a
+// time; a ballot numbers the tiles of count s and a lane scan of their GEMM
+// tile counts extends the running prefix.
+static_assert(EMU_MAX_SLICES == 9, "one wave per slice count");
+__global__ __launch_bounds__(9 * 64) void k_adaptive_lists(const int *__restrict__ smap, int nt,
+                                                          int s_cap, AdaptiveTiles t, int jlo,
+                                                          int jhi, GemmArgs *__restrict__ probs,
+                                                          int *__restrict__ prefix,
+                                                          int *__restrict__ counts) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, s = w + 1;
+    GemmArgs *P = probs + (size_t)w * nt;
+    int *pre = prefix + (size_t)w * (nt + 1);
+    const int rows = gemm_tile_rows(s);
+    int np = 0, tot = 0;
+    if (lane == 0) pre[0] = 0;
+    for (int q0 = 0; q0 < nt; q0 += 64) {
+        const int q = q0 + lane;
+        const int sq = q < nt ? min(smap[q], s_cap) : 0;
+        const int Jq = q / t.tm;
+        const bool match = q < nt && sq == s && Jq >= jlo && Jq < jhi;
+        const unsigned long long mask = __ballot(match);
+        const int pos = np + __popcll(mask & ((1ull << lane) - 1ull));
+        int tc = 0;
+        if (match) {
+            const int I = q % t.tm, J = q / t.tm;
+            GemmArgs a{};
+            a.Ap = t.pa + (size_t)I * (FT / 32) * t.KB * FRAG_BYTES;
+            a.Bp = t.pb + (size_t)J * (FT / 32) * t.KB * FRAG_BYTES;
+            a.a_plane = t.a_plane;
+            a.b_plane = t.b_plane;
+            a.codeA = t.codeA + I * FT;
+            a.codeB = t.codeB + J * FT;
+            a.M = min(FT, t.M - I * FT);
+            a.N = min(FT, t.N - J * FT);
+            a.KB = t.KB;
+            a.alpha = -1.0;
+            a.beta = 1.0;
+            a.C = t.C + I * FT + (long long)J * FT * t.ldc;
+            a.ldc = t.ldc;
+            a.tiles_m = (a.M + rows - 1) / rows;
+            a.tiles_n = (a.N + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
+            tc = a.tiles_m * a.tiles_n;
+            P[pos] = a;
+        }
+        int x = tc;                                   // inclusive scan over lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (match) pre[pos + 1] = tot + x;
+        tot += __shfl(x, 63, 64);
+        np += __popcll(mask);
+    }
+    if (lane == 0) {
+        counts[2 * w] = np;
+        counts[2 * w + 1] = tot;
+    }
+}
+
+int launch_adaptive_lists(const int *smap, int nt, int s_cap, const AdaptiveTiles &t, int jlo,
+                          int jhi, GemmArgs *probs, int *prefix, int *counts, hipStream_t st) {
+    if (nt <= 0) return 0;
+    hipLaunchKernelGGL(k_adaptive_lists, dim3(1), dim3(9 * 64), 0, st, smap, nt, s_cap, t, jlo,
+                       jhi, probs, prefix, counts);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
 int launch_features(const double *L21, long long ldl, const double *U12, long long ldu, int m,
                     int n, int k, float *feat, void *stat_ws, hipStream_t st) {
     const int tm = (m + FT - 1) / FT, tn = (n + FT - 1) / FT;
     Stat *rs = static_cast<Stat *>(stat_ws);
     Stat *cs = rs + tm;
-    hipLaunchKernelGGL(k_feat_lines, dim3(tm), dim3(FT), 0, st, L21, ldl, m, k, 1, rs);
-    hipLaunchKernelGGL(k_feat_lines, dim3(tn), dim3(FT), 0, st, U12, ldu, n, k, 0, cs);
+    hipLaunchKernelGGL(k_feat_lines, dim3(tm), dim3(FT * FQ), 0, st, L21, ldl, m, k, 1, rs);
+    hipLaunchKernelGGL(k_feat_lines, dim3(tn), dim3(FT * FQ), 0, st, U12, ldu, n, k, 0, cs);
     hipLaunchKernelGGL(k_feat_tiles, dim3((tm * tn + 255) / 256), dim3(256), 0, st, rs, cs, tm,
                        tn, feat);
     EMU_TRY_HIP(hipGetLastError());

@@ -357,8 +357,13 @@ __global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
 template <int S, int T>
 __global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__restrict__ probs,
                                                            const int *__restrict__ tile_prefix,
-                                                           int nprob, int total) {
+                                                           int nprob, int total,
+                                                           const int *__restrict__ dcounts) {
     using CF = Cfg<S, T, false>;
+    if (dcounts) {              // list built on the device
+        nprob = dcounts[0];
+        total = dcounts[1];
+    }
     __shared__ __attribute__((aligned(1024))) int8_t lds[CF::NST * CF::STAGE];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int lo = __builtin_amdgcn_readfirstlane(wave_search(tile_prefix, nprob, tile));
@@ -682,15 +687,21 @@ int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
 
 void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n) {
     // plain t = s + 1 shapes (Cfg): 128 x 128 tiles while s <= 5, else 64 x 128
-    const int tmr = (s <= 5) ? 128 : 64, tnc = 128;
+    static_assert(Cfg<5, 6, false>::TM * 32 == gemm_tile_rows(5) &&
+                      Cfg<6, 7, false>::TM * 32 == gemm_tile_rows(6) &&
+                      Cfg<5, 6, false>::TN * 32 == GEMM_TILE_COLS &&
+                      Cfg<6, 7, false>::TN * 32 == GEMM_TILE_COLS,
+                  "tile shape");
+    const int tmr = gemm_tile_rows(s), tnc = GEMM_TILE_COLS;
     *tiles_m = (m + tmr - 1) / tmr;
     *tiles_n = (n + tnc - 1) / tnc;
 }
 
 int gemm_grouped_blocks_per_cu(int s) {
-    // LDS per workgroup: 2 buffers x s digits x (TM + TN) fragments of 1 KB
+    // LDS per workgroup: stages (4 while s <= 3, else 2) x s digits x
+    // (TM + TN) fragments of 1 KB
     const int frags = (s <= 5) ? 8 : 6;
-    const int kb = 2 * s * frags;
+    const int kb = (s <= 3 ? 4 : 2) * s * frags;
     int b = 160 / (kb > 0 ? kb : 1);
     return b < 1 ? 1 : (b > 2 ? 2 : b);
 }
@@ -718,7 +729,27 @@ int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int 
 #define EMU_GCASE(S_)                                                                  \
     case S_:                                                                           \
         hipLaunchKernelGGL((k_slicegemm_grouped<S_, S_ + 1>), dim3(grid), dim3(512), 0, \
-                           stream, probs, tile_prefix, nprob, total_tiles);            \
+                           stream, probs, tile_prefix, nprob, total_tiles, nullptr);   \
+        break;
+    switch (s) {
+        EMU_GCASE(1) EMU_GCASE(2) EMU_GCASE(3) EMU_GCASE(4) EMU_GCASE(5) EMU_GCASE(6)
+        EMU_GCASE(7) EMU_GCASE(8) EMU_GCASE(9)
+        default:
+            set_error("grouped GEMM: slice count %d unsupported", s);
+            return EMU_ERR_UNSUPPORTED;
+    }
+#undef EMU_GCASE
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_slicegemm_grouped_dev(const GemmArgs *probs, const int *tile_prefix,
+                                 const int *counts, int grid, int s, hipStream_t stream) {
+    if (grid <= 0) return 0;
+#define EMU_GCASE(S_)                                                                  \
+    case S_:                                                                           \
+        hipLaunchKernelGGL((k_slicegemm_grouped<S_, S_ + 1>), dim3(grid), dim3(512), 0, \
+                           stream, probs, tile_prefix, 0, 0, counts);                  \
         break;
     switch (s) {
         EMU_GCASE(1) EMU_GCASE(2) EMU_GCASE(3) EMU_GCASE(4) EMU_GCASE(5) EMU_GCASE(6)

@@ -71,15 +71,23 @@ def _trained_params():
     return p
 
 
-def test_adaptive_lu_bit_exact_given_its_maps():
+@pytest.mark.parametrize("m,n,nb,lookahead", [(800, 800, 128, 1), (800, 800, 128, 0),
+                                               (600, 900, 128, 1), (900, 600, 128, 1),
+                                               (700, 700, 256, 1)])
+def test_adaptive_lu_bit_exact_given_its_maps(m, n, nb, lookahead):
+    # with look-ahead the tiles over the next panel are updated first and the
+    # others on the side stream; every tile gets the same operations
     p = _trained_params()
-    A = matgen.phi_matrix(800, 800, 6.0, seed=60)
+    A = matgen.phi_matrix(m, n, 6.0, seed=60)
     Ag = emu.colmajor(A)
-    ipiv, info, smaps, (used, full) = emu.dgetrf_adaptive(Ag, p, nb=128, s_full=9)
-    n, nb = 800, 128
+    emu.set_param("lu_lookahead", lookahead)
+    try:
+        ipiv, info, smaps, (used, full) = emu.dgetrf_adaptive(Ag, p, nb=nb, s_full=9)
+    finally:
+        emu.set_param("lu_lookahead", 1)
     steps, k = [], 0
-    for j1 in range(nb, n, nb):
-        t = ((n - j1 + 255) // 256) ** 2
+    for j1 in range(nb, min(m, n), nb):
+        t = ((m - j1 + 255) // 256) * ((n - j1 + 255) // 256)
         steps.append(np.array(smaps[k:k + t]))
         k += t
     assert k == len(smaps)
