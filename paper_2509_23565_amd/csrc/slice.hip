@@ -24,9 +24,24 @@
 
 namespace emu {
 
-// Selects, no branches, so that loads of several elements can be in flight
-// before the first code is formed.
 __device__ __forceinline__ int exp_code(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    int eb = (int)((b >> 52) & 0x7ff);
+    unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
+    if (eb == 0x7ff) return CODE_NONFINITE;
+    if (eb == 0) {
+        if (fr == 0) return CODE_ZERO;
+        return (63 - __clzll((long long)fr)) - 1073;   // subnormal
+    }
+    return eb - 1022;
+}
+
+// The same code with selects instead of branches, for loops that keep
+// several loads in flight before the first code is formed (with branches
+// the compiler waits for each load in turn).  Only there: in the grouped
+// slicer it lets the compiler hoist all sixteen loads and both address
+// forms, and the register count grows threefold.
+__device__ __forceinline__ int exp_code_sel(double x) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(x);
     const int eb = (int)((b >> 52) & 0x7ff);
     const unsigned long long fr = b & 0xFFFFFFFFFFFFFull;
@@ -139,7 +154,7 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
                         xv[u] = kx < k ? X[line + (long long)kx * ldx] : 0.0;
                     }
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) m = max(m, exp_code(xv[u]));
+                    for (int u = 0; u < 8; ++u) m = max(m, exp_code_sel(xv[u]));
                 }
             } else {
                 const double *xl = X + (long long)line * ldx;
@@ -150,7 +165,7 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
 #pragma unroll
                     for (int u = 0; u < 8; ++u) xv[u] = kx0 + u < k1 ? xl[kx0 + u] : 0.0;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) m = max(m, exp_code(xv[u]));
+                    for (int u = 0; u < 8; ++u) m = max(m, exp_code_sel(xv[u]));
                 }
             }
         }
