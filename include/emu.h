@@ -158,8 +158,9 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
  *   emu_dgesv_ir on this thread count as failed, which exercises the
  *   fallback to more slices (a test hook; the checks still run).
  *   "lu_lookahead" (0 or 1, default 1): emu_dgetrf (and the LU inside
- *   emu_dgesv_ir) updates the columns right of the next panel on a
- *   library-owned side stream of the device while that panel is factored;
+ *   emu_dgesv_ir, and emu_dgetrf_adaptive) updates the columns right of
+ *   the next panel on a library-owned side stream of the device while that
+ *   panel is factored;
  *   the caller's stream waits for it, so the call stays ordered on the
  *   caller's stream.  The factors are identical either way.
  *   "leaf_cooperative" (0 or 1, default 0): panel leaves taller than 2048
@@ -312,11 +313,14 @@ int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const doubl
  * emu_dgetrf_adaptive: emu_dgetrf whose every Schur update uses a slice count
  * per 256 x 256 tile predicted by the MLP (params, device) from
  * emu_features of that update, capped at s_full; operands are sliced once at
- * the step's largest count and each tile uses the leading digit planes.
+ * s_full and each tile uses the leading digit planes.  The problem lists of
+ * every step are built on the device, and with "lu_lookahead" the tiles
+ * right of the next panel are updated on the side stream as in emu_dgetrf.
  * smaps (HOST int32, capacity smaps_cap, may be NULL) receives every step's
- * tile counts in order; products (HOST int64[3]) receives the slice products
- * used (sum of tile area x s(s+1)/2), the same at s_full, and the number of
- * tiles.  Synchronizes the stream once per block step.
+ * tile counts in order (a step whose tiles do not fit is left out); products
+ * (HOST int64[3]) receives the slice products used (sum of tile area x
+ * s(s+1)/2), the same at s_full, and the number of tiles.  Synchronizes the
+ * stream once, at the end (to return the maps).
  * Argument numbers: m=1 n=2 A=3 lda=4 ipiv=5 info=6 nb=7 params=8
  * s_full=9 conf=10 smaps=11 smaps_cap=12 products=13.
  */
