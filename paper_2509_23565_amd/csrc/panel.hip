@@ -1,7 +1,7 @@
 // FP64 panel factorization and triangular solves of the blocked LU
 // (paper: section "Dense Numerical Solvers Using FP64 Emulation": the panel,
 // where partial pivoting picks the pivots and U11^-1 reaches A21, stays in
-// FP64 custom code; eqn (8)'s Schur update is the only emulated step).
+// hand-written FP64 code; eqn (8)'s Schur update is the only emulated step).
 //
 // Every update is one rounded product and one rounded subtraction (this
 // library is compiled with -ffp-contract=off), and every element receives
