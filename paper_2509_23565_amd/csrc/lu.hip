@@ -72,21 +72,32 @@ size_t laswp_plan_bytes(int nrows) {
            (nrows > PERM_LDS_MAX ? align256((size_t)nrows * sizeof(int)) : 0);
 }
 
+// Only the rows a move can touch are visited: the J rows of the block and
+// the pivot targets below it (not all R rows: the permutation array is
+// initialised and scanned there alone).
 __global__ __launch_bounds__(64) void k_swap_plan(const int *__restrict__ ipiv, int k1, int k2,
                                                   int nrows, int row0, int *__restrict__ plan,
                                                   int *__restrict__ gperm) {
     __shared__ int lp[PERM_LDS_MAX];
     const int lane = threadIdx.x;
     const int R = nrows - k1;
+    const int J = k2 - k1;
+    const int Jr = J < R ? J : R;
+    const int base = row0 + k1;                  // global row of relative row 0
     int *pm = R <= PERM_LDS_MAX ? lp : gperm;
-    for (int r = lane; r < R; r += 64) pm[r] = r;
+    for (int r = lane; r < Jr; r += 64) pm[r] = r;
+    for (int k = lane; k < J; k += 64) {
+        const int p = ipiv[k1 + k] - 1 - base;
+        if (p >= Jr && p < R) pm[p] = p;
+    }
     wave_sync_mem();
-    compose_interchanges(pm, R, k2 - k1, ipiv + k1, row0 + k1);
+    compose_interchanges(pm, R, J, ipiv + k1, base);
     int count = 0;
-    for (int r0 = 0; r0 < R; r0 += 64) {
+    // rows of the block
+    for (int r0 = 0; r0 < Jr; r0 += 64) {
         const int r = r0 + lane;
-        const int src = r < R ? pm[r] : r;
-        const bool ch = r < R && src != r;
+        const int src = r < Jr ? pm[r] : r;
+        const bool ch = r < Jr && src != r;
         const unsigned long long m = __ballot(ch);
         if (ch) {
             const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
@@ -94,6 +105,32 @@ __global__ __launch_bounds__(64) void k_swap_plan(const int *__restrict__ ipiv, 
             plan[1 + SW_SLOTS + pos] = k1 + src;
         }
         count += __popcll(m);
+    }
+    // targets below the block, each once: the lowest lane of a chunk holding
+    // it, and a listed target is reset to itself so later chunks skip it
+    for (int c0 = 0; c0 < J; c0 += 64) {
+        const int k = c0 + lane;
+        int p = -1;
+        if (k < J) {
+            p = ipiv[k1 + k] - 1 - base;
+            if (p < Jr || p >= R) p = -1;
+        }
+        bool first = p >= 0 && pm[p] != p;
+        for (int l2 = 0; l2 < 64; ++l2) {
+            const int p2 = __builtin_amdgcn_readlane(p, l2);
+            if (l2 < lane && p2 == p) first = false;
+        }
+        const int src = first ? pm[p] : 0;
+        const unsigned long long m = __ballot(first);
+        if (first) {
+            const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+            plan[1 + pos] = k1 + p;
+            plan[1 + SW_SLOTS + pos] = k1 + src;
+        }
+        count += __popcll(m);
+        wave_sync_mem();
+        if (first) pm[p] = p;
+        wave_sync_mem();
     }
     if (lane == 0) plan[0] = count;
 }
