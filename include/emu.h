@@ -51,7 +51,7 @@ extern "C" {
 #define EMU_SUCCESS            0
 #define EMU_ERR_HIP            1001  /* a HIP runtime call failed */
 #define EMU_ERR_WORKSPACE      1002  /* scratch allocation failed */
-#define EMU_ERR_UNSUPPORTED    1003  /* valid request this build cannot run */
+#define EMU_ERR_UNSUPPORTED    1003  /* valid request the library does not support */
 #define EMU_ERR_NOT_CONVERGED  1004  /* refinement missed its tolerance at the
                                         largest slice count */
 
