@@ -20,7 +20,9 @@ double-double block), native FP64 DGEMM and LU
 (torch / ROCm libraries) on the same GPU, and the LU solves: the plain
 method (n = 1024, 7 slices), the precision form (n = 8192, reduced slices
 plus FP64 refinement to a backward error of 1e-15, against native FP64 with
-and without refinement) and the batched form (2000 uneven systems).
+and without refinement), the batched form (2000 uneven systems) and the
+learned slice count (an MLP trained on tiles of emulated LUs, then one
+n = 16384 solve with its per-tile counts; --no-learned skips it).
 """
 from __future__ import annotations
 
@@ -351,8 +353,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
-    ap.add_argument("--learned", action="store_true",
-                    help="add the learned slice-count leg (training on n = 8192 and "
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned slice-count leg (training on n = 8192 and "
                          "16384 emulated LUs, evaluation on an n = 16384 solve)")
     ap.add_argument("--lu-trace", type=str, default="",
                     help="N,NB,S[,ir|,batch]: only factor one N x N phi=1 matrix twice "
@@ -602,8 +604,12 @@ def main():
     # ------------------------------------------------------------ solvers
     if not args.no_lu:
         result["lu_solve"] = bench_solvers(args, emu, torch, matgen)
-    if args.learned:
-        result["learned_form"] = bench_learned(args, emu, torch, matgen)
+    if not args.no_lu and not args.no_learned:
+        try:
+            result["learned_form"] = bench_learned(args, emu, torch, matgen)
+        except Exception as e:          # reported in the line, not fatal to it
+            result["learned_form"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"learned leg failed: {e}")
 
     print(json.dumps(result), flush=True)
 
