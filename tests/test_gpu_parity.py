@@ -307,6 +307,21 @@ def test_getrs_bit_exact(n, nrhs):
     assert _same_bits(_host(Bg), x)
 
 
+@pytest.mark.parametrize("n", [2048, 2100])
+def test_getrs_bit_exact_large(n):
+    # many 64-row blocks, a ragged last block at n = 2100; synthetic factors
+    # (any LU array and valid pivots define a solve)
+    g = matgen.rng(17, n)
+    LU = np.asfortranarray(g.uniform(-1.0, 1.0, size=(n, n)))
+    LU[np.diag_indices(n)] += float(n)
+    piv = (np.arange(n) + (g.random(n) * (n - np.arange(n))).astype(np.int64)) + 1
+    B = matgen.uniform(n, 2, seed=18)
+    x = O.getrs(LU, piv, B)
+    Bg = emu.colmajor(B)
+    emu.dgetrs(emu.colmajor(LU), torch.as_tensor(piv.astype(np.int32), device="cuda"), Bg)
+    assert _same_bits(_host(Bg), x)
+
+
 def test_getrf_singular_reports_info():
     A = np.array(matgen.uniform(150, 150, seed=16), order="F")
     A[:, 77] = 0.0
