@@ -30,10 +30,19 @@
  *     buffer passed in, the library never frees or retains them;
  *   - dimensions are int; all index arithmetic inside is 64-bit;
  *   - calls are asynchronous on the calling thread's current stream (see
- *     emu_set_stream) unless stated otherwise; the library's own scratch
- *     memory (digit planes, exponents, partial sums) is allocated on first
- *     use, grown when a larger problem arrives (after synchronizing the
- *     stream) and released by emu_finalize;
+ *     emu_set_stream) unless stated otherwise;
+ *   - scratch memory (digit planes, exponents, partial sums) belongs to the
+ *     calling thread: either a workspace the caller registered with
+ *     emu_set_workspace (then no entry point allocates or synchronizes for
+ *     scratch; a call that needs more returns EMU_ERR_WORKSPACE), or a buffer
+ *     the library allocates on first use, grows when a larger problem
+ *     arrives (after synchronizing the device) and releases in emu_finalize.
+ *     Threads never share scratch, so threads may call the library
+ *     concurrently, each on its own stream.  When one thread moves to another
+ *     stream, its next call waits (an event) for the work of its previous
+ *     call, so one thread's calls never overlap on its scratch.  Two threads
+ *     that register the same workspace must order their calls themselves;
+ *     emu_finalize may not run while another thread is inside a call.
  *   - return value 0 on success; -i if argument i is invalid (LAPACK
  *     xerbla style, counting from 1); a positive EMU_ERR_* code otherwise.
  *     emu_last_error() describes the last failure of the calling thread.
@@ -50,10 +59,13 @@ extern "C" {
 
 #define EMU_SUCCESS            0
 #define EMU_ERR_HIP            1001  /* a HIP runtime call failed */
-#define EMU_ERR_WORKSPACE      1002  /* scratch allocation failed */
+#define EMU_ERR_WORKSPACE      1002  /* scratch allocation failed, or the
+                                        registered workspace is too small */
 #define EMU_ERR_UNSUPPORTED    1003  /* valid request the library does not support */
 #define EMU_ERR_NOT_CONVERGED  1004  /* refinement missed its tolerance at the
                                         largest slice count */
+#define EMU_ERR_PANEL_WAIT     1005  /* a factorization the call waited for was
+                                        aborted (see EMU_INFO_ABORTED) */
 
 #define EMU_STATUS_NONFINITE   1     /* an emulated GEMM met Inf/NaN input */
 #define EMU_STATUS_PANEL_WAIT  2     /* a multi-workgroup panel leaf (more than
@@ -61,7 +73,14 @@ extern "C" {
                                         exceeded its bound; those LU factors are
                                         invalid */
 
-#define EMU_MAX_SLICES         9     /* GPU slice-count range is 1..9 */
+/* Value an LU writes to its device *info when a multi-workgroup panel leaf
+ * gave up its bounded grid-wide wait (the factors are then invalid; the
+ * status word also carries EMU_STATUS_PANEL_WAIT).  Entry points that wait
+ * for their factorization return EMU_ERR_PANEL_WAIT instead. */
+#define EMU_INFO_ABORTED       (-1000)
+
+#define EMU_MAX_SLICES         16    /* slice counts of the plain GEMM and LU:
+                                        1..16 (grouped forms: 1..9) */
 
 /* Library version as major*10000 + minor*100 + patch. */
 int emu_version(void);
@@ -70,13 +89,35 @@ int emu_version(void);
  * entry point initialises on first use. */
 int emu_init(void);
 
-/* Release all scratch memory held by the library (all devices it touched).
- * Synchronizes the library streams first. */
+/* Release the scratch memory, streams and events the library holds for every
+ * thread on every device it touched (synchronizing each device first) and
+ * forget registered workspaces. */
 int emu_finalize(void);
 
 /* Set the HIP stream (hipStream_t passed as void*) used by later calls from
  * the calling thread; NULL selects the default (null) stream. */
 int emu_set_stream(void *hip_stream);
+
+/*
+ * emu_set_workspace: register `bytes` of DEVICE memory at dptr (owned by the
+ * caller, on the current device) as the calling thread's scratch for later
+ * calls on that device; dptr = NULL with bytes = 0 returns to the library's
+ * own scratch.  While a workspace is registered no entry point allocates or
+ * synchronizes to obtain scratch (the batched calls, the autotuner and
+ * emu_dgesv_ir still synchronize for their own reasons, and the autotuner
+ * allocates copies); a call that needs more than `bytes` fails with
+ * EMU_ERR_WORKSPACE and emu_last_error names the size it needs.  The
+ * library reads and writes the workspace only during calls, in stream order.
+ * Argument numbers: dptr=1 bytes=2.
+ */
+int emu_set_workspace(void *dptr, size_t bytes);
+
+/* Scratch bytes emu_dgemm needs for that shape (0 for invalid arguments). */
+size_t emu_workspace_bytes(int m, int n, int k, int nslices);
+/* Scratch bytes emu_dgetrf needs (nb <= 0: 64; 0 for invalid arguments). */
+size_t emu_getrf_workspace_bytes(int m, int n, int nb, int nslices);
+/* Scratch bytes emu_dgetrs needs (0 for invalid arguments). */
+size_t emu_getrs_workspace_bytes(int n, int nrhs);
 
 /* Text of the last error raised on the calling thread ("" if none). */
 const char *emu_last_error(void);
@@ -117,7 +158,7 @@ int emu_dgemm(int m, int n, int k, double alpha, const double *A, int lda,
 /*
  * emu_dgemm_t: emu_dgemm with an explicit truncation threshold t (the
  * paper's t: products A_i B_j with i + j > t are dropped).  Supported:
- * t = s + 1 for s in 1..9 and t = 2s (all s^2 products) for s in 1..5.
+ * t = s + 1 for s in 1..16 and t = 2s (all s^2 products) for s in 1..5.
  * Argument 13 is t.
  */
 int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
@@ -136,7 +177,10 @@ int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
  * (nslices in 1..EMU_MAX_SLICES, threshold t = s + 1).
  * ipiv (device, min(m,n) int32) receives 1-based row interchanges in
  * LAPACK order.  *info (device int32) receives 0, or i > 0 when U(i,i) is
- * exactly zero (the first such i); the factorization still completes.
+ * exactly zero (the first such i; the factorization still completes), or
+ * EMU_INFO_ABORTED when a panel taller than 2048 rows gave up its bounded
+ * grid-wide wait (the factors are then invalid; the call returned 0 before
+ * this happened, since it does not wait for the GPU).
  * Argument numbers: m=1 n=2 A=3 lda=4 ipiv=5 info=6 nb=7 nslices=8.
  */
 int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info,
@@ -185,14 +229,17 @@ int emu_set_param(const char *key, long long value);
  *      Otherwise, if eta did not fall below half its previous value, or
  *      `maxiter` corrections were applied, or eta is NaN: fall back (step 3);
  *      else X += getrs(R).
- *   3. Fallback: refactor with s = min(s + 2, EMU_MAX_SLICES) and restart at
- *      step 1's solve; if s was already EMU_MAX_SLICES return
+ *   3. Fallback: refactor with s = min(s + 2, s_cap) and restart at step 1's
+ *      solve, where s_cap = 9 for a start nslices <= 9 and EMU_MAX_SLICES
+ *      above (beyond nine slices the update is already below the FP64 panel's
+ *      own rounding at LU block sizes); if s was already s_cap return
  *      EMU_ERR_NOT_CONVERGED.
  * A n x n (lda >= max(1,n)), B and X n x nrhs (ldb, ldx >= max(1,n)), all
  * device; outputs on the HOST: *iters = corrections applied (all
  * factorizations), *berr = last eta, *s_final = slice count of the last
  * factorization, *info = its LAPACK info (> 0: exactly singular U, X not
- * refined).  Synchronizes the stream once per refinement step.
+ * refined).  Synchronizes the stream once per refinement step.  Returns
+ * EMU_ERR_PANEL_WAIT if a factorization was aborted (EMU_INFO_ABORTED).
  * Argument numbers: n=1 nrhs=2 A=3 lda=4 B=5 ldb=6 X=7 ldx=8 nb=9
  * nslices=10 tol=11 maxiter=12 iters=13 berr=14 s_final=15 info=16.
  */
@@ -213,6 +260,17 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
 int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int ldlu,
                const int *ipiv, const double *B, int ldb, double *X, int ldx, double tol,
                int maxiter, int *iters, double *berr);
+
+/*
+ * emu_scaled_residual: the scaled residual of eqn (9),
+ * ||A X - B||_inf / ((||A||_inf ||X||_inf + ||B||_inf) n eps) with
+ * eps = 2^-53, evaluated in FP64 on the GPU (residual columns summed in a
+ * fixed order), the largest over the nrhs columns; *sres on the HOST.  The
+ * HPL acceptance test is *sres < 16.  Synchronizes the stream.
+ * Argument numbers: n=1 nrhs=2 A=3 lda=4 X=5 ldx=6 B=7 ldb=8 sres=9.
+ */
+int emu_scaled_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
+                        const double *B, int ldb, double *sres);
 
 /*
  * Batched grouped form (not in the paper; every system is the paper's LU):
@@ -302,7 +360,8 @@ int emu_mlp_infer(const float *params, const float *X, int B, float *prob, int *
  * emu_tile_labels: training labels produced by the emulator: X_s = L21 U12
  * emulated with s slices for s = s_lo..s_hi; label of 256 x 256 tile q =
  * the smallest s with ||X_s - X_shi||_F <= tau ||X_shi||_F on that tile
- * (s_hi if none).  labels: device int32[tiles] (values s, not classes).
+ * (s_hi if none), 1 <= s_lo <= s_hi <= 9.  labels: device int32[tiles]
+ * (values s, not classes).
  * Argument numbers: m=1 n=2 k=3 L21=4 ldl=5 U12=6 ldu=7 s_lo=8 s_hi=9
  * tau=10 labels=11.
  */
@@ -312,7 +371,7 @@ int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const doubl
 /*
  * emu_dgetrf_adaptive: emu_dgetrf whose every Schur update uses a slice count
  * per 256 x 256 tile predicted by the MLP (params, device) from
- * emu_features of that update, capped at s_full; operands are sliced once at
+ * emu_features of that update, capped at s_full (3..9); operands are sliced once at
  * s_full and each tile uses the leading digit planes.  The problem lists of
  * every step are built on the device, and with "lu_lookahead" the tiles
  * right of the next panel are updated on the side stream as in emu_dgetrf.
@@ -320,7 +379,8 @@ int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const doubl
  * tile counts in order (a step whose tiles do not fit is left out); products
  * (HOST int64[3]) receives the slice products used (sum of tile area x
  * s(s+1)/2), the same at s_full, and the number of tiles.  Synchronizes the
- * stream once, at the end (to return the maps).
+ * stream once, at the end (to return the maps); returns EMU_ERR_PANEL_WAIT
+ * when *info then holds EMU_INFO_ABORTED.
  * Argument numbers: m=1 n=2 A=3 lda=4 ipiv=5 info=6 nb=7 params=8
  * s_full=9 conf=10 smaps=11 smaps_cap=12 products=13.
  */

@@ -22,6 +22,8 @@ import os
 __all__ = [
     "EmuError", "lib", "library_path", "EMU_MAX_SLICES",
     "emu_version", "emu_init", "emu_finalize", "emu_set_stream", "emu_last_error",
+    "emu_set_workspace", "emu_workspace_bytes", "emu_getrf_workspace_bytes",
+    "emu_getrs_workspace_bytes", "set_workspace", "EMU_INFO_ABORTED", "EMU_ERR_PANEL_WAIT",
     "emu_status", "emu_dgemm", "emu_dgemm_t", "emu_dgetrf", "emu_dgetrs",
     "emu_debug_slices", "emu_debug_products", "emu_profile_start",
     "emu_profile_stop", "emu_profile_read", "profile_read", "PROF_SLICE", "PROF_GEMM",
@@ -30,13 +32,17 @@ __all__ = [
     "dgetrf_batched", "dgesv_batched", "autotune_batched",
     "emu_mlp_nparam", "emu_features", "emu_mlp_train_step", "emu_mlp_grad", "emu_mlp_infer",
     "emu_tile_labels", "emu_dgetrf_adaptive", "features", "mlp_init", "mlp_train_step",
-    "emu_refine", "refine",
+    "emu_refine", "refine", "emu_scaled_residual", "scaled_residual",
     "mlp_grad", "mlp_infer", "tile_labels", "dgetrf_adaptive",
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status",
 ]
 
-EMU_MAX_SLICES = 9
+EMU_MAX_SLICES = 16
+EMU_ERR_WORKSPACE = 1002
+EMU_ERR_NOT_CONVERGED = 1004
+EMU_ERR_PANEL_WAIT = 1005
+EMU_INFO_ABORTED = -1000
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libemu.so")
 
@@ -55,6 +61,10 @@ _SIGNATURES = {
     "emu_init": ([], _I),
     "emu_finalize": ([], _I),
     "emu_set_stream": ([_P], _I),
+    "emu_set_workspace": ([_P, ctypes.c_size_t], _I),
+    "emu_workspace_bytes": ([_I, _I, _I, _I], ctypes.c_size_t),
+    "emu_getrf_workspace_bytes": ([_I, _I, _I, _I], ctypes.c_size_t),
+    "emu_getrs_workspace_bytes": ([_I, _I], ctypes.c_size_t),
     "emu_last_error": ([], ctypes.c_char_p),
     "emu_status": ([ctypes.POINTER(_I)], _I),
     "emu_dgemm": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
@@ -73,6 +83,7 @@ _SIGNATURES = {
                               ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "emu_refine": ([_I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _I, _D, _I, ctypes.POINTER(_I),
                     ctypes.POINTER(_D)], _I),
+    "emu_scaled_residual": ([_I, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(_D)], _I),
     "emu_mlp_nparam": ([], _I),
     "emu_features": ([_I, _I, _I, _P, _I, _P, _I, _P], _I),
     "emu_mlp_train_step": ([_P, _P, _P, _I, _P, _P, _I, ctypes.c_float, _P], _I),
@@ -117,6 +128,10 @@ emu_version = _raw("emu_version")
 emu_init = _raw("emu_init")
 emu_finalize = _raw("emu_finalize")
 emu_set_stream = _raw("emu_set_stream")
+emu_set_workspace = _raw("emu_set_workspace")
+emu_workspace_bytes = _raw("emu_workspace_bytes")
+emu_getrf_workspace_bytes = _raw("emu_getrf_workspace_bytes")
+emu_getrs_workspace_bytes = _raw("emu_getrs_workspace_bytes")
 emu_status = _raw("emu_status")
 emu_dgemm = _raw("emu_dgemm")
 emu_dgemm_t = _raw("emu_dgemm_t")
@@ -130,6 +145,7 @@ emu_dgetrf_batched = _raw("emu_dgetrf_batched")
 emu_dgesv_batched = _raw("emu_dgesv_batched")
 emu_autotune_batched = _raw("emu_autotune_batched")
 emu_refine = _raw("emu_refine")
+emu_scaled_residual = _raw("emu_scaled_residual")
 emu_mlp_nparam = _raw("emu_mlp_nparam")
 emu_features = _raw("emu_features")
 emu_mlp_train_step = _raw("emu_mlp_train_step")
@@ -246,6 +262,17 @@ def dgetrs(LU, ipiv, B):
     _bind_stream()
     _check(emu_dgetrs(n, nrhs, pl, lda, ipiv.data_ptr(), pb, ldb), "emu_dgetrs")
     return B
+
+
+def set_workspace(buf=None) -> None:
+    """Register a caller-owned device buffer (any CUDA tensor; its bytes) as
+    the calling thread's scratch, or go back to library-owned scratch with
+    None.  The caller keeps the tensor alive while it is registered."""
+    if buf is None:
+        _check(emu_set_workspace(None, 0), "emu_set_workspace")
+    else:
+        nbytes = buf.numel() * buf.element_size()
+        _check(emu_set_workspace(ctypes.c_void_p(buf.data_ptr()), nbytes), "emu_set_workspace")
 
 
 def set_param(key: str, value: int) -> None:
@@ -368,6 +395,20 @@ def refine(A, LU, ipiv, B, X, tol=1e-15, maxiter=10):
     if rc not in (0, 1004):
         _check(rc, "emu_refine")
     return rc, it.value, be.value
+
+
+def scaled_residual(A, X, B):
+    """Eqn (9) scaled residual of X for A X = B, in FP64 on the GPU (host float)."""
+    n = A.shape[0]
+    nrhs = B.shape[1]
+    pa, lda = _mat(A, "A")
+    px, ldx = _mat(X, "X")
+    pb, ldb = _mat(B, "B")
+    out = ctypes.c_double(0.0)
+    _bind_stream()
+    _check(emu_scaled_residual(n, nrhs, pa, lda, px, ldx, pb, ldb, ctypes.byref(out)),
+           "emu_scaled_residual")
+    return out.value
 
 
 # --------------------------------------------------------------- learned

@@ -16,6 +16,15 @@ static std::mutex g_mu;
 constexpr int MAX_DEVICES = 64;
 static Device g_devs[MAX_DEVICES];
 
+// The status word lives in the library's own device memory (one copy per
+// device, zero when the code object loads), so no call allocates it.
+static __device__ int g_status_word;
+
+// Every thread context ever created (for emu_finalize); a context is never
+// deleted, so a thread's pointer to its own stays valid.
+static std::vector<ThreadCtx *> g_ctxs;
+static thread_local ThreadCtx *t_ctx[MAX_DEVICES];
+
 void set_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -35,49 +44,107 @@ int current(Device **dev, hipStream_t *stream) {
         set_error("device id %d out of range", id);
         return EMU_ERR_UNSUPPORTED;
     }
-    std::lock_guard<std::mutex> lk(g_mu);
     Device &d = g_devs[id];
     if (d.id < 0) {
-        int *st = nullptr;
-        EMU_TRY_HIP(hipMalloc(&st, sizeof(int)));
-        EMU_TRY_HIP(hipMemset(st, 0, sizeof(int)));
-        d.status = st;
-        d.id = id;
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (d.id < 0) {
+            void *st = nullptr;
+            EMU_TRY_HIP(hipGetSymbolAddress(&st, HIP_SYMBOL(g_status_word)));
+            d.status = static_cast<int *>(st);
+            d.id = id;
+        }
     }
     *dev = &d;
     *stream = g_stream;
     return 0;
 }
 
-int reserve(Device *dev, hipStream_t stream, size_t bytes) {
-    (void)stream;
-    if (bytes <= dev->ws_bytes) return 0;
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (bytes <= dev->ws_bytes) return 0;
-    if (dev->ws) {
-        // scratch may be in use by work queued on any stream of this device
-        EMU_TRY_HIP(hipDeviceSynchronize());
-        EMU_TRY_HIP(hipFree(dev->ws));
-        dev->ws = nullptr;
-        dev->ws_bytes = 0;
+ThreadCtx *thread_ctx(const Device *dev) {
+    ThreadCtx *&c = t_ctx[dev->id];
+    if (!c) {
+        c = new ThreadCtx();
+        c->dev = dev->id;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_ctxs.push_back(c);
     }
-    size_t want = bytes + bytes / 8;
-    want = (want + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
+    return c;
+}
+
+static bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
         (void)hipGetLastError();
-        p = nullptr;
-        e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("scratch allocation of %zu bytes failed", bytes);
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+int acquire(const Device *dev, hipStream_t st, size_t bytes, char **ws) {
+    ThreadCtx *c = thread_ctx(dev);
+    if (c->pending && c->last != st && !capturing(st))
+        EMU_TRY_HIP(hipStreamWaitEvent(st, c->done, 0));
+    c->pending = false;
+    if (c->user) {
+        if (bytes > c->user_bytes) {
+            set_error("the registered workspace holds %zu bytes; this call needs %zu", c->user_bytes,
+                      bytes);
             return EMU_ERR_WORKSPACE;
         }
-        want = bytes;
+        *ws = c->user;
+        return 0;
     }
-    dev->ws = p;
-    dev->ws_bytes = want;
+    if (bytes > c->own_bytes) {
+        if (c->own) {
+            // the buffer may still be read by this thread's work on any stream
+            EMU_TRY_HIP(hipDeviceSynchronize());
+            EMU_TRY_HIP(hipFree(c->own));
+            c->own = nullptr;
+            c->own_bytes = 0;
+        }
+        size_t want = bytes + bytes / 8;
+        want = (want + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("scratch allocation of %zu bytes failed", bytes);
+                return EMU_ERR_WORKSPACE;
+            }
+            want = bytes;
+        }
+        c->own = static_cast<char *>(p);
+        c->own_bytes = want;
+    }
+    *ws = c->own ? c->own : nullptr;
+    return 0;
+}
+
+void release(const Device *dev, hipStream_t st) {
+    ThreadCtx *c = thread_ctx(dev);
+    c->last = st;
+    c->pending = false;
+    if (capturing(st)) return;        // ordering inside a graph is the caller's
+    if (!c->done && hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        c->done = nullptr;
+        return;
+    }
+    if (hipEventRecord(c->done, st) == hipSuccess)
+        c->pending = true;
+    else
+        (void)hipGetLastError();
+}
+
+int side_stream(ThreadCtx *c) {
+    if (!c->side) {
+        EMU_TRY_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        EMU_TRY_HIP(hipEventCreateWithFlags(&c->ev_go, hipEventDisableTiming));
+        EMU_TRY_HIP(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+    }
     return 0;
 }
 
@@ -188,18 +255,9 @@ static int gemm_core(Device *dev, char *ws, hipStream_t stream, const GemmScratc
 static inline int imax1(int a) { return a > 1 ? a : 1; }
 
 static thread_local int g_ir_force_fail = 0;
+// largest slice count refinement falls back to from a start of at most nine
+constexpr int IR_MAX_SLICES = 9;
 static thread_local int g_lu_lookahead = 1;
-
-// The device's side stream and its two events, created on first use.
-static int side_stream(Device *dev) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (!dev->side) {
-        EMU_TRY_HIP(hipStreamCreateWithFlags(&dev->side, hipStreamNonBlocking));
-        EMU_TRY_HIP(hipEventCreateWithFlags(&dev->ev_go, hipEventDisableTiming));
-        EMU_TRY_HIP(hipEventCreateWithFlags(&dev->ev_done, hipEventDisableTiming));
-    }
-    return 0;
-}
 
 // Scratch of one blocked LU: the largest trailing update's GEMM scratch
 // (the first update; later ones are smaller), then the panel's buffers.
@@ -240,7 +298,8 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
     const int mn = m < n ? m : n;
     const int t = s + 1;
     const bool la = g_lu_lookahead != 0 && mn > nb;
-    if (la) EMU_TRY(side_stream(dev));
+    ThreadCtx *tc = thread_ctx(dev);
+    if (la) EMU_TRY(side_stream(tc));
     // TRSM + emulated GEMM of columns [c0, c1) by the panel at (j0, jb)
     auto update = [&](int j0, int jb, int c0, int c1, hipStream_t sx) -> int {
         if (c1 <= c0) return 0;
@@ -275,13 +334,13 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
         const int j2 = j1 + jn;
         EMU_TRY(update(j0, jb, j1, j2, st));
         if (j2 < n) {
-            EMU_TRY_HIP(hipEventRecord(dev->ev_go, st));
-            EMU_TRY_HIP(hipStreamWaitEvent(dev->side, dev->ev_go, 0));
-            EMU_TRY(update(j0, jb, j2, n, dev->side));
-            EMU_TRY_HIP(hipEventRecord(dev->ev_done, dev->side));
+            EMU_TRY_HIP(hipEventRecord(tc->ev_go, st));
+            EMU_TRY_HIP(hipStreamWaitEvent(tc->side, tc->ev_go, 0));
+            EMU_TRY(update(j0, jb, j2, n, tc->side));
+            EMU_TRY_HIP(hipEventRecord(tc->ev_done, tc->side));
         }
         EMU_TRY(panel(j1));
-        if (j2 < n) EMU_TRY_HIP(hipStreamWaitEvent(st, dev->ev_done, 0));
+        if (j2 < n) EMU_TRY_HIP(hipStreamWaitEvent(st, tc->ev_done, 0));
     }
     return 0;
 }
@@ -304,20 +363,47 @@ int emu_finalize(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     EMU_TRY_HIP(hipGetDevice(&cur));
-    for (int i = 0; i < MAX_DEVICES; ++i) {
-        Device &d = g_devs[i];
-        if (d.id < 0) continue;
-        EMU_TRY_HIP(hipSetDevice(d.id));
+    for (ThreadCtx *c : g_ctxs) {
+        EMU_TRY_HIP(hipSetDevice(c->dev));
         EMU_TRY_HIP(hipDeviceSynchronize());
-        if (d.ws) EMU_TRY_HIP(hipFree(d.ws));
-        if (d.status) EMU_TRY_HIP(hipFree(d.status));
-        if (d.ev_go) EMU_TRY_HIP(hipEventDestroy(d.ev_go));
-        if (d.ev_done) EMU_TRY_HIP(hipEventDestroy(d.ev_done));
-        if (d.side) EMU_TRY_HIP(hipStreamDestroy(d.side));
-        d = Device();
+        if (c->own) EMU_TRY_HIP(hipFree(c->own));
+        if (c->done) EMU_TRY_HIP(hipEventDestroy(c->done));
+        if (c->ev_go) EMU_TRY_HIP(hipEventDestroy(c->ev_go));
+        if (c->ev_done) EMU_TRY_HIP(hipEventDestroy(c->ev_done));
+        if (c->side) EMU_TRY_HIP(hipStreamDestroy(c->side));
+        const int d = c->dev;
+        *c = ThreadCtx();             // the caller's workspace is forgotten too
+        c->dev = d;
     }
     EMU_TRY_HIP(hipSetDevice(cur));
     return 0;
+}
+
+int emu_set_workspace(void *dptr, size_t bytes) {
+    if (!dptr && bytes > 0) return -1;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    ThreadCtx *c = thread_ctx(dev);
+    c->user = bytes > 0 ? static_cast<char *>(dptr) : nullptr;
+    c->user_bytes = bytes > 0 ? bytes : 0;
+    return 0;
+}
+
+size_t emu_workspace_bytes(int m, int n, int k, int nslices) {
+    if (m < 0 || n < 0 || k < 0 || nslices < 1 || nslices > EMU_MAX_SLICES) return 0;
+    if (m == 0 || n == 0 || k == 0) return 0;
+    return gemm_scratch(m, n, k, nslices, nslices + 1).total;
+}
+
+size_t emu_getrf_workspace_bytes(int m, int n, int nb, int nslices) {
+    if (m < 0 || n < 0 || nb > 1024 || nslices < 1 || nslices > EMU_MAX_SLICES) return 0;
+    return getrf_scratch_bytes(m, n, nb <= 0 ? 64 : nb, nslices);
+}
+
+size_t emu_getrs_workspace_bytes(int n, int nrhs) {
+    if (n < 0 || nrhs < 0) return 0;
+    return getrs_scratch_bytes(n, nrhs);
 }
 
 int emu_profile_start(void) {
@@ -408,20 +494,19 @@ static int dgemm_impl(int m, int n, int k, double alpha, const double *A, int ld
         return EMU_ERR_UNSUPPORTED;
     }
     if (m == 0 || n == 0) return 0;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
-    if (k == 0 || alpha == 0.0) {
+    const bool quick = k == 0 || alpha == 0.0;
+    GemmScratch g = gemm_scratch(m, n, k, s, t, Dout != nullptr);
+    Call c;
+    EMU_TRY(c.begin(quick ? 0 : g.total));
+    if (quick) {
         if (Dout) {
-            EMU_TRY_HIP(hipMemsetAsync(Dout, 0, (size_t)(t - 1) * m * n * sizeof(int64_t), st));
+            EMU_TRY_HIP(hipMemsetAsync(Dout, 0, (size_t)(t - 1) * m * n * sizeof(int64_t), c.st));
             return 0;
         }
-        return scale_c(C, ldc, m, n, beta, st);
+        return scale_c(C, ldc, m, n, beta, c.st);
     }
-    GemmScratch g = gemm_scratch(m, n, k, s, t, Dout != nullptr);
-    EMU_TRY(reserve(dev, st, g.total));
-    return gemm_core(dev, static_cast<char *>(dev->ws), st, g, m, n, k, alpha, A, lda, B,
-                     ldb, beta, C, ldc, s, t, Dout);
+    return gemm_core(c.dev, c.ws, c.st, g, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, t,
+                     Dout);
 }
 
 int emu_dgemm(int m, int n, int k, double alpha, const double *A, int lda,
@@ -459,15 +544,15 @@ int emu_debug_slices(int rows, int cols, const double *X, int ldx, int by_rows,
     if (lines > 0 && !exps) return -7;
     if (lines > 0 && k > 0 && !digits) return -9;
     if (lines == 0) return 0;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
     Planes g = plane_geom(lines, k);
     size_t off_code = 0;
     size_t off_planes = align256((size_t)g.LB * 32 * sizeof(int));
     size_t total = off_planes + align256((size_t)nslices * g.plane_bytes);
-    EMU_TRY(reserve(dev, st, total));
-    char *ws = static_cast<char *>(dev->ws);
+    Call c;
+    EMU_TRY(c.begin(total));
+    Device *dev = c.dev;
+    hipStream_t st = c.st;
+    char *ws = c.ws;
     int *code = reinterpret_cast<int *>(ws + off_code);
     int8_t *planes = reinterpret_cast<int8_t *>(ws + off_planes);
     EMU_TRY(launch_slice(X, ldx, by_rows, g, nslices, code, planes, dev->status, st));
@@ -486,18 +571,11 @@ int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info, int nb,
     if (mn > 0 && !ipiv) return -5;
     if (!info) return -6;
     if (nb > 1024) return -7;
-    if (nslices < 1 || nslices > 16) return -8;
-    if (nslices > EMU_MAX_SLICES) {
-        set_error("emu_dgetrf: nslices=%d above %d", nslices, EMU_MAX_SLICES);
-        return EMU_ERR_UNSUPPORTED;
-    }
+    if (nslices < 1 || nslices > EMU_MAX_SLICES) return -8;
     if (nb <= 0) nb = 64;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
-    EMU_TRY(reserve(dev, st, getrf_scratch_bytes(m, n, nb, nslices)));
-    return getrf_impl(dev, static_cast<char *>(dev->ws), st, m, n, A, lda, ipiv, info, nb,
-                      nslices);
+    Call c;
+    EMU_TRY(c.begin(getrf_scratch_bytes(m, n, nb, nslices)));
+    return getrf_impl(c.dev, c.ws, c.st, m, n, A, lda, ipiv, info, nb, nslices);
 }
 
 int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv, double *B,
@@ -514,11 +592,9 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv, doub
         set_error("emu_dgetrs: nrhs above 65535");
         return EMU_ERR_UNSUPPORTED;
     }
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
-    EMU_TRY(reserve(dev, st, getrs_scratch_bytes(n, nrhs)));
-    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, static_cast<int *>(dev->ws), st);
+    Call c;
+    EMU_TRY(c.begin(getrs_scratch_bytes(n, nrhs)));
+    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, reinterpret_cast<int *>(c.ws), c.st);
 }
 
 int emu_set_param(const char *key, long long value) {
@@ -571,9 +647,6 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
         set_error("emu_dgesv_ir: nrhs above 65535");
         return EMU_ERR_UNSUPPORTED;
     }
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
     // scratch: LU copy | ipiv | info | R | partials | norm + stats | LU/solve scratch
     size_t off = 0;
     const size_t o_lu = off;
@@ -589,12 +662,18 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     const size_t o_stats = off;
     off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
     const size_t o_sub = off;
-    size_t sub = getrf_scratch_bytes(n, n, nb, EMU_MAX_SLICES);
+    // refinement falls back up to nine slices (or from a larger start up to
+    // the library's largest count)
+    const int s_cap = nslices > IR_MAX_SLICES ? EMU_MAX_SLICES : IR_MAX_SLICES;
+    size_t sub = getrf_scratch_bytes(n, n, nb, s_cap);
     const size_t sub2 = getrs_scratch_bytes(n, nrhs);
     if (sub2 > sub) sub = sub2;
     off += sub;
-    EMU_TRY(reserve(dev, st, off));
-    char *ws = static_cast<char *>(dev->ws);
+    Call call;
+    EMU_TRY(call.begin(off));
+    Device *dev = call.dev;
+    hipStream_t st = call.st;
+    char *ws = call.ws;
     double *LU = reinterpret_cast<double *>(ws + o_lu);
     int *ipiv = reinterpret_cast<int *>(ws + o_ipiv);
     int *dinfo = reinterpret_cast<int *>(ws + o_info);
@@ -619,6 +698,10 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
         EMU_TRY_HIP(hipStreamSynchronize(st));
         *info = hinfo;
         *s_final = s;
+        if (hinfo == EMU_INFO_ABORTED) {
+            set_error("emu_dgesv_ir: a panel leaf gave up its grid-wide wait (factors invalid)");
+            return EMU_ERR_PANEL_WAIT;
+        }
         if (hinfo > 0) return 0;       // exactly singular U: nothing to refine
         EMU_TRY(launch_copy_mat(B, ldb, X, ldx, n, nrhs, st));
         EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, X, ldx, reinterpret_cast<int *>(subws), st));
@@ -657,12 +740,12 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
             ++total_iters;
         }
         if (fallback) {
-            if (s >= EMU_MAX_SLICES) {
+            if (s >= s_cap) {
                 set_error("emu_dgesv_ir: no convergence to %g at %d slices (eta %g)", tol, s,
                           *berr);
                 return EMU_ERR_NOT_CONVERGED;
             }
-            s = s + 2 < EMU_MAX_SLICES ? s + 2 : EMU_MAX_SLICES;
+            s = s + 2 < s_cap ? s + 2 : s_cap;
         }
     }
 }
@@ -688,9 +771,6 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
     *iters = 0;
     *berr = 0.0;
     if (n == 0 || nrhs == 0) return 0;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
     size_t off = 0;
     const size_t o_r = off;
     off += align256((size_t)n * nrhs * sizeof(double));
@@ -700,8 +780,11 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
     off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
     const size_t o_sub = off;
     off += getrs_scratch_bytes(n, nrhs);
-    EMU_TRY(reserve(dev, st, off));
-    char *ws = static_cast<char *>(dev->ws);
+    Call call;
+    EMU_TRY(call.begin(off));
+    Device *dev = call.dev;
+    hipStream_t st = call.st;
+    char *ws = call.ws;
     double *R = reinterpret_cast<double *>(ws + o_r);
     double *part = reinterpret_cast<double *>(ws + o_part);
     double *normA = reinterpret_cast<double *>(ws + o_stats);
@@ -735,6 +818,52 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
     }
 }
 
+int emu_scaled_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
+                        const double *B, int ldb, double *sres) {
+    if (n < 0) return -1;
+    if (nrhs < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < imax1(n)) return -4;
+    if (n > 0 && nrhs > 0 && !X) return -5;
+    if (ldx < imax1(n)) return -6;
+    if (n > 0 && nrhs > 0 && !B) return -7;
+    if (ldb < imax1(n)) return -8;
+    if (!sres) return -9;
+    *sres = 0.0;
+    if (n == 0 || nrhs == 0) return 0;
+    size_t off = 0;
+    const size_t o_r = off;
+    off += align256((size_t)n * nrhs * sizeof(double));
+    const size_t o_part = off;
+    off += align256(refine_partial_bytes(n, nrhs));
+    const size_t o_stats = off;
+    off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
+    Call call;
+    EMU_TRY(call.begin(off));
+    hipStream_t st = call.st;
+    char *ws = call.ws;
+    double *R = reinterpret_cast<double *>(ws + o_r);
+    double *part = reinterpret_cast<double *>(ws + o_part);
+    double *normA = reinterpret_cast<double *>(ws + o_stats);
+    double *stats = normA + 1;
+    EMU_TRY(launch_norm_inf(A, lda, n, part, normA, st));
+    EMU_TRY(launch_residual(A, lda, n, X, ldx, B, ldb, nrhs, R, n, part, stats, st));
+    std::vector<double> h(1 + 3 * (size_t)nrhs);
+    EMU_TRY_HIP(hipMemcpyAsync(h.data(), normA, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               st));
+    EMU_TRY_HIP(hipStreamSynchronize(st));
+    // eqn (9) with eps = 2^-53, the largest over the right-hand sides
+    const double neps = (double)n * 0x1p-53;
+    double worst = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        const double den = (h[0] * h[1 + 3 * r + 1] + h[1 + 3 * r + 2]) * neps;
+        const double v = den > 0.0 ? h[1 + 3 * r] / den : h[1 + 3 * r];
+        if (!(v <= worst)) worst = v;       // NaN propagates
+    }
+    *sres = worst;
+    return 0;
+}
+
 // ------------------------------------------------------------ learned form
 int emu_mlp_nparam(void) { return learned_nparam(); }
 
@@ -749,11 +878,9 @@ int emu_features(int m, int n, int k, const double *L21, int ldl, const double *
     if (ldu < imax1(k)) return -7;
     if (m > 0 && n > 0 && !feat) return -8;
     if (m == 0 || n == 0) return 0;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
-    EMU_TRY(reserve(dev, st, features_ws_bytes(m, n)));
-    return launch_features(L21, ldl, U12, ldu, m, n, k, feat, dev->ws, st);
+    Call c;
+    EMU_TRY(c.begin(features_ws_bytes(m, n)));
+    return launch_features(L21, ldl, U12, ldu, m, n, k, feat, c.ws, c.st);
 }
 
 int emu_mlp_train_step(float *params, const float *X, const int *labels, int B, float *m,
@@ -766,11 +893,9 @@ int emu_mlp_train_step(float *params, const float *X, const int *labels, int B, 
     if (!v) return -6;
     if (step < 1) return -7;
     if (!(lr > 0.0f)) return -8;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
-    EMU_TRY(reserve(dev, st, mlp_train_ws_bytes(B)));
-    return launch_mlp_train_step(params, X, labels, B, m, v, step, lr, dev->ws, loss, st);
+    Call c;
+    EMU_TRY(c.begin(mlp_train_ws_bytes(B)));
+    return launch_mlp_train_step(params, X, labels, B, m, v, step, lr, c.ws, loss, c.st);
 }
 
 int emu_mlp_grad(const float *params, const float *X, const int *labels, int B, float *grad) {
@@ -779,11 +904,9 @@ int emu_mlp_grad(const float *params, const float *X, const int *labels, int B, 
     if (!labels) return -3;
     if (B < 1) return -4;
     if (!grad) return -5;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
-    EMU_TRY(reserve(dev, st, mlp_train_ws_bytes(B)));
-    return launch_mlp_grad_only(params, X, labels, B, grad, dev->ws, st);
+    Call c;
+    EMU_TRY(c.begin(mlp_train_ws_bytes(B)));
+    return launch_mlp_grad_only(params, X, labels, B, grad, c.ws, c.st);
 }
 
 int emu_mlp_infer(const float *params, const float *X, int B, float *prob, int *s_out,
@@ -809,13 +932,10 @@ int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const doubl
     if (ldl < m) return -5;
     if (!U12) return -6;
     if (ldu < k) return -7;
-    if (s_lo < 1 || s_lo > EMU_MAX_SLICES) return -8;
-    if (s_hi < s_lo || s_hi > EMU_MAX_SLICES) return -9;
+    if (s_lo < 1 || s_lo > GROUPED_MAX_SLICES) return -8;
+    if (s_hi < s_lo || s_hi > GROUPED_MAX_SLICES) return -9;
     if (!(tau > 0.0)) return -10;
     if (!labels) return -11;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
     const int tm = (m + 255) / 256, tn = (n + 255) / 256, nt = tm * tn;
     // scratch: X_ref | X_s | err2 | ref2 | GEMM scratch
     size_t off = 0;
@@ -830,8 +950,11 @@ int emu_tile_labels(int m, int n, int k, const double *L21, int ldl, const doubl
     const size_t o_g = off;
     GemmScratch g = gemm_scratch(m, n, k, s_hi, s_hi + 1);
     off += g.total;
-    EMU_TRY(reserve(dev, st, off));
-    char *ws = static_cast<char *>(dev->ws);
+    Call call;
+    EMU_TRY(call.begin(off));
+    Device *dev = call.dev;
+    hipStream_t st = call.st;
+    char *ws = call.ws;
     double *Xr = reinterpret_cast<double *>(ws + o_ref);
     double *Xs = reinterpret_cast<double *>(ws + o_x);
     double *e2 = reinterpret_cast<double *>(ws + o_e);
@@ -863,14 +986,11 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     if (!info) return -6;
     if (nb > 1024) return -7;
     if (!params) return -8;
-    if (s_full < 3 || s_full > EMU_MAX_SLICES) return -9;
+    if (s_full < 3 || s_full > GROUPED_MAX_SLICES) return -9;
     if (!(conf > 0.0f && conf <= 1.0f)) return -10;
     if (smaps_cap < 0) return -12;
     if (!products) return -13;
     if (nb <= 0) nb = 64;
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
     const int jb0 = nb < mn ? nb : mn;
     const int M0 = m - jb0 > 0 ? m - jb0 : 1, N0 = n - jb0 > 0 ? n - jb0 : 1;
     const int tm0 = (M0 + 255) / 256, tn0 = (N0 + 255) / 256, nt0 = tm0 * tn0;
@@ -902,8 +1022,11 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     }
     const size_t o_rec = off;
     off += align256((size_t)(rec_total > 0 ? rec_total : 1) * sizeof(int));
-    EMU_TRY(reserve(dev, st, off));
-    char *ws = static_cast<char *>(dev->ws);
+    Call call;
+    EMU_TRY(call.begin(off));
+    Device *dev = call.dev;
+    hipStream_t st = call.st;
+    char *ws = call.ws;
     char *lws = ws + o_lu;
     char *pws = lws + getrf_gemm_bytes(m, n, nb, s_full);
     int *plan = reinterpret_cast<int *>(pws + align256(panel_scratch_bytes(m)));
@@ -936,7 +1059,8 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     if (cus <= 0) cus = 256;
     const long long ld = lda;
     const bool la_on = g_lu_lookahead != 0 && mn > nb;
-    if (la_on) EMU_TRY(side_stream(dev));
+    ThreadCtx *tc = thread_ctx(dev);
+    if (la_on) EMU_TRY(side_stream(tc));
     auto panel = [&](int j0) -> int {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         return launch_panel(A + j0 + (long long)j0 * ld, ld, m - j0, jb, ipiv + j0, j0, info,
@@ -1006,19 +1130,24 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
                                           dcnt + 18, st));
         EMU_TRY(gemms(0, nt, st));
         if (la) {
-            EMU_TRY_HIP(hipEventRecord(dev->ev_go, st));
-            EMU_TRY_HIP(hipStreamWaitEvent(dev->side, dev->ev_go, 0));
-            EMU_TRY(gemms(1, nt, dev->side));
-            EMU_TRY_HIP(hipEventRecord(dev->ev_done, dev->side));
+            EMU_TRY_HIP(hipEventRecord(tc->ev_go, st));
+            EMU_TRY_HIP(hipStreamWaitEvent(tc->side, tc->ev_go, 0));
+            EMU_TRY(gemms(1, nt, tc->side));
+            EMU_TRY_HIP(hipEventRecord(tc->ev_done, tc->side));
         }
         if (jn > 0) EMU_TRY(panel(j1));
-        if (la) EMU_TRY_HIP(hipStreamWaitEvent(st, dev->ev_done, 0));
+        if (la) EMU_TRY_HIP(hipStreamWaitEvent(st, tc->ev_done, 0));
     }
     std::vector<int> hs((size_t)(rec > 0 ? rec : 1));
-    if (rec > 0) {
+    int hinfo = 0;
+    if (rec > 0)
         EMU_TRY_HIP(hipMemcpyAsync(hs.data(), drec, (size_t)rec * sizeof(int),
                                    hipMemcpyDeviceToHost, st));
-        EMU_TRY_HIP(hipStreamSynchronize(st));
+    EMU_TRY_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    EMU_TRY_HIP(hipStreamSynchronize(st));
+    if (hinfo == EMU_INFO_ABORTED) {
+        set_error("emu_dgetrf_adaptive: a panel leaf gave up its grid-wide wait (factors invalid)");
+        return EMU_ERR_PANEL_WAIT;
     }
     long long used = 0, full = 0;
     const long long pfull = (long long)s_full * (s_full + 1) / 2;

@@ -748,7 +748,7 @@ static int check_batch(int count, const int *n, const int *nrhs, double *const *
     if (count > 0 && !info) return -7;
     if (solve && count > 0 && (!B || !ldb)) return -8;
     if (nb < 0 || nb > BMAX_NB) return -9;
-    if (nslices < 1 || nslices > EMU_MAX_SLICES) return -10;
+    if (nslices < 1 || nslices > GROUPED_MAX_SLICES) return -10;
     for (int i = 0; i < count; ++i) {
         if (n[i] < 1 || n[i] > BMAX_N) {
             set_error("batched: system %d has n = %d (supported 1..%d)", i, n[i], BMAX_N);
@@ -767,38 +767,41 @@ static int check_batch(int count, const int *n, const int *nrhs, double *const *
     return 0;
 }
 
-// Factor (and solve) a batch through the cached graph of its shape.
+// Factor (and solve) a batch through the cached graph of its shape.  A graph
+// is tied to the scratch it was captured with (its descriptor tables and
+// digit planes live there): a call whose scratch is elsewhere captures anew.
 static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
                      const int *lda, int *const *ipiv, int *info, double *const *B,
                      const int *ldb, int nb, int nslices, int mult, bool solve) {
-    Device *dev;
-    hipStream_t st;
-    EMU_TRY(current(&dev, &st));
     std::lock_guard<std::mutex> lk(g_bmu);
     const std::string key = shape_key(count, n, nrhs, nb, nslices, solve, mult);
     auto it = g_graphs.find(key);
-    if (it == g_graphs.end() || it->second.ws != dev->ws) {
-        if (it != g_graphs.end()) {
-            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
-            g_graphs.erase(it);
-        }
-        GraphEntry e;
+    GraphEntry e;
+    size_t need;
+    if (it != g_graphs.end()) {
+        need = it->second.plan.total;
+    } else {
         plan_shape(e.plan, count, n, nrhs, nb, nslices, solve);
         e.plan.grid_mult = mult;
-        const void *before = dev->ws;
-        EMU_TRY(reserve(dev, st, e.plan.total));
-        if (dev->ws != before) {                 // scratch moved: every graph is stale
-            for (auto &kv : g_graphs)
-                if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-            g_graphs.clear();
-        }
-        char *base = static_cast<char *>(dev->ws);
+        need = e.plan.total;
+    }
+    Call call;
+    EMU_TRY(call.begin(need));
+    hipStream_t st = call.st;
+    char *base = call.ws;
+    if (it != g_graphs.end() && it->second.ws != base) {
+        e.plan = std::move(it->second.plan);
+        if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+        g_graphs.erase(it);
+        it = g_graphs.end();
+    }
+    if (it == g_graphs.end()) {
         plan_fill(e.plan, n, nrhs, A, lda, ipiv, info, B, ldb, base);
         EMU_TRY(plan_upload(e.plan, base, st));
         hipStream_t cap;
         EMU_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         EMU_TRY_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        int rc = plan_launch(e.plan, base, dev->status, device_cus(), cap);
+        int rc = plan_launch(e.plan, base, call.dev->status, device_cus(), cap);
         hipGraph_t graph = nullptr;
         hipError_t ec = hipStreamEndCapture(cap, &graph);
         (void)hipStreamDestroy(cap);
@@ -810,12 +813,11 @@ static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
         ec = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ec != hipSuccess) return fail_hip(ec, "hipGraphInstantiate");
-        e.ws = dev->ws;
+        e.ws = base;
         it = g_graphs.emplace(key, std::move(e)).first;
     } else {
-        plan_fill(it->second.plan, n, nrhs, A, lda, ipiv, info, B, ldb,
-                  static_cast<char *>(dev->ws));
-        EMU_TRY(plan_upload(it->second.plan, static_cast<char *>(dev->ws), st));
+        plan_fill(it->second.plan, n, nrhs, A, lda, ipiv, info, B, ldb, base);
+        EMU_TRY(plan_upload(it->second.plan, base, st));
     }
     EMU_TRY_HIP(hipGraphLaunch(it->second.exec, st));
     return 0;

@@ -30,9 +30,23 @@ int fail_hip(hipError_t e, const char *what);
 // ------------------------------------------------------ device context
 struct Device {
     int id = -1;
-    int *status = nullptr;        // device word: OR of EMU_STATUS_* bits
-    void *ws = nullptr;           // library scratch
-    size_t ws_bytes = 0;
+    int *status = nullptr;        // device word: OR of EMU_STATUS_* bits (a
+                                  // file-scope __device__ variable of the library)
+};
+
+// State of one thread on one device.  Scratch belongs to a thread, so two
+// threads never share it; a thread that moves to another stream has its next
+// call ordered after the work of its previous call (an event), so one
+// thread's calls never overlap on its scratch either.
+struct ThreadCtx {
+    int dev = -1;
+    char *own = nullptr;          // library-owned scratch (grown on demand)
+    size_t own_bytes = 0;
+    char *user = nullptr;         // caller's workspace (emu_set_workspace)
+    size_t user_bytes = 0;
+    hipStream_t last = nullptr;   // stream of the previous call
+    hipEvent_t done = nullptr;    // recorded on it at the end of that call
+    bool pending = false;
     hipStream_t side = nullptr;   // LU look-ahead: trailing updates (default priority)
     hipEvent_t ev_go = nullptr;   // main stream -> side stream
     hipEvent_t ev_done = nullptr; // side stream -> main stream
@@ -40,8 +54,42 @@ struct Device {
 
 // Current device's state (initialised on first use) and the thread's stream.
 int current(Device **dev, hipStream_t *stream);
-// Make sure dev->ws holds at least `bytes` (synchronizes `stream` to grow).
-int reserve(Device *dev, hipStream_t stream, size_t bytes);
+// The calling thread's context on the device.
+ThreadCtx *thread_ctx(const Device *dev);
+// Scratch of at least `bytes` for a call on `st`: the caller's workspace when
+// one is registered (EMU_ERR_WORKSPACE if it is too small), else the thread's
+// own buffer (grown after a device synchronization).  Orders `st` after the
+// thread's previous call when that ran on another stream.
+int acquire(const Device *dev, hipStream_t st, size_t bytes, char **ws);
+// End of a call's work on `st` (records the ordering event).
+void release(const Device *dev, hipStream_t st);
+// The thread's side stream and its two events (created on first use).
+int side_stream(ThreadCtx *c);
+
+// One entry point's use of the device: begin() finds the device and stream
+// and takes `bytes` of scratch; the destructor marks the end of the call.
+struct Call {
+    Device *dev = nullptr;
+    hipStream_t st = nullptr;
+    char *ws = nullptr;
+    bool held = false;
+    int begin(size_t bytes) {
+        int r = current(&dev, &st);
+        if (r) return r;
+        r = acquire(dev, st, bytes, &ws);
+        if (r) return r;
+        held = true;
+        return 0;
+    }
+    ~Call() {
+        if (held) release(dev, st);
+    }
+};
+
+// Slice counts of the grouped launches (batched LU, adaptive LU and its
+// learned map, whose classes are s = 3..9): 1..9.  The plain emulated GEMM
+// and LU take 1..EMU_MAX_SLICES.
+constexpr int GROUPED_MAX_SLICES = 9;
 
 // ----------------------------------------------------------- geometry
 // Exponent codes kept per line during a scan: INT_MIN for a line of zeros

@@ -28,7 +28,8 @@
 //     round.  Leaves taller than 2048 rows run as one launch of up to 32
 //     workgroups that exchange their candidates the same way through global
 //     memory, with one grid-wide wait per column (bounded: a wait that
-//     exceeds its bound aborts the leaf and raises EMU_STATUS_PANEL_WAIT).
+//     exceeds its bound aborts the leaf, sets info to EMU_INFO_ABORTED and
+//     raises EMU_STATUS_PANEL_WAIT).
 #include "common.h"
 #include "devutil.h"
 
@@ -545,7 +546,13 @@ __global__ __launch_bounds__(NT) void k_leaf(double *__restrict__ P, long long l
         for (int j = 0; j < LEAF_W; ++j)
             v[q][j] = (i < rows && j < w) ? P[i + (long long)j * lda] : 0.0;
     }
-    if (!leaf_cols<MULTI, NT>(v, L, rows, w, base_row, g, x, base)) return;
+    if (!leaf_cols<MULTI, NT>(v, L, rows, w, base_row, g, x, base)) {
+        // a grid-wide wait gave up: the factors are invalid; say so in info
+        // (every aborting workgroup stores the same value)
+        if (t == 0) __hip_atomic_store(info, EMU_INFO_ABORTED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * NT;

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "emu.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|int)\s*(emu_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|int|size_t)\s*(emu_\w+)\s*\(",
                                  text, re.M)))
 
 
@@ -54,7 +54,10 @@ def test_dgemm_argument_errors(args, code):
 
 
 def test_dgemm_unsupported_slice_count():
-    assert emu.emu_dgemm(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 12) == 1003
+    # 1..16 slices are accepted (on a machine without a GPU the call then
+    # fails in the runtime, 1001); all-pairs thresholds stop at s = 5
+    for s in (10, 12, 16):
+        assert emu.emu_dgemm(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, s) not in (-12, 1003)
     assert emu.emu_dgemm_t(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7, 14) == 1003
     assert emu.emu_dgemm_t(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 3, 7) == -13
 
@@ -66,7 +69,24 @@ def test_lu_argument_errors():
     assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), None, 64, 7) == -6
     assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 2048, 7) == -7
     assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 64, 0) == -8
+    assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 64, 17) == -8
     assert emu.emu_dgetrs(4, 1, _p(), 3, _p(), _p(), 4) == -4
     assert emu.emu_dgetrs(4, -1, _p(), 4, _p(), _p(), 4) == -2
     assert emu.emu_dgetrs(4, 1, _p(), 4, _p(), _p(), 2) == -7
     assert emu.emu_status(None) == -1
+
+
+def test_workspace_calls_argument_codes_and_sizes():
+    assert emu.emu_set_workspace(None, 4096) == -1
+    assert emu.emu_workspace_bytes(-1, 4, 4, 7) == 0
+    assert emu.emu_workspace_bytes(4, 4, 4, 0) == 0
+    assert emu.emu_workspace_bytes(4, 4, 4, emu.EMU_MAX_SLICES + 1) == 0
+    assert emu.emu_workspace_bytes(0, 4, 4, 7) == 0
+    # digit planes: s planes of lines padded to 128 and K to 32, 1 byte each
+    small = emu.emu_workspace_bytes(100, 100, 100, 3)
+    assert small >= 2 * 3 * 128 * 128
+    assert emu.emu_workspace_bytes(100, 100, 100, 7) > small
+    assert emu.emu_getrf_workspace_bytes(4, 4, 2048, 7) == 0
+    assert emu.emu_getrf_workspace_bytes(1000, 1000, 128, 7) > 0
+    assert emu.emu_getrs_workspace_bytes(-1, 1) == 0
+    assert emu.emu_getrs_workspace_bytes(1000, 2) >= 1000 * 2 * 8
