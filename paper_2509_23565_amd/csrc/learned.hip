@@ -383,7 +383,7 @@ int learned_nparam() { return NPARAM; }
 // of tile columns [jlo, jhi): wave s - 1 walks the tiles in order, 64 at a
 // time; a ballot numbers the tiles of count s and a lane scan of their GEMM
 // tile counts extends the running prefix.
-static_assert(EMU_MAX_SLICES == 9, "one wave per slice count");
+static_assert(GROUPED_MAX_SLICES == 9, "one wave per slice count");
 __global__ __launch_bounds__(9 * 64) void k_adaptive_lists(const int *__restrict__ smap, int nt,
                                                           int s_cap, AdaptiveTiles t, int jlo,
                                                           int jhi, GemmArgs *__restrict__ probs,

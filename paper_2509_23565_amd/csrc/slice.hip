@@ -11,7 +11,8 @@
 //   exponents.
 // Pass 2 (k_slice_*): digits by exact integer arithmetic on the significand:
 //   with |x| = M 2^E (M the 53-bit significand), Z = floor(|x| 2^(7s - e))
-//   is M shifted by E - e + 7s bits (Z < 2^(7s) <= 2^63), and digit i
+//   is M shifted by E - e + 7s bits (Z < 2^(7s): 64-bit words up to s = 9,
+//   128-bit words for s = 10..16), and digit i
 //   (1-based) is bits 7(s-i)..7(s-i)+6 of Z with the sign of x.  This equals
 //   the truncated base-128 expansion of x 2^-e digit by digit.
 // Both passes read the operand once (8 bytes per element each); pass 2
@@ -21,6 +22,8 @@
 // the line K / 32 times in all, from cache), and the wave of the first K
 // block stores them; no fill and no scan launch precede it.
 #include "common.h"
+
+#include <type_traits>
 
 namespace emu {
 
@@ -56,9 +59,15 @@ __device__ __forceinline__ int code_to_exp(int c) {
     return (c == CODE_ZERO || c == CODE_NONFINITE) ? 0 : c;
 }
 
-// Z = floor(|x| 2^(7s - e)), sign of x.
-__device__ __forceinline__ unsigned long long digits_word(double x, int e, int s,
-                                                         int *neg) {
+// Z = floor(|x| 2^(7s - e)), sign of x, in 64 bits while 7s <= 63 and in
+// 128 bits above (s = 10..16: Z < 2^(7s) <= 2^112).  |x| < 2^e gives
+// E - e < -52 for the 53-bit significand M = |x| 2^-E, so the left shift
+// below is at most 7s - 53 bits (at most 10 for s <= 9, 59 for s = 16).
+template <int S>
+using ZWord = typename std::conditional<(S <= 9), unsigned long long, unsigned __int128>::type;
+
+template <int S>
+__device__ __forceinline__ ZWord<S> digits_word(double x, int e, int *neg) {
     unsigned long long b = (unsigned long long)__double_as_longlong(x);
     *neg = (int)(b >> 63);
     int eb = (int)((b >> 52) & 0x7ff);
@@ -71,10 +80,10 @@ __device__ __forceinline__ unsigned long long digits_word(double x, int e, int s
         E = eb - 1075;
     }
     if (M == 0) return 0;
-    int sh = E - e + 7 * s;
-    if (sh >= 0) return M << sh;       // value < 2^(7s) by choice of e
+    int sh = E - e + 7 * S;
+    if (sh >= 0) return (ZWord<S>)M << sh;   // value < 2^(7S) by choice of e
     if (sh <= -64) return 0;
-    return M >> (-sh);
+    return (ZWord<S>)(M >> (-sh));
 }
 
 // ------------------------------------------------------------------ scans
@@ -213,10 +222,10 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X,
                 x = tile[(threadIdx.x >> 6) & 3][(lane & 31) * SL_TILE_LD + (lane >> 5) * 16 + kk];
         }
         int neg;
-        unsigned long long Z = digits_word(x, e, S, &neg);
+        const ZWord<S> Z = digits_word<S>(x, e, &neg);
 #pragma unroll
         for (int d = 0; d < S; ++d) {
-            int q = (int)((Z >> (7 * (S - 1 - d))) & 127ull);
+            int q = (int)((Z >> (7 * (S - 1 - d))) & 127u);
             if (neg) q = -q;
             w[d][kk >> 2] |= ((unsigned int)(q & 0xff)) << (8 * (kk & 3));
         }
@@ -310,6 +319,13 @@ int launch_slice(const double *X, long long ldx, int by_rows, const Planes &g,
         case 7: launch_slice_s<7>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
         case 8: launch_slice_s<8>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
         case 9: launch_slice_s<9>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 10: launch_slice_s<10>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 11: launch_slice_s<11>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 12: launch_slice_s<12>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 13: launch_slice_s<13>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 14: launch_slice_s<14>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 15: launch_slice_s<15>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
+        case 16: launch_slice_s<16>(X, ldx, by_rows, g, code, planes, status, fused, stream); break;
         default:
             set_error("slice count %d outside 1..%d", s, EMU_MAX_SLICES);
             return EMU_ERR_UNSUPPORTED;
@@ -358,10 +374,10 @@ __global__ __launch_bounds__(256) void k_slice_small_grouped(const SliceJob *__r
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
         int neg;
-        const unsigned long long Z = digits_word(good ? x[kk] : 0.0, e, S, &neg);
+        const ZWord<S> Z = digits_word<S>(good ? x[kk] : 0.0, e, &neg);
 #pragma unroll
         for (int d = 0; d < S; ++d) {
-            int q = (int)((Z >> (7 * (S - 1 - d))) & 127ull);
+            int q = (int)((Z >> (7 * (S - 1 - d))) & 127u);
             if (neg) q = -q;
             w[d][kk >> 2] |= ((unsigned int)(q & 0xff)) << (8 * (kk & 3));
         }

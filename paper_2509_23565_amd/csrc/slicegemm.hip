@@ -23,8 +23,8 @@
 // Exactness: a slot holding p pairs over a K range of length L is bounded by
 // p L 127^2, which must stay below 2^31.  The longest diagonal (t = s + 1
 // has s pairs) can be split over two slots ("split" variant) so that no slot
-// holds more than s - 1 pairs; K up to 16640 then needs no chunking for any
-// s <= 9.  Longer K is cut into chunks of the exact-INT32 length; each chunk
+// holds more than max(s - 1, ceil(s / 2)) pairs; K up to 16640 then needs no
+// chunking for any s <= 9 (s = 16: up to 16640 as well, eight pairs per slot).  Longer K is cut into chunks of the exact-INT32 length; each chunk
 // writes its INT32 diagonal sums to scratch and a combine pass adds them in
 // INT64 before recombining.  The cuts depend on (s, t, k) only, so tile
 // shapes never change a bit of the result.
@@ -98,11 +98,15 @@ struct Cfg {
     static constexpr int NSLOT = (T - 1) + (SPLIT ? 1 : 0);
     // wave tile WM x WN blocks of 32x32; workgroup WAVES_M x WAVES_N waves.
     // Two 32x32 blocks per wave while the accumulators fit two waves per
-    // SIMD (16 NSLOT VGPRs per block), else one.
+    // SIMD (16 NSLOT VGPRs per block), else one.  Above ten slots (s >= 10)
+    // the accumulators (16 NSLOT), the B digits kept in registers (4 S) and
+    // the streamed A digit need more than half of a SIMD's 512 registers per
+    // lane: four waves, one per SIMD, 64 x 64 tiles.
+    static constexpr bool WIDE = NSLOT > 10;
     static constexpr int WM = 1;
     static constexpr int WN = (NSLOT <= 5) ? 2 : 1;
-    static constexpr int WAVES_M = (WN == 2) ? 4 : 2;
-    static constexpr int WAVES_N = (WN == 2) ? 2 : 4;
+    static constexpr int WAVES_M = WIDE ? 2 : (WN == 2) ? 4 : 2;
+    static constexpr int WAVES_N = WIDE ? 2 : (WN == 2) ? 2 : 4;
     static constexpr int NW = WAVES_M * WAVES_N;
     static constexpr int THREADS = 64 * NW;
     static constexpr int TM = WAVES_M * WM;     // 32-row blocks per tile
@@ -156,7 +160,6 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
                                            int kb1, int chunk, int8_t *lds) {
     using CF = Cfg<S, T, SPLIT>;
     static_assert(!PF || (MODE == 0 && CF::WM * CF::WN == 1), "C prefetch: one block per wave");
-    static_assert(CF::THREADS == 512, "launch bounds assume 8 waves");
     constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
     constexpr int NSLOT = CF::NSLOT;
 
@@ -320,7 +323,9 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
 #pragma unroll
                     for (int g = T - 2; g >= 0; --g) {
                         long long D = acc[i][j][g][r];
-                        if (SPLIT && g == T - 2) D += acc[i][j][T - 1][r];
+                        if constexpr (SPLIT) {
+                            if (g == T - 2) D += acc[i][j][T - 1][r];
+                        }
                         // weight 2^-7(g+2), an exact power of two
                         const double wgt =
                             __longlong_as_double((long long)(1023 - 7 * (g + 2)) << 52);
@@ -339,7 +344,7 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
 }
 
 template <int S, int T, bool SPLIT, int MODE>
-__global__ __launch_bounds__(512) void k_slicegemm(GemmArgs p) {
+__global__ __launch_bounds__((Cfg<S, T, SPLIT>::THREADS)) void k_slicegemm(GemmArgs p) {
     using CF = Cfg<S, T, SPLIT>;
     __shared__ __attribute__((aligned(1024))) int8_t lds[CF::NST * CF::STAGE];
     int tm, tn;
@@ -360,6 +365,7 @@ __global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__res
                                                            int nprob, int total,
                                                            const int *__restrict__ dcounts) {
     using CF = Cfg<S, T, false>;
+    static_assert(CF::THREADS == 512, "launch bounds assume 8 waves");
     if (dcounts) {              // list built on the device
         nprob = dcounts[0];
         total = dcounts[1];
@@ -679,6 +685,8 @@ int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
     if (s == S_ && t == T_) return launch_st<S_, T_>(a, pl, Dout, stream);
     EMU_CASE(1, 2) EMU_CASE(2, 3) EMU_CASE(3, 4) EMU_CASE(4, 5) EMU_CASE(5, 6)
     EMU_CASE(6, 7) EMU_CASE(7, 8) EMU_CASE(8, 9) EMU_CASE(9, 10)
+    EMU_CASE(10, 11) EMU_CASE(11, 12) EMU_CASE(12, 13) EMU_CASE(13, 14) EMU_CASE(14, 15)
+    EMU_CASE(15, 16) EMU_CASE(16, 17)
     EMU_CASE(2, 4) EMU_CASE(3, 6) EMU_CASE(4, 8) EMU_CASE(5, 10)
 #undef EMU_CASE
     set_error("no kernel for s=%d t=%d", s, t);
