@@ -30,6 +30,11 @@ Workload families:
   sub-diagonals of -1).
 * ``int_matrix``: random integers of a given bit width, for inputs that fit a
   slice count exactly.
+* ``parawilk`` / ``parawilk_random``: the paper's three-parameter family
+  ParaWilk_n(d, b, alpha) (parametric-family section) and its randomized form
+  (randomization section, eqns (15)-(16)).
+* ``spd_matrix``: symmetric positive definite matrices for the Cholesky
+  variant.
 """
 from __future__ import annotations
 
@@ -37,7 +42,8 @@ import numpy as np
 
 __all__ = [
     "rng", "uniform", "phi_matrix", "kappa_matrix", "turing", "wilkinson",
-    "dband", "int_matrix", "hpl_uniform", "batched_specs",
+    "dband", "int_matrix", "hpl_uniform", "batched_specs", "parawilk", "parawilk_random",
+    "spd_matrix",
 ]
 
 
@@ -171,3 +177,47 @@ def batched_specs(count: int, seed: int = 0, nmin: int = 64, nmax: int = 1024,
     phi = g.uniform(0.0, phimax, size=count)
     nrhs = g.integers(1, rhsmax + 1, size=count)
     return [(int(n[i]), float(phi[i]), int(nrhs[i])) for i in range(count)]
+
+
+def parawilk(n: int, d: int, b: int, alpha: float) -> np.ndarray:
+    """ParaWilk_n(d, b, alpha) of the paper's parametric-family section.
+
+    Unit diagonal; -1 on the first d sub-diagonals (1 <= i - j <= d); the
+    value alpha in every entry above the diagonal of each column j (1-based)
+    with (j - 1) mod b == 0, j > 1, and of the last column.  The paper defines
+    the placement only through its n = 5, d = 5, b = 2 example (columns 3 and
+    5 carry the above-diagonal values); this is the reading that reproduces
+    it.  d = n - 1, b >= n, alpha = 1 gives the Wilkinson matrix.
+    """
+    A = dband(n, d)
+    cols = [j for j in range(2, n + 1) if (j - 1) % b == 0]
+    if n > 1 and n not in cols:
+        cols.append(n)
+    for j in cols:
+        A[: j - 1, j - 1] = alpha
+    return np.asfortranarray(A)
+
+
+def parawilk_random(n: int, d: int, b: int, alpha: float, seed: int = 0,
+                    substream: int = 0) -> np.ndarray:
+    """Randomized ParaWilk (eqn (16)): 2 u^2 with u ~ U(0, 1) in every entry
+    where ParaWilk is zero, the ParaWilk entries kept (the nonzero-pattern
+    function of eqn (15) selects the positions; the printed formula writes the
+    matrix itself where its pattern is meant).  u is drawn for all n^2
+    positions in column-major order."""
+    P = parawilk(n, d, b, alpha)
+    g = rng(seed, substream)
+    u = _colmajor(g.uniform(0.0, 1.0, size=(n, n)))
+    R = 2.0 * u * u
+    return np.asfortranarray(np.where(P != 0.0, P, R))
+
+
+def spd_matrix(n: int, phi: float = 0.0, seed: int = 0, substream: int = 0) -> np.ndarray:
+    """Symmetric positive definite: A = G G^T / n + I with G a phi-matrix
+    (G G^T formed in float64 by the host BLAS; the input is whatever bits it
+    produces, shared by every consumer), symmetrized exactly."""
+    G = phi_matrix(n, n, phi, seed, substream)
+    A = (G @ G.T) / float(n)
+    A = np.triu(A) + np.triu(A, 1).T
+    A[np.diag_indices(n)] += 1.0
+    return np.asfortranarray(A)
