@@ -156,6 +156,27 @@ int emu_dgemm(int m, int n, int k, double alpha, const double *A, int lda,
               int nslices);
 
 /*
+ * emu_dgemm_noalloc: emu_dgemm for callers that cannot allocate device
+ * memory or synchronize (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, argument numbers and
+ * quick returns as emu_dgemm, and bit-identical results.  It allocates
+ * nothing, creates no HIP objects and never synchronizes: its scratch (digit
+ * planes, exponent codes, chunk partial sums) is a fixed array of
+ * EMU_NOALLOC_SCRATCH_BYTES in the library's own device memory, one per
+ * device, held until the process ends.  A shape whose emu_workspace_bytes
+ * exceeds that size returns EMU_ERR_WORKSPACE (nothing is launched).  Every
+ * call on one device uses the same array, so calls that overlap on one
+ * device (two streams, two threads) race and give wrong results: the caller
+ * orders them.  The array keeps the last call's contents; no call relies on
+ * it starting at zero.  It ignores emu_set_workspace and takes no part in
+ * emu_profile_*.
+ */
+#define EMU_NOALLOC_SCRATCH_BYTES (64u << 20)   /* 64 MiB */
+int emu_dgemm_noalloc(int m, int n, int k, double alpha, const double *A, int lda,
+                      const double *B, int ldb, double beta, double *C, int ldc,
+                      int nslices);
+
+/*
  * emu_dgemm_t: emu_dgemm with an explicit truncation threshold t (the
  * paper's t: products A_i B_j with i + j > t are dropped).  Supported:
  * t = s + 1 for s in 1..16 and t = 2s (all s^2 products) for s in 1..5.

@@ -35,11 +35,12 @@ __all__ = [
     "emu_refine", "refine", "emu_scaled_residual", "scaled_residual",
     "mlp_grad", "mlp_infer", "tile_labels", "dgetrf_adaptive",
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
-    "status",
+    "status", "emu_dgemm_noalloc", "EMU_NOALLOC_SCRATCH_BYTES",
 ]
 
 EMU_MAX_SLICES = 16
 EMU_ERR_WORKSPACE = 1002
+EMU_NOALLOC_SCRATCH_BYTES = 64 << 20
 EMU_ERR_NOT_CONVERGED = 1004
 EMU_ERR_PANEL_WAIT = 1005
 EMU_INFO_ABORTED = -1000
@@ -68,6 +69,7 @@ _SIGNATURES = {
     "emu_last_error": ([], ctypes.c_char_p),
     "emu_status": ([ctypes.POINTER(_I)], _I),
     "emu_dgemm": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
+    "emu_dgemm_noalloc": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
     "emu_dgemm_t": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I, _I], _I),
     "emu_dgetrf": ([_I, _I, _P, _I, _P, _P, _I, _I], _I),
     "emu_dgetrs": ([_I, _I, _P, _I, _P, _P, _I], _I),
@@ -134,6 +136,7 @@ emu_getrf_workspace_bytes = _raw("emu_getrf_workspace_bytes")
 emu_getrs_workspace_bytes = _raw("emu_getrs_workspace_bytes")
 emu_status = _raw("emu_status")
 emu_dgemm = _raw("emu_dgemm")
+emu_dgemm_noalloc = _raw("emu_dgemm_noalloc")
 emu_dgemm_t = _raw("emu_dgemm_t")
 emu_dgetrf = _raw("emu_dgetrf")
 emu_dgetrs = _raw("emu_dgetrs")

@@ -20,6 +20,12 @@ static Device g_devs[MAX_DEVICES];
 // device, zero when the code object loads), so no call allocates it.
 static __device__ int g_status_word;
 
+// Scratch of emu_dgemm_noalloc: a fixed array in the library's device memory
+// (one copy per device, held until the process ends).  Host code never uses
+// this name as an address: the device address of each device's copy is
+// taken once, when the device is first set up (Device::scratch).
+static __device__ __align__(256) char scratch[EMU_NOALLOC_SCRATCH_BYTES];
+
 // Every thread context ever created (for emu_finalize); a context is never
 // deleted, so a thread's pointer to its own stays valid.
 static std::vector<ThreadCtx *> g_ctxs;
@@ -51,6 +57,9 @@ int current(Device **dev, hipStream_t *stream) {
             void *st = nullptr;
             EMU_TRY_HIP(hipGetSymbolAddress(&st, HIP_SYMBOL(g_status_word)));
             d.status = static_cast<int *>(st);
+            void *sp = nullptr;
+            EMU_TRY_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+            d.scratch = static_cast<char *>(sp);
             d.id = id;
         }
     }
@@ -231,10 +240,11 @@ struct ProfScope {
 };
 
 // Emulated GEMM on reserved scratch at `ws` (m, n, k > 0, alpha != 0).
+// `prof` = false leaves the profiling events out (no event objects created).
 static int gemm_core(Device *dev, char *ws, hipStream_t stream, const GemmScratch &g,
                      int m, int n, int k, double alpha, const double *A, long long lda,
                      const double *B, long long ldb, double beta, double *C,
-                     long long ldc, int s, int t, int64_t *Dout) {
+                     long long ldc, int s, int t, int64_t *Dout, bool prof = true) {
     int *codeA = reinterpret_cast<int *>(ws + g.off_codeA);
     int *codeB = reinterpret_cast<int *>(ws + g.off_codeB);
     int8_t *pa = reinterpret_cast<int8_t *>(ws + g.off_pa);
@@ -242,6 +252,12 @@ static int gemm_core(Device *dev, char *ws, hipStream_t stream, const GemmScratc
     int32_t *chunk = gemm_chunk_bytes(m, n, k, s, t, Dout != nullptr)
                          ? reinterpret_cast<int32_t *>(ws + g.off_chunk)
                          : nullptr;
+    if (!prof) {
+        EMU_TRY(launch_slice(A, lda, 1, g.ga, s, codeA, pa, dev->status, stream));
+        EMU_TRY(launch_slice(B, ldb, 0, g.gb, s, codeB, pb, dev->status, stream));
+        return launch_slicegemm(pa, g.ga, pb, g.gb, codeA, codeB, m, n, k, s, t, alpha, beta,
+                                C, ldc, Dout, chunk, stream);
+    }
     ProfScope ps(EMU_PROF_SLICE, stream);
     EMU_TRY(launch_slice(A, lda, 1, g.ga, s, codeA, pa, dev->status, stream));
     EMU_TRY(launch_slice(B, ldb, 0, g.gb, s, codeB, pb, dev->status, stream));
@@ -514,6 +530,33 @@ int emu_dgemm(int m, int n, int k, double alpha, const double *A, int lda,
               int nslices) {
     return dgemm_impl(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices,
                       nslices + 1, nullptr);
+}
+
+int emu_dgemm_noalloc(int m, int n, int k, double alpha, const double *A, int lda,
+                      const double *B, int ldb, double beta, double *C, int ldc,
+                      int nslices) {
+    const int s = nslices, t = nslices + 1;
+    int bad = check_gemm_args(m, n, k, A, lda, B, ldb, C, ldc, s, t, alpha);
+    if (bad) {
+        set_error("emu_dgemm_noalloc: argument %d invalid", -bad);
+        return bad;
+    }
+    if (m == 0 || n == 0) return 0;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    if (k == 0 || alpha == 0.0) return scale_c(C, ldc, m, n, beta, st);
+    const GemmScratch g = gemm_scratch(m, n, k, s, t);
+    if (g.total > (size_t)EMU_NOALLOC_SCRATCH_BYTES) {
+        set_error("emu_dgemm_noalloc: this shape needs %zu bytes of scratch, more than the "
+                  "fixed %zu", g.total, (size_t)EMU_NOALLOC_SCRATCH_BYTES);
+        return EMU_ERR_WORKSPACE;
+    }
+    // nothing in the scratch has to start at zero: the scans and the slicing
+    // write every exponent code and digit block the GEMM reads, and chunk
+    // partials are written before they are combined
+    return gemm_core(dev, dev->scratch, st, g, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s,
+                     t, nullptr, false);
 }
 
 int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,

@@ -32,6 +32,8 @@ struct Device {
     int id = -1;
     int *status = nullptr;        // device word: OR of EMU_STATUS_* bits (a
                                   // file-scope __device__ variable of the library)
+    char *scratch = nullptr;      // device address of this device's copy of the
+                                  // fixed scratch array of emu_dgemm_noalloc
 };
 
 // State of one thread on one device.  Scratch belongs to a thread, so two

@@ -51,6 +51,9 @@ def _p(v=0x1000):
 def test_dgemm_argument_errors(args, code):
     assert emu.emu_dgemm(*args) == code
     assert "argument" in emu.emu_last_error()
+    # the entry point that allocates nothing checks its arguments the same way
+    assert emu.emu_dgemm_noalloc(*args) == code
+    assert "argument" in emu.emu_last_error()
 
 
 def test_dgemm_unsupported_slice_count():
