@@ -218,20 +218,22 @@ def _argmax_abs_first(v: np.ndarray) -> int:
     return int(np.argmax(a))           # argmax returns the first maximum
 
 
-def getf2(P: np.ndarray, ipiv: np.ndarray, row0: int) -> int:
+def getf2(P: np.ndarray, ipiv: np.ndarray, row0: int, pivot: bool = True) -> int:
     """Unblocked right-looking LU of the panel P (rows x jb) in place.
 
-    Column by column: pick the pivot (first largest magnitude), swap it into
-    place across the panel, scale the column below by the reciprocal of the
-    pivot (by division when |pivot| < DBL_MIN), then subtract the rank-1
-    product from the rest of the panel, one rounded multiply and one rounded
-    subtract per entry.  ipiv[row0 + c] receives the 1-based global row.
-    Returns the first zero-pivot position (1-based, global) or 0.
+    Column by column: pick the pivot (first largest magnitude; the diagonal
+    entry itself when pivot is False, the performance section's LU without
+    pivoting), swap it into place across the panel, scale the column below
+    by the reciprocal of the pivot (by division when |pivot| < DBL_MIN), then
+    subtract the rank-1 product from the rest of the panel, one rounded
+    multiply and one rounded subtract per entry.  ipiv[row0 + c] receives
+    the 1-based global row.  Returns the first zero-pivot position (1-based,
+    global) or 0.
     """
     rows, jb = P.shape
     info = 0
     for c in range(min(rows, jb)):
-        p = c + _argmax_abs_first(P[c:, c])
+        p = c + _argmax_abs_first(P[c:, c]) if pivot else c
         ipiv[row0 + c] = row0 + p + 1
         if P[p, c] != 0.0:
             if p != c:
@@ -265,8 +267,11 @@ def laswp(A: np.ndarray, ipiv: np.ndarray, k1: int, k2: int) -> None:
             A[[c, p], :] = A[[p, c], :]
 
 
-def getrf(A, nb: int = 64, s: int | None = None, t: int | None = None):
-    """Blocked right-looking LU with partial pivoting, PA = LU.
+def getrf(A, nb: int = 64, s: int | None = None, t: int | None = None,
+          pivot: bool = True):
+    """Blocked right-looking LU with partial pivoting, PA = LU (pivot=False:
+    no interchanges, A = LU, ipiv the identity; the performance section's
+    simplified LU).
 
     s=None uses an FP64 matmul for the trailing update (native reference);
     otherwise the update is dgemm_emu(L21, U12, s, alpha=-1, beta=1, C=A22).
@@ -280,7 +285,7 @@ def getrf(A, nb: int = 64, s: int | None = None, t: int | None = None):
     for j0 in range(0, mn, nb):
         jb = min(nb, mn - j0)
         j1 = j0 + jb
-        pinfo = getf2(LU[j0:, j0:j1], ipiv, j0)
+        pinfo = getf2(LU[j0:, j0:j1], ipiv, j0, pivot)
         if info == 0 and pinfo:
             info = pinfo
         # row interchanges of this panel, applied left and right of it

@@ -318,6 +318,37 @@ def test_singular_matrix_reports_first_zero_pivot():
         assert np.array_equal(ipiv[:17], ref[1][:17] + 1)
 
 
+def test_lu_without_pivoting_closed_form_and_lapack_on_dominant_columns():
+    # 2 x 2 with a tiny leading entry: no interchange, L21 = 1/eps, and
+    # U22 = 1 - 1/eps exactly as elimination without pivoting defines it
+    A = np.array([[2.0 ** -60, 1.0], [1.0, 1.0]], order="F")
+    LU, ipiv, info = O.getrf(A, nb=1, s=None, pivot=False)
+    assert info == 0 and list(ipiv) == [1, 2]
+    assert LU[1, 0] == 2.0 ** 60 and LU[1, 1] == 1.0 - 2.0 ** 60 and LU[0, 1] == 1.0
+    LUp, ipivp, _ = O.getrf(A, nb=1, s=None)
+    assert list(ipivp) == [2, 2]                         # partial pivoting swaps
+    # a zero leading entry: reported as the first zero pivot, no interchange
+    Z = np.array([[0.0, 1.0], [1.0, 1.0]], order="F")
+    _, ipz, infz = O.getrf(Z, nb=2, s=None, pivot=False)
+    assert infz == 1 and list(ipz) == [1, 2]
+    # columns whose diagonal dominates: partial pivoting (LAPACK) makes no
+    # interchange, so its factors are those of elimination without pivoting
+    n = 60
+    G = np.array(matgen.uniform(n, n, seed=31), order="F")
+    G[np.arange(n), np.arange(n)] = 2.0 * n
+    for nb, s in ((8, None), (16, 9), (7, None)):
+        LU, ipiv, info = O.getrf(G, nb=nb, s=s, pivot=False)
+        ref_lu, ref_piv = scipy.linalg.lu_factor(G, check_finite=False)
+        assert info == 0 and np.array_equal(ipiv, np.arange(1, n + 1))
+        assert np.array_equal(ref_piv, np.arange(n))
+        assert np.abs(LU - ref_lu).max() <= 1e-13 * np.abs(ref_lu).max()
+    # and on a general matrix the two orders differ while both reconstruct A
+    M = np.array(matgen.uniform(50, 50, seed=32), order="F")
+    LUn, _, _ = O.getrf(M, nb=8, s=None, pivot=False)
+    L = np.tril(LUn, -1) + np.eye(50)
+    assert np.abs(L @ np.triu(LUn) - M).max() <= 1e-9 * np.abs(M).max() * np.abs(LUn).max()
+
+
 def test_scaled_residual_matches_eqn9():
     A = matgen.uniform(30, 30, seed=1)
     b = matgen.uniform(30, 1, seed=2)
