@@ -17,6 +17,9 @@ Parity status of each function (what pins it, in tests/test_oracle_pins.py):
   getf2/getrf/trsm/laswp/getrs  - Turing/Wilkinson/d-band closed forms
                                   (eqns (10)-(12)), PA = LU, LAPACK-style
                                   info on singular input
+  potf2/potrf                   - closed 2 x 2 form, exact integer factors
+                                  recovered at one slice, LAPACK's Cholesky,
+                                  first non-positive pivot
   backward_error/scaled_residual - eqn (9) identity, exact rational residual
   gesv_ir                       - the delivered solution's double-double
                                   backward error meets the tolerance; forced
@@ -35,5 +38,6 @@ from .emu import (  # noqa: F401
     DIGIT_BITS, EPS, line_exponents, slice_digits, slice_products, recombine,
     dgemm_emu, dgemm_dd, rel_err_fro, getf2, trsm_unit_lower, laswp, getrf,
     getrs, residual_dd, backward_error, scaled_residual, pa_minus_lu, gesv_ir,
+    potf2, potrf,
 )
 from ._clib import build_oracle  # noqa: F401

@@ -307,6 +307,65 @@ def getrf(A, nb: int = 64, s: int | None = None, t: int | None = None,
     return LU, ipiv, info
 
 
+# --------------------------------------------------------------------------
+# Cholesky (the symmetric case the paper names as a further application of
+# the emulated update, solver section and conclusions)
+# --------------------------------------------------------------------------
+
+def potf2(P: np.ndarray, row0: int) -> int:
+    """Unblocked right-looking Cholesky of the tall panel P (rows x jb, its
+    top jb x jb block on the diagonal) in place, lower triangle: column by
+    column, l_cc = sqrt(a_cc) (a_cc not positive or NaN: stop and return the
+    1-based global column), the column below is multiplied by 1 / l_cc, then
+    every a_ij with c < j <= i inside the panel loses l_ic l_jc (one rounded
+    multiply, one rounded subtract).  Entries above the diagonal are not
+    touched.  Returns 0 or the failing column."""
+    rows, jb = P.shape
+    for c in range(min(rows, jb)):
+        a = P[c, c]
+        if not a > 0.0:
+            return row0 + c + 1
+        l = np.sqrt(a)
+        P[c, c] = l
+        r = 1.0 / l
+        P[c + 1:, c] *= r
+        for j in range(c + 1, jb):
+            P[j:, j] -= P[j:, c] * P[j, c]
+    return 0
+
+
+def potrf(A, nb: int = 64, s: int | None = None):
+    """Blocked right-looking Cholesky A = L L^T of a symmetric matrix, lower
+    triangle (the strictly upper part is neither read nor written).
+
+    Per block column: potf2 on the panel A[j0:, j0:j1] (FP64), then the
+    trailing update A22 <- A22 - L21 L21^T of the lower triangle, with the
+    emulated GEMM (s slices, threshold s + 1; its product of L21 with L21^T
+    is exactly symmetric) or an FP64 matmul (s=None).  Returns (L, info):
+    info = 0, or the 1-based column whose pivot was not positive, where the
+    factorization stops (columns before it are complete, the rest of the
+    array is left as it was at that point).
+    """
+    L = np.array(A, dtype=np.float64, order="F", copy=True)
+    n = L.shape[0]
+    assert L.shape == (n, n)
+    for j0 in range(0, n, nb):
+        j1 = min(n, j0 + nb)
+        info = potf2(L[j0:, j0:j1], j0)
+        if info:
+            return L, info
+        if j1 < n:
+            L21 = L[j1:, j0:j1]
+            if s is None:
+                upd = L[j1:, j1:] - L21 @ L21.T
+            else:
+                upd = dgemm_emu(L21, np.asfortranarray(L21.T), s, alpha=-1.0, beta=1.0,
+                                C=L[j1:, j1:])
+            low = np.tril(np.ones((n - j1, n - j1), dtype=bool))
+            L[j1:, j1:] = np.where(low, upd, L[j1:, j1:])
+    return L, 0
+
+
 def getrs(LU, ipiv, B) -> np.ndarray:
     """Solve A X = B from getrf's factors: interchanges, then forward
     substitution with unit L (column order), then back substitution with U

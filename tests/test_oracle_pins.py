@@ -386,3 +386,54 @@ def test_refinement_fallback_on_forced_failure_and_give_up():
     # a failure at the largest slice count gives up
     X, inf = O.gesv_ir(A, b, nb=32, s=8, tol=1e-15, force_fail=2)
     assert not inf["converged"] and inf["s_final"] == 9
+
+
+# ----------------------------------------------------------------- Cholesky
+
+def test_cholesky_closed_forms_and_first_nonpositive_pivot():
+    L, info = O.potrf(np.array([[4.0, 99.0], [2.0, 5.0]], order="F"), nb=1, s=1)
+    assert info == 0
+    assert L[0, 0] == 2.0 and L[1, 0] == 1.0 and L[1, 1] == 2.0
+    assert L[0, 1] == 99.0                     # the upper part is not touched
+    for bad, col in ((-1.0, 6), (0.0, 6), (np.nan, 4)):
+        A = np.eye(9, order="F")
+        A[col - 1, col - 1] = bad
+        for nb in (1, 4, 9):
+            L, info = O.potrf(A, nb=nb, s=3)
+            assert info == col
+            assert np.array_equal(L[:, :col - 1], np.eye(9)[:, :col - 1])
+
+
+@pytest.mark.parametrize("s", [1, 2, 5, None])
+def test_cholesky_recovers_integer_factor_exactly(s):
+    # A = B B^T with B unit lower triangular, |b_ij| <= 127: every pivot is
+    # 1 and every Schur complement an exact integer, and one 7-bit digit
+    # holds each entry of L21, so even one slice reproduces B exactly
+    n = 40
+    g = np.random.default_rng(5)
+    B = np.tril(g.integers(-127, 128, size=(n, n)).astype(np.float64), -1) + np.eye(n)
+    A = np.asfortranarray(B @ B.T)
+    assert np.abs(A).max() < 2.0 ** 52
+    for nb in (3, 8, 16):
+        L, info = O.potrf(A, nb=nb, s=s)
+        assert info == 0
+        assert np.array_equal(np.tril(L), B)
+        assert np.array_equal(np.triu(L, 1), np.triu(A, 1))
+
+
+def test_cholesky_against_lapack_and_symmetric_emulated_product():
+    n = 200
+    A = matgen.spd_matrix(n, phi=1.0, seed=8)
+    ref = scipy.linalg.cholesky(A, lower=True, check_finite=False)
+    for nb, s in ((32, None), (48, 9), (64, 7)):
+        L, info = O.potrf(A, nb=nb, s=s)
+        assert info == 0
+        err = np.abs(np.tril(L) - ref).max() / np.abs(ref).max()
+        assert err < (1e-13 if s in (None, 9) else 1e-10), (nb, s, err)
+    # the trailing update's emulated L21 L21^T is exactly symmetric: pair
+    # (i, j) of entry (p, q) is pair (j, i) of entry (q, p), and the scale is
+    # 2^(e_p + e_q) either way
+    X = np.asfortranarray(matgen.phi_matrix(70, 33, 3.0, seed=9))
+    for s in (3, 9):
+        P = O.dgemm_emu(X, np.asfortranarray(X.T), s)
+        assert np.array_equal(P, P.T)
