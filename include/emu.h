@@ -79,6 +79,8 @@ extern "C" {
  * for their factorization return EMU_ERR_PANEL_WAIT instead. */
 #define EMU_INFO_ABORTED       (-1000)
 
+#define EMU_MAX_NB             2048  /* largest block size of emu_dgetrf and
+                                        emu_dgesv_ir */
 #define EMU_MAX_SLICES         16    /* slice counts of the plain GEMM and LU:
                                         1..16 (grouped forms: 1..9) */
 
@@ -188,7 +190,9 @@ int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
 
 /*
  * emu_dgetrf: PA = LU of the m x n matrix A (lda >= max(1,m)) in place,
- * right-looking blocked with block size nb (nb <= 0 selects 64), partial
+ * right-looking blocked with block size nb (nb <= 0 selects 64, at most
+ * EMU_MAX_NB; interchanges are applied to the other columns in chunks of
+ * 1024, in order), partial
  * pivoting (paper: solvers section, eqns (5)-(8)).  Per block column:
  * FP64 panel factorization (first row of largest magnitude is the pivot;
  * the column below is scaled by the reciprocal of the pivot, or divided
@@ -208,6 +212,28 @@ int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info,
                int nb, int nslices);
 
 /*
+ * emu_dpotrf: Cholesky A = L L^T of the symmetric positive definite n x n
+ * matrix A (lda >= max(1,n)), lower triangle, in place; the strictly upper
+ * part is neither read nor written (the symmetric case the paper names
+ * beside LU, solvers section and conclusions).  Right-looking blocked with
+ * block size nb (nb <= 0 selects 64, at most EMU_MAX_NB).  Per block column:
+ * FP64 panel (l_jj = sqrt(a_jj), the column below multiplied by 1 / l_jj,
+ * each a_ij, i >= j, losing l_ik l_jk for k = 0..j-1 in order), then the
+ * update A22 <- A22 - L21 L21^T of the lower triangle as an emulated GEMM
+ * with nslices slices (1..EMU_MAX_SLICES, t = s + 1) whose two operands are
+ * the same digit planes of L21 (sliced once; the product is exactly
+ * symmetric).  With emu_set_param("lu_update", 1) the update is rocBLAS
+ * dsyrk instead.  *info (device int32) receives 0, or the first column j
+ * (1-based) whose pivot a_jj was not positive or was NaN; then columns
+ * 1..j-1 of L are complete and the rest of the lower triangle is
+ * unspecified (the call does not wait to find out).
+ * Argument numbers: n=1 A=2 lda=3 info=4 nb=5 nslices=6.
+ */
+int emu_dpotrf(int n, double *A, int lda, int *info, int nb, int nslices);
+/* Scratch bytes emu_dpotrf needs (0 for invalid arguments). */
+size_t emu_potrf_workspace_bytes(int n, int nb, int nslices);
+
+/*
  * emu_dgetrs: solve A X = B (no transpose) with the factors of emu_dgetrf:
  * row interchanges, forward substitution with unit L, back substitution
  * with U, all FP64 (paper: eqn (5)).  LU n x n (lda >= max(1,n)), ipiv
@@ -222,12 +248,26 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
  *   "ir_force_fail" (value >= 0): the next `value` convergence checks of
  *   emu_dgesv_ir on this thread count as failed, which exercises the
  *   fallback to more slices (a test hook; the checks still run).
+ *   "lu_pivot" (0 or 1, default 1): 0 makes emu_dgetrf (and the LU inside
+ *   emu_dgesv_ir) factor without interchanges, A = LU: the pivot of column
+ *   c is the entry in row c, ipiv receives the identity, and *info still
+ *   reports the first exactly zero pivot (the performance section of the
+ *   paper times this simplified LU).
+ *   "lu_update" (0 or 1, default 0): 1 makes the same factorizations (and
+ *   emu_dpotrf) do their Schur-complement update in native FP64 (rocBLAS
+ *   dgemm, dsyrk for the Cholesky) instead of the emulated GEMM, for
+ *   comparisons at an equal block size; panel, interchanges and triangular
+ *   solves are unchanged.
  *   "lu_lookahead" (0 or 1, default 1): emu_dgetrf (and the LU inside
  *   emu_dgesv_ir, and emu_dgetrf_adaptive) updates the columns right of
  *   the next panel on a library-owned side stream of the device while that
  *   panel is factored;
  *   the caller's stream waits for it, so the call stays ordered on the
  *   caller's stream.  The factors are identical either way.
+ *   "gemm_map" (0 or 1, default 1): order in which the workgroups of an
+ *   emulated GEMM visit the output tiles: 1 lets all eight XCDs work on one
+ *   block of tiles at a time (used when both tile counts are multiples of
+ *   16), 0 gives each XCD its own contiguous range.  Results are identical.
  *   "leaf_cooperative" (0 or 1, default 0): panel leaves taller than 2048
  *   rows (several workgroups that wait for each other) are launched with
  *   hipLaunchCooperativeKernel instead of a plain launch.  The factors are

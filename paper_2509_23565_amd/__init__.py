@@ -20,7 +20,7 @@ import ctypes
 import os
 
 __all__ = [
-    "EmuError", "lib", "library_path", "EMU_MAX_SLICES",
+    "EmuError", "lib", "library_path", "EMU_MAX_SLICES", "EMU_MAX_NB",
     "emu_version", "emu_init", "emu_finalize", "emu_set_stream", "emu_last_error",
     "emu_set_workspace", "emu_workspace_bytes", "emu_getrf_workspace_bytes",
     "emu_getrs_workspace_bytes", "set_workspace", "EMU_INFO_ABORTED", "EMU_ERR_PANEL_WAIT",
@@ -36,9 +36,11 @@ __all__ = [
     "mlp_grad", "mlp_infer", "tile_labels", "dgetrf_adaptive",
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status", "emu_dgemm_noalloc", "EMU_NOALLOC_SCRATCH_BYTES",
+    "emu_dpotrf", "emu_potrf_workspace_bytes", "dpotrf",
 ]
 
 EMU_MAX_SLICES = 16
+EMU_MAX_NB = 2048
 EMU_ERR_WORKSPACE = 1002
 EMU_NOALLOC_SCRATCH_BYTES = 64 << 20
 EMU_ERR_NOT_CONVERGED = 1004
@@ -70,6 +72,8 @@ _SIGNATURES = {
     "emu_status": ([ctypes.POINTER(_I)], _I),
     "emu_dgemm": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
     "emu_dgemm_noalloc": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
+    "emu_dpotrf": ([_I, _P, _I, _P, _I, _I], _I),
+    "emu_potrf_workspace_bytes": ([_I, _I, _I], ctypes.c_size_t),
     "emu_dgemm_t": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I, _I], _I),
     "emu_dgetrf": ([_I, _I, _P, _I, _P, _P, _I, _I], _I),
     "emu_dgetrs": ([_I, _I, _P, _I, _P, _P, _I], _I),
@@ -137,6 +141,8 @@ emu_getrs_workspace_bytes = _raw("emu_getrs_workspace_bytes")
 emu_status = _raw("emu_status")
 emu_dgemm = _raw("emu_dgemm")
 emu_dgemm_noalloc = _raw("emu_dgemm_noalloc")
+emu_dpotrf = _raw("emu_dpotrf")
+emu_potrf_workspace_bytes = _raw("emu_potrf_workspace_bytes")
 emu_dgemm_t = _raw("emu_dgemm_t")
 emu_dgetrf = _raw("emu_dgetrf")
 emu_dgetrs = _raw("emu_dgetrs")
@@ -254,6 +260,20 @@ def dgetrf(A, nb=64, nslices=7):
     _check(emu_dgetrf(m, n, pa, lda, ipiv.data_ptr(), info.data_ptr(), int(nb),
                       int(nslices)), "emu_dgetrf")
     return ipiv[:min(m, n)], info
+
+
+def dpotrf(A, nb=64, nslices=7):
+    """In-place lower Cholesky of A (upper part untouched); returns info as an
+    int32 device tensor."""
+    torch = _torch()
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise EmuError("dpotrf: A must be square")
+    pa, lda = _mat(A, "A")
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _bind_stream()
+    _check(emu_dpotrf(n, pa, lda, info.data_ptr(), int(nb), int(nslices)), "emu_dpotrf")
+    return info
 
 
 def dgetrs(LU, ipiv, B):

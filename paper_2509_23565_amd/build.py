@@ -19,7 +19,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libemu.so")
 ARCH = "gfx950"
 SOURCES = ["api.hip", "slice.hip", "slicegemm.hip", "lu.hip", "panel.hip", "refine.hip",
-           "batched.hip", "learned.hip"]
+           "batched.hip", "learned.hip", "native.hip"]
+# rocBLAS: only the native FP64 trailing update of the LU comparison runs
+LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
 
 
 def _hipcc() -> str:
@@ -55,7 +57,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -274,6 +274,11 @@ static thread_local int g_ir_force_fail = 0;
 // largest slice count refinement falls back to from a start of at most nine
 constexpr int IR_MAX_SLICES = 9;
 static thread_local int g_lu_lookahead = 1;
+static thread_local int g_lu_pivot = 1;       // 0: LU without interchanges
+static thread_local int g_lu_native = 0;      // 1: rocBLAS FP64 trailing update
+// interchanges one laswp call applies at most (the panel's are applied in
+// chunks of this many, in order)
+constexpr int LASWP_CHUNK = 1024;
 
 // Scratch of one blocked LU: the largest trailing update's GEMM scratch
 // (the first update; later ones are smaller), then the panel's buffers.
@@ -314,6 +319,7 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
     const int mn = m < n ? m : n;
     const int t = s + 1;
     const bool la = g_lu_lookahead != 0 && mn > nb;
+    const bool pivot = g_lu_pivot != 0, native = g_lu_native != 0;
     ThreadCtx *tc = thread_ctx(dev);
     if (la) EMU_TRY(side_stream(tc));
     // TRSM + emulated GEMM of columns [c0, c1) by the panel at (j0, jb)
@@ -323,6 +329,9 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
         const double *Ajj = A + j0 + (long long)j0 * ld;
         double *U12 = A + j0 + (long long)c0 * ld;
         EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, c1 - c0, sx));
+        if (j1 < m && native)
+            return native_update(m - j1, c1 - c0, jb, A + j1 + (long long)j0 * ld, ld, U12, ld,
+                                 A + j1 + (long long)c0 * ld, ld, sx);
         if (j1 < m) {
             GemmScratch gs = gemm_scratch(m - j1, c1 - c0, jb, s, t);
             EMU_TRY(gemm_core(dev, ws, sx, gs, m - j1, c1 - c0, jb, -1.0,
@@ -334,13 +343,16 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
     auto panel = [&](int j0) -> int {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         return launch_panel(A + j0 + (long long)j0 * ld, ld, m - j0, jb, ipiv + j0, j0, info,
-                            pws, dev->status, st);
+                            pws, dev->status, st, pivot);
     };
     if (mn > 0) EMU_TRY(panel(0));
     for (int j0 = 0; j0 < mn; j0 += nb) {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
-        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
+        if (pivot)
+            for (int k1 = j0; k1 < j1; k1 += LASWP_CHUNK)
+                EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, k1,
+                                     k1 + LASWP_CHUNK < j1 ? k1 + LASWP_CHUNK : j1, 0, plan, st));
         const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
         if (!la || jn == 0) {
             EMU_TRY(update(j0, jb, j1, n, st));
@@ -357,6 +369,45 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
         }
         EMU_TRY(panel(j1));
         if (j2 < n) EMU_TRY_HIP(hipStreamWaitEvent(st, tc->ev_done, 0));
+    }
+    return 0;
+}
+
+// Scratch of the Cholesky update: exponent codes and digit planes of L21
+// (the largest, first one); B of the product is L21 itself.
+static size_t potrf_scratch_bytes(int n, int nb, int s) {
+    const int jb = nb < n ? nb : n;
+    if (n - jb <= 0) return 256;
+    const Planes g = plane_geom(n - jb, jb);
+    return align256((size_t)g.LB * 32 * sizeof(int)) + align256((size_t)s * g.plane_bytes);
+}
+
+// Blocked right-looking lower Cholesky on reserved scratch `ws`: per block
+// column the FP64 panel (launch_chol_panel), then A22 <- A22 - L21 L21^T,
+// lower triangle, as one emulated GEMM whose two operands are the same
+// digit planes of L21 (sliced once, by rows: row q of L21 is column q of
+// L21^T, with the same exponent).
+static int potrf_impl(Device *dev, char *ws, hipStream_t st, int n, double *A, long long ld,
+                      int *info, int nb, int s) {
+    EMU_TRY(launch_fill_int(info, 0, 1, st));
+    for (int j0 = 0; j0 < n; j0 += nb) {
+        const int jb = nb < n - j0 ? nb : n - j0;
+        const int j1 = j0 + jb;
+        EMU_TRY(launch_chol_panel(A + j0 + (long long)j0 * ld, ld, n - j0, jb, j0, info, st));
+        if (j1 >= n) break;
+        const int m = n - j1;
+        const double *L21 = A + j1 + (long long)j0 * ld;
+        double *A22 = A + j1 + (long long)j1 * ld;
+        if (g_lu_native) {
+            EMU_TRY(native_syrk_update(m, jb, L21, ld, A22, ld, st));
+            continue;
+        }
+        const Planes g = plane_geom(m, jb);
+        int *code = reinterpret_cast<int *>(ws);
+        int8_t *planes = reinterpret_cast<int8_t *>(ws + align256((size_t)g.LB * 32 * sizeof(int)));
+        EMU_TRY(launch_slice(L21, ld, 1, g, s, code, planes, dev->status, st));
+        EMU_TRY(launch_slicegemm(planes, g, planes, g, code, code, m, m, jb, s, s + 1, -1.0, 1.0,
+                                 A22, ld, nullptr, nullptr, st, true));
     }
     return 0;
 }
@@ -413,7 +464,7 @@ size_t emu_workspace_bytes(int m, int n, int k, int nslices) {
 }
 
 size_t emu_getrf_workspace_bytes(int m, int n, int nb, int nslices) {
-    if (m < 0 || n < 0 || nb > 1024 || nslices < 1 || nslices > EMU_MAX_SLICES) return 0;
+    if (m < 0 || n < 0 || nb > EMU_MAX_NB || nslices < 1 || nslices > EMU_MAX_SLICES) return 0;
     return getrf_scratch_bytes(m, n, nb <= 0 ? 64 : nb, nslices);
 }
 
@@ -613,12 +664,30 @@ int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info, int nb,
     int mn = m < n ? m : n;
     if (mn > 0 && !ipiv) return -5;
     if (!info) return -6;
-    if (nb > 1024) return -7;
+    if (nb > EMU_MAX_NB) return -7;
     if (nslices < 1 || nslices > EMU_MAX_SLICES) return -8;
     if (nb <= 0) nb = 64;
     Call c;
     EMU_TRY(c.begin(getrf_scratch_bytes(m, n, nb, nslices)));
     return getrf_impl(c.dev, c.ws, c.st, m, n, A, lda, ipiv, info, nb, nslices);
+}
+
+int emu_dpotrf(int n, double *A, int lda, int *info, int nb, int nslices) {
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < imax1(n)) return -3;
+    if (!info) return -4;
+    if (nb > EMU_MAX_NB) return -5;
+    if (nslices < 1 || nslices > EMU_MAX_SLICES) return -6;
+    if (nb <= 0) nb = 64;
+    Call c;
+    EMU_TRY(c.begin(potrf_scratch_bytes(n, nb, nslices)));
+    return potrf_impl(c.dev, c.ws, c.st, n, A, lda, info, nb, nslices);
+}
+
+size_t emu_potrf_workspace_bytes(int n, int nb, int nslices) {
+    if (n < 0 || nb > EMU_MAX_NB || nslices < 1 || nslices > EMU_MAX_SLICES) return 0;
+    return potrf_scratch_bytes(n, nb <= 0 ? 64 : nb, nslices);
 }
 
 int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv, double *B,
@@ -652,6 +721,21 @@ int emu_set_param(const char *key, long long value) {
         set_leaf_cooperative((int)value);
         return 0;
     }
+    if (std::strcmp(key, "gemm_map") == 0) {
+        if (value != 0 && value != 1) return -2;
+        set_gemm_map((int)value);
+        return 0;
+    }
+    if (std::strcmp(key, "lu_pivot") == 0) {
+        if (value != 0 && value != 1) return -2;
+        g_lu_pivot = (int)value;
+        return 0;
+    }
+    if (std::strcmp(key, "lu_update") == 0) {
+        if (value != 0 && value != 1) return -2;
+        g_lu_native = (int)value;
+        return 0;
+    }
     if (std::strcmp(key, "lu_lookahead") == 0) {
         if (value != 0 && value != 1) return -2;
         g_lu_lookahead = (int)value;
@@ -672,7 +756,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     if (ldb < imax1(n)) return -6;
     if (n > 0 && nrhs > 0 && !X) return -7;
     if (ldx < imax1(n)) return -8;
-    if (nb > 1024) return -9;
+    if (nb > EMU_MAX_NB) return -9;
     if (nslices < 1 || nslices > EMU_MAX_SLICES) return -10;
     if (!(tol > 0.0)) return -11;
     if (maxiter < 0) return -12;

@@ -197,18 +197,27 @@ struct GemmArgs {
     double *C;
     long long ldc;
     int32_t *part;        // chunk partials [chunk][g-2][n][m]
+    int map;              // tile order of the plain launch (tile_of)
+    int lower;            // store only entries with row >= column (symmetric update)
 };
+
+// Tile order of the plain slice-GEMM launches on the calling thread
+// (emu_set_param "gemm_map"; 1 by default); bits are unaffected.
+void set_gemm_map(int map);
+int gemm_map();
 
 // Slice-product GEMM with fused recombination, or the raw diagonal sums
 // D_g (Dout != null, int64 [t-1][n][m]).  ws_part: INT32 scratch for K-chunk
 // partial sums of gemm_chunk_bytes(..., raw_sums = Dout != null) bytes; may
 // be null when that is 0.
 size_t gemm_chunk_bytes(int m, int n, int k, int s, int t, bool raw_sums);
+// lower = true (the Cholesky update A22 - L21 L21^T, Bp = Ap): entries above
+// the diagonal are neither computed nor stored; K must not need chunks.
 int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
                      const Planes &gb, const int *codeA, const int *codeB,
                      int m, int n, int k, int s, int t, double alpha,
                      double beta, double *C, long long ldc, int64_t *Dout,
-                     int32_t *ws_part, hipStream_t stream);
+                     int32_t *ws_part, hipStream_t stream, bool lower = false);
 bool gemm_supported(int s, int t);
 // Many problems of one (s, t = s + 1) in one persistent launch: probs[q]
 // (device) holds problem q with tiles_m/tiles_n set by gemm_tile_counts;
@@ -234,12 +243,27 @@ int launch_slicegemm_grouped_dev(const GemmArgs *probs, const int *tile_prefix,
 int launch_fill_int(int *p, int v, int count, hipStream_t stream);
 // Panel factorization (recursive, see panel.hip) of the rows x jb block at
 // A (global row/column row0); ws: panel_scratch_bytes(rows) bytes; status:
-// the device status word (EMU_STATUS_PANEL_WAIT on an aborted tall leaf).
+// the device status word (EMU_STATUS_PANEL_WAIT on an aborted tall leaf);
+// pivot = false: no interchanges (ipiv receives the identity).
 size_t panel_scratch_bytes(int rows);
 // Launch multi-workgroup panel leaves cooperatively (process-wide switch).
 void set_leaf_cooperative(int on);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
-                 int row0, int *info, char *ws, int *status, hipStream_t stream);
+                 int row0, int *info, char *ws, int *status, hipStream_t stream,
+                 bool pivot = true);
+// Lower Cholesky of the rows x jb panel at A (its top jb x jb block on the
+// diagonal; global column col0), FP64; *info receives the first column
+// (1-based, global) whose pivot is not positive, if it is still 0.
+int launch_chol_panel(double *A, long long lda, int rows, int jb, int col0, int *info,
+                      hipStream_t stream);
+// C (m x n) <- C - A B in native FP64 (rocBLAS dgemm) on `stream`: the
+// trailing update of the LU when emu_set_param("lu_update", 1) asks for the
+// native comparison.
+int native_update(int m, int n, int k, const double *A, long long lda, const double *B,
+                  long long ldb, double *C, long long ldc, hipStream_t stream);
+// C (m x m, lower triangle) <- C - A A^T in native FP64 (rocBLAS dsyrk).
+int native_syrk_update(int m, int k, const double *A, long long lda, double *C, long long ldc,
+                       hipStream_t stream);
 // Interchanges ipiv[k1..k2) on columns [0, ncols_left) and [col_right,
 // col_right + ncols_right); plan: laswp_plan_bytes(nrows) bytes of scratch.
 size_t laswp_plan_bytes(int nrows);

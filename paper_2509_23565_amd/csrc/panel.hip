@@ -61,6 +61,7 @@ struct LeafX {
     unsigned long long *rec;        // [2][LF_MAX_G][RW]
     int *abort;                     // set by a workgroup whose wait exceeded the bound
     int *status;                    // device status word (EMU_STATUS_PANEL_WAIT)
+    int nopiv;                      // no interchanges: row c is the pivot of column c
 };
 
 __device__ __forceinline__ void st_relaxed(double *p, double v) {
@@ -175,7 +176,9 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
 #pragma unroll
     for (int q = 0; q < LF_R; ++q) {
         const int i = base_row + t + q * NT;
-        valid[q] = i >= c && i < rows;
+        // without pivoting row c is the only candidate, so it wins the
+        // search below and no interchange follows
+        valid[q] = (x.nopiv ? i == c : i >= c) && i < rows;
         if (valid[q]) m = fmax(m, fabs(v[q][k]));
     }
     const double M = wave_max_f64(m);
@@ -575,12 +578,15 @@ __global__ __launch_bounds__(NT) void k_leaf(double *__restrict__ P, long long l
 // increasing order as c = c - a_ik b_kj (two roundings), as in elimination.
 // Tile TM x 64 (TM = 64, 32 or 16; narrow tiles when the output is small,
 // so the launch still covers the chip), 256 threads of (TM / 16) x 4.
+// TB: B is given transposed (b_kj at B[j + k ldb]; the Cholesky panel's
+// L21 L21^T); lower: only entries with i >= j are written (the rest of C
+// is neither stored nor meant to change).
 constexpr int GS_N = 64, GS_K = 16;
-template <int TM>
+template <int TM, bool TB = false>
 __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, long long lda,
                                                   const double *__restrict__ B, long long ldb,
                                                   double *__restrict__ C, long long ldc, int m,
-                                                  int n, int k) {
+                                                  int n, int k, int lower = 0) {
     constexpr int RM = TM / 16;
     __shared__ double As[GS_K][TM + 1];
     __shared__ double Bs[GS_K][GS_N + 1];
@@ -607,9 +613,12 @@ __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, 
         }
 #pragma unroll
         for (int r = 0; r < PB; ++r) {
-            const int e = t + 256 * r, kk = e % GS_K, jj = e / GS_K;
+            const int e = t + 256 * r;
+            const int kk = TB ? e / GS_N : e % GS_K, jj = TB ? e % GS_N : e / GS_K;
             const int j = n0 + jj, kx = k0 + kk;
-            bv[r] = (j < n && kx < k) ? B[kx + (long long)j * ldb] : 0.0;
+            bv[r] = (j < n && kx < k) ? (TB ? B[j + (long long)kx * ldb]
+                                            : B[kx + (long long)j * ldb])
+                                      : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < PA; ++r) {
@@ -619,7 +628,10 @@ __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, 
 #pragma unroll
         for (int r = 0; r < PB; ++r) {
             const int e = t + 256 * r;
-            Bs[e % GS_K][e / GS_K] = bv[r];
+            if (TB)
+                Bs[e / GS_N][e % GS_N] = bv[r];
+            else
+                Bs[e % GS_K][e / GS_K] = bv[r];
         }
         __syncthreads();
         const int kend = min(GS_K, k - k0);
@@ -641,24 +653,25 @@ __global__ __launch_bounds__(256) void k_gemm_seq(const double *__restrict__ A, 
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int i = m0 + tr + 16 * r, j = n0 + tc + 16 * s;
-            if (i < m && j < n) C[i + (long long)j * ldc] = c[r][s];
+            if (i < m && j < n && (!lower || i >= j)) C[i + (long long)j * ldc] = c[r][s];
         }
 }
 
+template <bool TB = false>
 static int gemm_seq(const double *A, long long lda, const double *B, long long ldb, double *C,
-                    long long ldc, int m, int n, int k, hipStream_t st) {
+                    long long ldc, int m, int n, int k, hipStream_t st, int lower = 0) {
     if (m <= 0 || n <= 0 || k <= 0) return 0;
     const int gy = (n + GS_N - 1) / GS_N;
     const long long want = 1024;      // workgroups that keep every CU busy
     if ((long long)((m + 63) / 64) * gy >= want) {
-        hipLaunchKernelGGL(k_gemm_seq<64>, dim3((m + 63) / 64, gy), dim3(256), 0, st, A, lda, B,
-                           ldb, C, ldc, m, n, k);
+        hipLaunchKernelGGL((k_gemm_seq<64, TB>), dim3((m + 63) / 64, gy), dim3(256), 0, st, A,
+                           lda, B, ldb, C, ldc, m, n, k, lower);
     } else if ((long long)((m + 31) / 32) * gy >= want) {
-        hipLaunchKernelGGL(k_gemm_seq<32>, dim3((m + 31) / 32, gy), dim3(256), 0, st, A, lda, B,
-                           ldb, C, ldc, m, n, k);
+        hipLaunchKernelGGL((k_gemm_seq<32, TB>), dim3((m + 31) / 32, gy), dim3(256), 0, st, A,
+                           lda, B, ldb, C, ldc, m, n, k, lower);
     } else {
-        hipLaunchKernelGGL(k_gemm_seq<16>, dim3((m + 15) / 16, gy), dim3(256), 0, st, A, lda, B,
-                           ldb, C, ldc, m, n, k);
+        hipLaunchKernelGGL((k_gemm_seq<16, TB>), dim3((m + 15) / 16, gy), dim3(256), 0, st, A,
+                           lda, B, ldb, C, ldc, m, n, k, lower);
     }
     EMU_TRY_HIP(hipGetLastError());
     return 0;
@@ -747,6 +760,7 @@ static LeafX leaf_x(char *ws, int *status) {
     x.rec = reinterpret_cast<unsigned long long *>(ws);
     x.abort = reinterpret_cast<int *>(x.rec + 2 * LF_MAX_G * RW);
     x.status = status;
+    x.nopiv = 0;
     return x;
 }
 
@@ -757,6 +771,7 @@ struct PanelRun {
     char *ws;
     int *status;
     unsigned arrivals;
+    bool pivot;
 };
 
 // Multi-workgroup leaves are plain launches unless this is set.  Their
@@ -771,6 +786,7 @@ void set_leaf_cooperative(int on) { g_leaf_cooperative = on != 0; }
 static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0, int *info,
                 int ncl, int ncr, PanelRun &pr, hipStream_t st) {
     LeafX x = leaf_x(pr.ws, pr.status);
+    x.nopiv = pr.pivot ? 0 : 1;
     if (rows <= LF_ROWS / 2) {
         hipLaunchKernelGGL((k_leaf<false, LF_THREADS / 2>), dim3(1), dim3(LF_THREADS / 2), 0, st,
                            P, lda, rows, w, ipiv, grow0, info, x, 0u, ncl, ncr);
@@ -825,8 +841,8 @@ static int panel_rec(double *A, long long lda, int m_rows, int pw, int c0, int w
 }
 
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0, int *info,
-                 char *ws, int *status, hipStream_t stream) {
-    PanelRun pr{ws, status, 0u};
+                 char *ws, int *status, hipStream_t stream, bool pivot) {
+    PanelRun pr{ws, status, 0u, pivot};
     if (rows > LF_ROWS) {
         // record words (tag 0: not yet written) and the abort flag start at
         // zero (a fill kernel, not a memset)
@@ -835,6 +851,129 @@ int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0
                                 stream));
     }
     return panel_rec(A, lda, rows, jb, 0, jb, ipiv, row0, info, pr, stream);
+}
+
+
+// ------------------------------------------------------ Cholesky panel
+// Lower Cholesky of a tall panel (the symmetric variant of the factorization:
+// the paper names it beside LU as a solver the emulated update serves).
+// Same recursion as the LU panel, without interchanges: a strip of at most
+// 16 columns is a leaf; the columns right of a strip lose L21 L_strip^T by
+// the order-preserving FP64 tile kernel (B transposed, lower entries only).
+// Element (i, j), i >= j, receives a_ij - l_ik l_jk for k = 0..j-1 in that
+// order and then l_ij = a_ij * (1 / l_jj), with l_jj = sqrt(a_jj): the
+// unblocked right-looking order.
+//
+// Leaf: every workgroup factors the strip's 16 x 16 diagonal block itself
+// (one wave, lane i holding row i; every workgroup computes the same bits),
+// so no workgroup waits for another; then each thread finishes its own rows
+// below the block (4 per thread, 1024 per workgroup) with the block's L and
+// reciprocals from LDS.  Workgroup 0 writes the block's lower triangle and
+// the first column whose pivot is not positive (or NaN) into *info (if
+// *info is still 0); the factorization is not stopped there, so entries
+// from that column on are unspecified.
+constexpr int CH_THREADS = 256;
+constexpr int CH_R = 4;
+constexpr int CH_ROWS = CH_THREADS * CH_R;
+
+__global__ __launch_bounds__(CH_THREADS) void k_chol_leaf(double *__restrict__ P, long long lda,
+                                                          int rows, int w, int gcol0,
+                                                          int *__restrict__ info) {
+    __shared__ double Ld[LEAF_W][LEAF_W + 1];
+    __shared__ double rr[LEAF_W];
+    __shared__ int fail;
+    const int t = threadIdx.x, lane = t & 63;
+    const int g = blockIdx.x;
+    const int nd = w < rows ? w : rows;          // rows of the diagonal block
+    if (t < 64) {
+        // lane i < nd holds row i of the diagonal block (lower part)
+        double d[LEAF_W];
+#pragma unroll
+        for (int j = 0; j < LEAF_W; ++j)
+            d[j] = (lane < nd && j < w && j <= lane) ? P[lane + (long long)j * lda] : 0.0;
+        int first = -1;
+#pragma unroll
+        for (int c = 0; c < LEAF_W; ++c) {
+            if (c < nd) {
+                const double a = uniform_f64(__shfl(d[c], c));
+                if (!(a > 0.0) && first < 0) first = c;
+                const double l = sqrt(a);
+                const double r = 1.0 / l;
+                if (lane == c) d[c] = l;
+                if (lane > c) d[c] = d[c] * r;
+                if (lane == 0) rr[c] = r;
+#pragma unroll
+                for (int j = c + 1; j < LEAF_W; ++j) {
+                    if (j < nd) {
+                        const double ljc = __shfl(d[c], j);
+                        if (lane >= j) d[j] = d[j] - d[c] * ljc;
+                    }
+                }
+            }
+        }
+        if (lane < nd)
+#pragma unroll
+            for (int j = 0; j < LEAF_W; ++j) Ld[lane][j] = d[j];
+        if (lane == 0) fail = first;
+        if (g == 0 && lane < nd)
+#pragma unroll
+            for (int j = 0; j < LEAF_W; ++j)
+                if (j <= lane) P[lane + (long long)j * lda] = d[j];
+    }
+    __syncthreads();
+    if (g == 0 && t == 0 && fail >= 0 && *info == 0) *info = gcol0 + fail + 1;
+    // rows below the diagonal block
+#pragma unroll
+    for (int q = 0; q < CH_R; ++q) {
+        const int i = g * CH_ROWS + t + q * CH_THREADS;
+        if (i < nd || i >= rows) continue;
+        double a[LEAF_W];
+#pragma unroll
+        for (int j = 0; j < LEAF_W; ++j) a[j] = j < w ? P[i + (long long)j * lda] : 0.0;
+#pragma unroll
+        for (int c = 0; c < LEAF_W; ++c) {
+            if (c < w) {
+                const double x = a[c] * rr[c];
+                a[c] = x;
+#pragma unroll
+                for (int j = c + 1; j < LEAF_W; ++j)
+                    if (j < w) a[j] = a[j] - x * Ld[j][c];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < LEAF_W; ++j)
+            if (j < w) P[i + (long long)j * lda] = a[j];
+    }
+}
+
+// Columns [c0, c0 + w) of the panel at A (rows [c0, m_rows)); gcol0: global
+// column of panel column 0.
+static int chol_rec(double *A, long long lda, int m_rows, int c0, int w, int gcol0, int *info,
+                    hipStream_t st) {
+    double *P = A + c0 + (long long)c0 * lda;
+    const int rows = m_rows - c0;
+    if (rows <= 0) return 0;
+    if (w <= LEAF_W) {
+        const int G = (rows + CH_ROWS - 1) / CH_ROWS;
+        hipLaunchKernelGGL(k_chol_leaf, dim3(G), dim3(CH_THREADS), 0, st, P, lda, rows, w,
+                           gcol0 + c0, info);
+        EMU_TRY_HIP(hipGetLastError());
+        return 0;
+    }
+    int w1 = (w / 2) / LEAF_W * LEAF_W;
+    if (w1 < LEAF_W) w1 = LEAF_W;
+    const int w2 = w - w1;
+    EMU_TRY(chol_rec(A, lda, m_rows, c0, w1, gcol0, info, st));
+    // C = panel rows [c0 + w1, m_rows) x columns [c0 + w1, c0 + w) minus
+    // L(those rows, strip) L(rows c0 + w1 .. c0 + w, strip)^T, lower part
+    EMU_TRY(gemm_seq<true>(P + w1, lda, P + w1, lda, P + w1 + (long long)w1 * lda, lda,
+                           rows - w1, w2, w1, st, 1));
+    return chol_rec(A, lda, m_rows, c0 + w1, w2, gcol0, info, st);
+}
+
+int launch_chol_panel(double *A, long long lda, int rows, int jb, int col0, int *info,
+                      hipStream_t stream) {
+    return chol_rec(A, lda, rows, 0, jb, col0, info, stream);
 }
 
 }  // namespace emu

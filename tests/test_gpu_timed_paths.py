@@ -6,6 +6,10 @@ timed workload, compared with the CPU oracle bit for bit:
 * the emulated GEMM at s = 9 with K between the plain exact length (14784)
   and the split-diagonal one (16640): the longest diagonal is split over two
   accumulator tiles and folded back in the epilogue (the 16384^3 product);
+* tile counts that are multiples of 16 in both directions (every square
+  size the benchmark times), where the workgroups of all XCDs share one
+  block of tiles at a time ("gemm_map" 1, the default), against the oracle
+  and against the per-XCD order;
 * K above 16640: exact-length chunks of INT32 partial sums, added in INT64
   and recombined into C by the combine pass;
 * the batched LU at s = 6, 7 and 9 (the pipelined one-K-step grouped GEMM)
@@ -43,6 +47,21 @@ def _host(t):
 # nine pairs -> 14784, eight pairs (longest diagonal split) -> 16640
 K_PLAIN_S9 = 14784
 K_SPLIT_S9 = 16640
+
+
+@pytest.mark.parametrize("m,n,k,s", [(1024, 2048, 300, 9), (2048, 2048, 200, 3)])
+def test_dgemm_shared_tile_block_order(m, n, k, s):
+    A = matgen.phi_matrix(m, k, 1.0, seed=74, substream=0)
+    B = matgen.phi_matrix(k, n, 1.0, seed=74, substream=1)
+    Ag, Bg = emu.colmajor(A), emu.colmajor(B)
+    ref = O.dgemm_emu(A, B, s)
+    try:
+        for mp in (1, 0):
+            emu.set_param("gemm_map", mp)
+            Cg = emu.dgemm(Ag, Bg, nslices=s)
+            assert _same_bits(_host(Cg), ref), mp
+    finally:
+        emu.set_param("gemm_map", 1)
 
 
 def test_dgemm_split_longest_diagonal_s9():

@@ -70,13 +70,15 @@ def test_lu_argument_errors():
     assert emu.emu_dgetrf(4, 4, _p(), 3, _p(), _p(), 64, 7) == -4
     assert emu.emu_dgetrf(4, 4, _p(), 4, None, _p(), 64, 7) == -5
     assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), None, 64, 7) == -6
-    assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 2048, 7) == -7
+    assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), emu.EMU_MAX_NB + 1, 7) == -7
     assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 64, 0) == -8
     assert emu.emu_dgetrf(4, 4, _p(), 4, _p(), _p(), 64, 17) == -8
     assert emu.emu_dgetrs(4, 1, _p(), 3, _p(), _p(), 4) == -4
     assert emu.emu_dgetrs(4, -1, _p(), 4, _p(), _p(), 4) == -2
     assert emu.emu_dgetrs(4, 1, _p(), 4, _p(), _p(), 2) == -7
     assert emu.emu_status(None) == -1
+    for key in ("lu_pivot", "lu_update", "gemm_map"):
+        assert emu.emu_set_param(key.encode(), 2) == -2
 
 
 def test_workspace_calls_argument_codes_and_sizes():
@@ -89,7 +91,8 @@ def test_workspace_calls_argument_codes_and_sizes():
     small = emu.emu_workspace_bytes(100, 100, 100, 3)
     assert small >= 2 * 3 * 128 * 128
     assert emu.emu_workspace_bytes(100, 100, 100, 7) > small
-    assert emu.emu_getrf_workspace_bytes(4, 4, 2048, 7) == 0
+    assert emu.emu_getrf_workspace_bytes(4, 4, emu.EMU_MAX_NB + 1, 7) == 0
+    assert emu.emu_getrf_workspace_bytes(4000, 4000, 2048, 7) > 0
     assert emu.emu_getrf_workspace_bytes(1000, 1000, 128, 7) > 0
     assert emu.emu_getrs_workspace_bytes(-1, 1) == 0
     assert emu.emu_getrs_workspace_bytes(1000, 2) >= 1000 * 2 * 8
