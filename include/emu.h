@@ -362,6 +362,32 @@ int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A
                       const int *ldb, int nb, int nslices);
 
 /*
+ * emu_dgesv_batched_ir: the precision form for a batch (the single-system
+ * form is emu_dgesv_ir): A[i] and B[i] (host arrays of DEVICE pointers,
+ * n[i] in 1..1024, nrhs[i] in 1..8) are left untouched; X[i] (ldx[i] >=
+ * n[i]) receives the solutions.  All systems are factored together from
+ * copies of A with nslices slices (1..9; grouped launches as in
+ * emu_dgesv_batched, block size nb in 1..32, 0 selects 32) and solved;
+ * then every system not yet at tol takes a refinement step: FP64 residual
+ * r = B - A X and its backward error eta = max over columns of
+ * ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf); eta <= tol ends the
+ * system; eta not below half the previous one, more than maxiter steps or
+ * NaN sends it back to be refactored with two slices more (at most nine);
+ * otherwise d = solve(LU, r), x += d.  Systems still refining share one
+ * grouped launch per phase.  Host outputs per system: iters[i] (corrections
+ * applied), berr[i] (last eta), s_final[i], info[i] (> 0: U(info,info) is
+ * exactly zero; no refinement).  Synchronizes; allocates and frees device
+ * memory for the factors and residuals.  Returns 0, or
+ * EMU_ERR_NOT_CONVERGED when a system missed tol at nine slices.
+ * Argument numbers: count=1 n/nrhs=2 A/lda=4 B/ldb=6 X/ldx=8 nb=10
+ * nslices=11 tol=12 maxiter=13 outputs=14.
+ */
+int emu_dgesv_batched_ir(int count, const int *n, const int *nrhs, const double *const *A,
+                         const int *lda, const double *const *B, const int *ldb,
+                         double *const *X, const int *ldx, int nb, int nslices, double tol,
+                         int maxiter, int *iters, double *berr, int *s_final, int *info);
+
+/*
  * emu_autotune_batched: time the batched solve of this batch on private
  * copies (inputs untouched) for block sizes {16, 32} and grouped-GEMM grid
  * sizes {1, 2} x (CUs x resident workgroups), record the fastest for the

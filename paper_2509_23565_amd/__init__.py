@@ -37,6 +37,7 @@ __all__ = [
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status", "emu_dgemm_noalloc", "EMU_NOALLOC_SCRATCH_BYTES",
     "emu_dpotrf", "emu_potrf_workspace_bytes", "dpotrf",
+    "emu_dgesv_batched_ir", "dgesv_batched_ir",
 ]
 
 EMU_MAX_SLICES = 16
@@ -73,6 +74,8 @@ _SIGNATURES = {
     "emu_dgemm": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
     "emu_dgemm_noalloc": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
     "emu_dpotrf": ([_I, _P, _I, _P, _I, _I], _I),
+    "emu_dgesv_batched_ir": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I, _D, _I, _P, _P, _P,
+                              _P], _I),
     "emu_potrf_workspace_bytes": ([_I, _I, _I], ctypes.c_size_t),
     "emu_dgemm_t": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I, _I], _I),
     "emu_dgetrf": ([_I, _I, _P, _I, _P, _P, _I, _I], _I),
@@ -142,6 +145,7 @@ emu_status = _raw("emu_status")
 emu_dgemm = _raw("emu_dgemm")
 emu_dgemm_noalloc = _raw("emu_dgemm_noalloc")
 emu_dpotrf = _raw("emu_dpotrf")
+emu_dgesv_batched_ir = _raw("emu_dgesv_batched_ir")
 emu_potrf_workspace_bytes = _raw("emu_potrf_workspace_bytes")
 emu_dgemm_t = _raw("emu_dgemm_t")
 emu_dgetrf = _raw("emu_dgetrf")
@@ -368,6 +372,33 @@ def dgesv_batched(As, Bs, nb=32, nslices=5):
     _check(emu_dgesv_batched(count, n, nrhs, a.ptr, a.ld, pp, info.data_ptr(), b.ptr, b.ld,
                              int(nb), int(nslices)), "emu_dgesv_batched")
     return ipivs, info
+
+
+def dgesv_batched_ir(As, Bs, Xs=None, nb=32, nslices=3, tol=1e-15, maxiter=10):
+    """Batched precision form: As, Bs untouched, Xs (allocated when None)
+    receive the solutions.  Returns (Xs, dict(rc, iters, berr, s_final, info)
+    with per-system lists); rc is 0 or EMU_ERR_NOT_CONVERGED (1004)."""
+    torch = _torch()
+    count = len(As)
+    if Xs is None:
+        Xs = [torch.empty((b.shape[1], b.shape[0]), dtype=torch.float64, device=b.device).t()
+              for b in Bs]
+    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
+    nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
+    a = _Batch(As, "A")
+    b = _Batch(Bs, "B")
+    x = _Batch(Xs, "X")
+    iters = (ctypes.c_int * count)()
+    berr = (ctypes.c_double * count)()
+    sfin = (ctypes.c_int * count)()
+    info = (ctypes.c_int * count)()
+    _bind_stream()
+    rc = emu_dgesv_batched_ir(count, n, nrhs, a.ptr, a.ld, b.ptr, b.ld, x.ptr, x.ld, int(nb),
+                              int(nslices), float(tol), int(maxiter), iters, berr, sfin, info)
+    if rc not in (0, EMU_ERR_NOT_CONVERGED):
+        _check(rc, "emu_dgesv_batched_ir")
+    return Xs, {"rc": rc, "iters": list(iters), "berr": list(berr), "s_final": list(sfin),
+                "info": list(info)}
 
 
 def dgetrf_batched(As, nb=32, nslices=5):

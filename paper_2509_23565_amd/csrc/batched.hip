@@ -673,6 +673,138 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
     return 0;
 }
 
+
+// --------------------------------------------------- batched refinement
+// Precision form for a batch: every system is factored (grouped, as above)
+// from a copy of A with s slices and solved; then, per system, the FP64
+// residual r = b - A x and eta = max_r ||r||_inf / (||A||_inf ||x||_inf +
+// ||b||_inf) (the single-system form's stopping quantity), a solve with the
+// stored factors and x += d, until eta <= tol.  A system whose eta stops
+// halving, exceeds the step budget or is NaN is refactored with two slices
+// more (up to nine), the others keep their result.  All systems still
+// refining take one grouped launch per phase.
+struct BIr {
+    const double *A;
+    long long lda;
+    const double *B;
+    long long ldb;
+    double *X;
+    long long ldx;
+    double *R;          // n x nrhs, leading dimension n
+    int n, nrhs;
+};
+
+struct BCopy {
+    const double *src;
+    long long lds;
+    double *dst;
+    long long ldd;
+    int rows, cols;
+};
+
+__global__ __launch_bounds__(256) void k_bcopy(const BCopy *__restrict__ jobs) {
+    const BCopy J = jobs[blockIdx.x];
+    const long long total = (long long)J.rows * J.cols;
+    for (long long e = threadIdx.x; e < total; e += blockDim.x) {
+        const int i = (int)(e % J.rows), j = (int)(e / J.rows);
+        J.dst[i + (long long)j * J.ldd] = J.src[i + (long long)j * J.lds];
+    }
+}
+
+// One workgroup per system: R = B - A X (each entry: the products a_ij x_j
+// accumulated with fma in increasing j, then subtracted from b), and eta.
+__global__ __launch_bounds__(256) void k_bresid(const BIr *__restrict__ sys,
+                                                double *__restrict__ eta) {
+    __shared__ double xs[BMAX_N * BMAX_RHS];
+    __shared__ double red[4][1 + 3 * BMAX_RHS];
+    const BIr S = sys[blockIdx.x];
+    const int n = S.n, nr = S.nrhs, t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    for (int e = t; e < n * nr; e += blockDim.x)
+        xs[(e / n) * BMAX_N + e % n] = S.X[e % n + (long long)(e / n) * S.ldx];
+    __syncthreads();
+    double mA = 0.0, mR[BMAX_RHS], mX[BMAX_RHS], mB[BMAX_RHS];
+#pragma unroll
+    for (int r = 0; r < BMAX_RHS; ++r) mR[r] = mX[r] = mB[r] = 0.0;
+    for (int i = t; i < n; i += blockDim.x) {
+        double ax[BMAX_RHS], ra = 0.0;
+#pragma unroll
+        for (int r = 0; r < BMAX_RHS; ++r) ax[r] = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double a = S.A[i + (long long)j * S.lda];
+            ra += fabs(a);
+#pragma unroll
+            for (int r = 0; r < BMAX_RHS; ++r)
+                if (r < nr) ax[r] = fma(a, xs[r * BMAX_N + j], ax[r]);
+        }
+        mA = fmax(mA, ra);
+#pragma unroll
+        for (int r = 0; r < BMAX_RHS; ++r) {
+            if (r < nr) {
+                const double b = S.B[i + (long long)r * S.ldb];
+                const double rv = b - ax[r];
+                S.R[i + (long long)r * n] = rv;
+                mR[r] = (rv != rv || mR[r] != mR[r]) ? __builtin_nan("") : fmax(mR[r], fabs(rv));
+                mX[r] = fmax(mX[r], fabs(xs[r * BMAX_N + i]));
+                mB[r] = fmax(mB[r], fabs(b));
+            }
+        }
+    }
+    // workgroup maxima (NaN in a residual is kept)
+    auto wmax = [&](double v) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const double w = __shfl_xor(v, o);
+            v = (v != v || w != w) ? __builtin_nan("") : fmax(v, w);
+        }
+        return v;
+    };
+    mA = wmax(mA);
+#pragma unroll
+    for (int r = 0; r < BMAX_RHS; ++r) {
+        mR[r] = wmax(mR[r]);
+        mX[r] = wmax(mX[r]);
+        mB[r] = wmax(mB[r]);
+    }
+    if (lane == 0) {
+        red[wid][0] = mA;
+#pragma unroll
+        for (int r = 0; r < BMAX_RHS; ++r) {
+            red[wid][1 + 3 * r] = mR[r];
+            red[wid][2 + 3 * r] = mX[r];
+            red[wid][3 + 3 * r] = mB[r];
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        double nA = 0.0, e = 0.0;
+        for (int w = 0; w < 4; ++w) nA = fmax(nA, red[w][0]);
+        for (int r = 0; r < nr; ++r) {
+            double R = 0.0, X = 0.0, B = 0.0;
+            bool nan = false;
+            for (int w = 0; w < 4; ++w) {
+                const double v = red[w][1 + 3 * r];
+                nan = nan || v != v;
+                R = fmax(R, v);
+                X = fmax(X, red[w][2 + 3 * r]);
+                B = fmax(B, red[w][3 + 3 * r]);
+            }
+            const double den = nA * X + B;
+            const double er = nan ? __builtin_nan("") : (den > 0.0 ? R / den : R);
+            if (!(er <= e)) e = er;
+        }
+        eta[blockIdx.x] = e;
+    }
+}
+
+// X += R (the correction the solve left in R), one workgroup per system.
+__global__ __launch_bounds__(256) void k_badd(const BIr *__restrict__ sys) {
+    const BIr S = sys[blockIdx.x];
+    for (int e = threadIdx.x; e < S.n * S.nrhs; e += blockDim.x) {
+        const int i = e % S.n, r = e / S.n;
+        double *x = S.X + i + (long long)r * S.ldx;
+        *x = *x + S.R[i + (long long)r * S.n];
+    }
+}
+
 // ------------------------------------------------------ graph cache, tuning
 struct GraphEntry {
     BatchPlan plan;
@@ -864,6 +996,199 @@ int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A
         mult = t != g_tuned.end() ? t->second.second : 1;
     }
     return run_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, mult, true);
+}
+
+int emu_dgesv_batched_ir(int count, const int *n, const int *nrhs, const double *const *A,
+                         const int *lda, const double *const *B, const int *ldb,
+                         double *const *X, const int *ldx, int nb, int nslices, double tol,
+                         int maxiter, int *iters, double *berr, int *s_final, int *info) {
+    if (count < 0) return -1;
+    if (count > 0 && (!n || !nrhs)) return -2;
+    if (count > 0 && (!A || !lda)) return -4;
+    if (count > 0 && (!B || !ldb)) return -6;
+    if (count > 0 && (!X || !ldx)) return -8;
+    if (nb < 0 || nb > BMAX_NB) return -10;
+    if (nslices < 1 || nslices > GROUPED_MAX_SLICES) return -11;
+    if (!(tol > 0.0)) return -12;
+    if (maxiter < 0) return -13;
+    if (count > 0 && (!iters || !berr || !s_final || !info)) return -14;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 1 || n[i] > BMAX_N || nrhs[i] < 1 || nrhs[i] > BMAX_RHS) {
+            set_error("batched refinement: system %d has n = %d, nrhs = %d (1..%d, 1..%d)", i,
+                      n[i], nrhs[i], BMAX_N, BMAX_RHS);
+            return EMU_ERR_UNSUPPORTED;
+        }
+        if (!A[i] || lda[i] < n[i]) return -4;
+        if (!B[i] || ldb[i] < n[i]) return -6;
+        if (!X[i] || ldx[i] < n[i]) return -8;
+        iters[i] = 0;
+        berr[i] = 0.0;
+        s_final[i] = nslices;
+        info[i] = 0;
+    }
+    if (count == 0) return 0;
+    if (nb == 0) nb = BMAX_NB;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    // private memory of this call: factors, pivots, info, residuals, eta,
+    // descriptor tables
+    std::vector<size_t> o_lu(count), o_piv(count), o_r(count);
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        o_lu[i] = off;
+        off += align256((size_t)n[i] * n[i] * sizeof(double));
+        o_piv[i] = off;
+        off += align256((size_t)n[i] * sizeof(int));
+        o_r[i] = off;
+        off += align256((size_t)n[i] * nrhs[i] * sizeof(double));
+    }
+    const size_t o_info = off;
+    off += align256((size_t)count * sizeof(int));
+    const size_t o_eta = off;
+    off += align256((size_t)count * sizeof(double));
+    const size_t o_ir = off;
+    off += align256((size_t)count * sizeof(BIr));
+    const size_t o_cp = off;
+    off += align256((size_t)2 * count * sizeof(BCopy));
+    char *mem = nullptr;
+    EMU_TRY_HIP(hipMalloc(&mem, off));
+    struct Free {
+        char *p;
+        hipStream_t st;
+        ~Free() {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(p);
+        }
+    } guard{mem, st};
+    auto LUp = [&](int i) { return reinterpret_cast<double *>(mem + o_lu[i]); };
+    auto PIVp = [&](int i) { return reinterpret_cast<int *>(mem + o_piv[i]); };
+    auto Rp = [&](int i) { return reinterpret_cast<double *>(mem + o_r[i]); };
+    int *dinfo = reinterpret_cast<int *>(mem + o_info);
+    double *deta = reinterpret_cast<double *>(mem + o_eta);
+    BIr *dir = reinterpret_cast<BIr *>(mem + o_ir);
+    BCopy *dcp = reinterpret_cast<BCopy *>(mem + o_cp);
+
+    std::vector<int> todo(count);             // systems to (re)factor
+    std::iota(todo.begin(), todo.end(), 0);
+    // host descriptor tables, alive for the whole call: each is rewritten
+    // only after a stream synchronization that follows its last upload
+    std::vector<BIr> ir, ir2;
+    std::vector<BSys> sol;
+    ir.reserve(count);
+    ir2.reserve(count);
+    sol.reserve(count);
+    std::vector<double> prev(count), heta(count);
+    int s = nslices;
+    int rc_all = 0;
+    while (!todo.empty()) {
+        const int c = (int)todo.size();
+        // copies A -> LU, B -> X of the systems to factor
+        std::vector<BCopy> cp(2 * c);
+        std::vector<int> sn(c), snr(c), sld(c), sldx(c);
+        std::vector<double *> sA(c), sX(c);
+        std::vector<int *> spiv(c);
+        for (int q = 0; q < c; ++q) {
+            const int i = todo[q];
+            cp[2 * q] = {A[i], lda[i], LUp(i), n[i], n[i], n[i]};
+            cp[2 * q + 1] = {B[i], ldb[i], X[i], ldx[i], n[i], nrhs[i]};
+            sn[q] = n[i];
+            snr[q] = nrhs[i];
+            sld[q] = n[i];
+            sldx[q] = ldx[i];
+            sA[q] = LUp(i);
+            sX[q] = X[i];
+            spiv[q] = PIVp(i);
+        }
+        EMU_TRY_HIP(hipMemcpyAsync(dcp, cp.data(), cp.size() * sizeof(BCopy),
+                                   hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_bcopy, dim3(2 * c), dim3(256), 0, st, dcp);
+        EMU_TRY_HIP(hipGetLastError());
+        EMU_TRY(run_batch(c, sn.data(), snr.data(), sA.data(), sld.data(), spiv.data(), dinfo,
+                          sX.data(), sldx.data(), nb, s, 1, true));
+        std::vector<int> hinfo(c);
+        EMU_TRY_HIP(hipMemcpyAsync(hinfo.data(), dinfo, c * sizeof(int), hipMemcpyDeviceToHost,
+                                   st));
+        EMU_TRY_HIP(hipStreamSynchronize(st));
+        std::vector<int> act;                 // systems refining
+        for (int q = 0; q < c; ++q) {
+            const int i = todo[q];
+            info[i] = hinfo[q];
+            s_final[i] = s;
+            prev[i] = -1.0;
+            if (hinfo[q] == 0) act.push_back(i);
+        }
+        std::vector<int> fall;                // systems to refactor with more slices
+        for (int it = 0; !act.empty(); ++it) {
+            const int a = (int)act.size();
+            ir.resize(a);
+            for (int q = 0; q < a; ++q) {
+                const int i = act[q];
+                ir[q] = {A[i], lda[i], B[i], ldb[i], X[i], ldx[i], Rp(i), n[i], nrhs[i]};
+            }
+            EMU_TRY_HIP(hipMemcpyAsync(dir, ir.data(), a * sizeof(BIr), hipMemcpyHostToDevice,
+                                       st));
+            hipLaunchKernelGGL(k_bresid, dim3(a), dim3(256), 0, st, dir, deta);
+            EMU_TRY_HIP(hipGetLastError());
+            EMU_TRY_HIP(hipMemcpyAsync(heta.data(), deta, a * sizeof(double),
+                                       hipMemcpyDeviceToHost, st));
+            EMU_TRY_HIP(hipStreamSynchronize(st));
+            std::vector<int> next;
+            sol.clear();
+            for (int q = 0; q < a; ++q) {
+                const int i = act[q];
+                const double e = heta[q];
+                berr[i] = e;
+                if (e <= tol) continue;
+                if (it >= maxiter || (prev[i] >= 0.0 && !(e <= 0.5 * prev[i])) || e != e) {
+                    fall.push_back(i);
+                    continue;
+                }
+                prev[i] = e;
+                ++iters[i];
+                next.push_back(i);
+                BSys S{};
+                S.A = LUp(i);
+                S.lda = n[i];
+                S.n = n[i];
+                S.nrhs = nrhs[i];
+                S.ipiv = PIVp(i);
+                S.info = dinfo;
+                S.B = Rp(i);
+                S.ldb = n[i];
+                sol.push_back(S);
+            }
+            if (!next.empty()) {
+                // correction: d = solve(LU, r) in R, then x += d
+                const int b = (int)next.size();
+                static_assert(sizeof(BSys) <= 2 * sizeof(BCopy), "descriptor space");
+                BSys *dsys = reinterpret_cast<BSys *>(dcp);     // the copies are done
+                EMU_TRY_HIP(hipMemcpyAsync(dsys, sol.data(), b * sizeof(BSys),
+                                           hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_bgetrs, dim3(b), dim3(1024), 0, st, dsys);
+                ir2.resize(b);
+                for (int q = 0; q < b; ++q) {
+                    const int i = next[q];
+                    ir2[q] = {A[i], lda[i], B[i], ldb[i], X[i], ldx[i], Rp(i), n[i], nrhs[i]};
+                }
+                EMU_TRY_HIP(hipMemcpyAsync(dir, ir2.data(), b * sizeof(BIr),
+                                           hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_badd, dim3(b), dim3(256), 0, st, dir);
+                EMU_TRY_HIP(hipGetLastError());
+            }
+            act.swap(next);
+        }
+        if (fall.empty()) break;
+        if (s >= GROUPED_MAX_SLICES) {
+            set_error("batched refinement: %zu system(s) missed %g at %d slices", fall.size(),
+                      tol, s);
+            rc_all = EMU_ERR_NOT_CONVERGED;
+            break;
+        }
+        s = s + 2 < GROUPED_MAX_SLICES ? s + 2 : GROUPED_MAX_SLICES;
+        todo.swap(fall);
+    }
+    return rc_all;
 }
 
 int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const *A,

@@ -96,3 +96,25 @@ def test_workspace_calls_argument_codes_and_sizes():
     assert emu.emu_getrf_workspace_bytes(1000, 1000, 128, 7) > 0
     assert emu.emu_getrs_workspace_bytes(-1, 1) == 0
     assert emu.emu_getrs_workspace_bytes(1000, 2) >= 1000 * 2 * 8
+
+
+def test_batched_refinement_argument_codes():
+    n = (ctypes.c_int * 1)(8)
+    r = (ctypes.c_int * 1)(1)
+    ld = (ctypes.c_int * 1)(8)
+    P = (ctypes.c_void_p * 1)(0x1000)
+    it = (ctypes.c_int * 1)()
+    be = (ctypes.c_double * 1)()
+    sf = (ctypes.c_int * 1)()
+    inf = (ctypes.c_int * 1)()
+    f = emu.emu_dgesv_batched_ir
+    assert f(-1, n, r, P, ld, P, ld, P, ld, 32, 3, 1e-15, 10, it, be, sf, inf) == -1
+    assert f(1, n, r, P, ld, P, ld, P, ld, 33, 3, 1e-15, 10, it, be, sf, inf) == -10
+    assert f(1, n, r, P, ld, P, ld, P, ld, 32, 10, 1e-15, 10, it, be, sf, inf) == -11
+    assert f(1, n, r, P, ld, P, ld, P, ld, 32, 3, 0.0, 10, it, be, sf, inf) == -12
+    assert f(1, n, r, P, ld, P, ld, P, ld, 32, 3, 1e-15, -1, it, be, sf, inf) == -13
+    assert f(1, n, r, P, ld, P, ld, P, ld, 32, 3, 1e-15, 10, None, be, sf, inf) == -14
+    big = (ctypes.c_int * 1)(2000)
+    assert f(1, big, r, P, big, P, big, P, big, 32, 3, 1e-15, 10, it, be, sf, inf) == 1003
+    assert f(0, None, None, None, None, None, None, None, None, 32, 3, 1e-15, 10, None, None,
+             None, None) == 0
