@@ -7,22 +7,30 @@ on INT8 MFMA, and the fused FP64 recombination.  Default workload: the
 emulated-DGEMM sweep's largest square size m = n = k = 16384, entries
 a = u exp(phi g) with phi = 1, at the full slice count s = 9 (at phi <= 1
 nine slices keep the normwise error against a double-double product below
-1e-15; the error is measured on a sampled block every run).  value = 2 m n k / (seconds per step) / 1e12 in FP64-equivalent
-TFLOP/s.
+1e-15; the error is measured on a sampled block every run).
+value = 2 m n k / (seconds per step) / 1e12 in FP64-equivalent TFLOP/s.
 
-Printed on one JSON line, beside value: the slice-product kernel's roofline
-(INT8 MFMA operations per launch over its event-timed duration, against the
-dense INT8 peak), the CPU oracle timed on a bounded sample of the same
-product (and the sampled block checked bit for bit), the normwise error of
-that block against a double-double reference, the slice-count sweep (s = 3..8
-on the same inputs: kernel time, INT8 rate, and each count's error on the
-double-double block), native FP64 DGEMM and LU
-(torch / ROCm libraries) on the same GPU, and the LU solves: the plain
-method (n = 1024, 7 slices), the precision form (n = 8192, reduced slices
-plus FP64 refinement to a backward error of 1e-15, against native FP64 with
-and without refinement), the batched form (2000 uneven systems) and the
-learned slice count (an MLP trained on tiles of emulated LUs, then one
-n = 16384 solve with its per-tile counts; --no-learned skips it).
+Printed on one JSON line, beside value:
+  * the slice-product kernel's roofline (INT8 MFMA operations per launch over
+    its event-timed duration, against the dense INT8 peak);
+  * the CPU oracle timed on a bounded sample of the same product (and the
+    sampled block checked bit for bit), the block's normwise error against a
+    double-double reference;
+  * the slice-count sweep s = 3..8 on the same inputs (kernel time, INT8
+    rate, error on the double-double block), and for phi = 4 and 10 the
+    errors at s = 9..16 next to native FP64's;
+  * native FP64 DGEMM on the same GPU;
+  * the LU solves: the plain method (n = 1024, 7 slices); the precision form
+    (n = 8192, 16384, 32768; scaled and randsvd condition numbers; reduced
+    slices plus FP64 refinement to a backward error of 1e-15, against native
+    FP64 with and without refinement); the batched form (2000 uneven systems:
+    the plain batched solve and the batched precision form, against native
+    solves looped and in padded batches);
+  * the blocking-factor study (n = 16384, nb = 256..2048, with and without
+    pivoting, emulated against native FP64 updates in the same LU code) and
+    the Cholesky variant over nb;
+  * the learned slice count (an MLP trained on tiles of emulated LUs, then
+    one n = 16384 solve with its per-tile counts; --no-learned skips it).
 """
 from __future__ import annotations
 
@@ -109,6 +117,57 @@ def _native_refined(torch, At, bt, tol, maxiter=5):
     return x
 
 
+def _gpu_matrix(torch, n, phi, kappa, seed, variant):
+    """Seeded synthetic matrix generated on the GPU (n up to 32768 in
+    seconds): variant "scaled": D_r (G + sigma I) D_c with G = u exp(phi g)
+    (u ~ U(-1,1), g ~ N(0,1)), sigma = 2 sqrt(n) rms(G) and log-spaced row and
+    column scalings spanning sqrt(kappa) each; "randsvd": H_u diag(sigma) H_v
+    with sigma geometric from 1 to 1/kappa and two random Householder
+    reflectors; "dominant": G + sigma I (no scaling).  Column-major view."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1000003 * seed + 17)
+    if variant in ("scaled", "dominant"):
+        A = torch.rand((n, n), generator=g, dtype=torch.float64, device="cuda")
+        A.mul_(2.0).sub_(1.0)
+        if phi != 0.0:
+            A.mul_(torch.exp(phi * torch.randn((n, n), generator=g, dtype=torch.float64,
+                                               device="cuda")))
+        sigma = 2.0 * (n ** 0.5) * float(A.square().mean().sqrt())
+        A.diagonal().add_(sigma)
+        if variant == "scaled":
+            half = 0.5 * float(np.log10(kappa))
+            dr = torch.logspace(0.0, -half, n, dtype=torch.float64, device="cuda")
+            dc = torch.logspace(0.0, -half, n, dtype=torch.float64, device="cuda")
+            dr = dr[torch.randperm(n, generator=g, device="cuda")]
+            dc = dc[torch.randperm(n, generator=g, device="cuda")]
+            A.mul_(dc[:, None]).mul_(dr[None, :])   # storage is A^T: rows of storage = columns
+        return A.t()
+    if variant == "randsvd":
+        sig = torch.logspace(0.0, -float(np.log10(kappa)), n, dtype=torch.float64, device="cuda")
+        u = torch.randn(n, generator=g, dtype=torch.float64, device="cuda")
+        v = torch.randn(n, generator=g, dtype=torch.float64, device="cuda")
+        # (I - 2uu^T/u'u) diag(sig) (I - 2vv^T/v'v), formed in O(n^2)
+        M = torch.diag(sig)
+        w = (2.0 / float(u @ u)) * (u @ M)          # u^T M
+        M.sub_(torch.outer(u, w))
+        z = (2.0 / float(v @ v)) * (M @ v)
+        M.sub_(torch.outer(z, v))
+        return M.t().contiguous().t()
+    raise ValueError(variant)
+
+
+def _sampled_eta(oracle, torch, A, x, b, rows):
+    """Backward error with the residual of the sampled rows in double-double
+    and ||A||_inf, ||x||_inf, ||b||_inf over the whole system: each sampled
+    A x - b is one Dot2 evaluation of [A_i, b_i] . [x; -1] (the oracle's
+    double-double product, rounded once)."""
+    Ab = np.asfortranarray(np.hstack([A[rows].cpu().numpy(), b[rows].cpu().numpy()]))
+    xe = np.asfortranarray(np.vstack([x.cpu().numpy(), [[-1.0]]]))
+    r = oracle.dgemm_dd(Ab, xe)
+    nA = float(A.abs().sum(dim=1).max())
+    return float(np.abs(r).max() / (nA * float(x.abs().max()) + float(b.abs().max())))
+
+
 def bench_solvers(args, emu, torch, matgen):
     """Plain-method LU, precision form and batched form, each next to native
     FP64 on the same GPU; backward errors from the oracle's double-double
@@ -152,43 +211,63 @@ def bench_solvers(args, emu, torch, matgen):
         out["plain_n1024"]["native_eta"] = oracle.backward_error(Al, xn.cpu().numpy(), bl)
     log(f"plain n=1024: emu {t_plain:.2f} ms, emu+IR {t_ir:.2f} ms, native {t_nat:.2f} ms")
 
-    # precision form: n = lu_n, phi = 1 entries, diagonal scaling for kappa,
-    # reduced slices + FP64 refinement to 1e-15, vs native (+ refinement)
-    if args.lu_n > 0:
-        n = args.lu_n
-        res = []
-        # panel width: 256, or 512 from n = 32768 on (measured faster there:
-        # 379 against 415 ms for the s = 3 factorization)
+    # precision form (n in {8192, 16384, 32768}): reduced slices + FP64
+    # refinement to 1e-15 against native FP64 LU with and without the same
+    # refinement.  "scaled": diagonal scalings give the condition number
+    # (absorbed by the per-line exponents); "randsvd": a genuinely
+    # ill-conditioned matrix (singular values 1..1/kappa).
+    sizes = [int(v) for v in args.lu_sizes.split(",") if v]
+    runs = []
+    for n in sizes:
         nb_p = 512 if n >= 32768 else 256
-        for kappa, s_lo, nb in ((1e2, 3, nb_p), (1e6, 4, nb_p), (1e10, 5, nb_p)):
-            A = matgen.kappa_matrix(n, 1.0, kappa, seed=0, variant="scaled")
-            b = matgen.uniform(n, 1, seed=0, substream=1)
-            Ag2, bg2 = emu.colmajor(A), emu.colmajor(b)
-            t_e = _time(torch, lambda: emu.dgesv_ir(Ag2, bg2, nb=nb, nslices=s_lo, tol=tol),
-                        reps=2)
-            X, inf = emu.dgesv_ir(Ag2, bg2, nb=nb, nslices=s_lo, tol=tol)
-            At2, bt2 = Ag2.contiguous(), bg2.contiguous()
-            t_n = _time(torch, lambda: _native_solve(torch, At2, bt2), reps=2)
-            t_nr = _time(torch, lambda: _native_refined(torch, At2, bt2, tol), reps=2)
-            xn = _native_solve(torch, At2, bt2)
-            xr = _native_refined(torch, At2, bt2, tol)
-            entry = {"kappa": kappa, "nslices": s_lo, "nb": nb,
-                     "emulated_ir_ms": round(t_e, 2), "iters": inf["iters"],
-                     "s_final": inf["s_final"], "berr_fp64": inf["berr"],
-                     "native_ms": round(t_n, 2), "native_refined_ms": round(t_nr, 2),
-                     "speedup_vs_native_refined": round(t_nr / t_e, 3)}
-            if oracle is not None:
-                entry["eta_dd"] = oracle.backward_error(A, X.cpu().numpy(), b)
-                entry["native_eta_dd"] = oracle.backward_error(A, xn.cpu().numpy(), b)
-                entry["native_refined_eta_dd"] = oracle.backward_error(A, xr.cpu().numpy(), b)
-            res.append(entry)
-            log(f"precision n={n} kappa={kappa:.0e} s={s_lo}: emu+IR {t_e:.1f} ms "
-                f"({inf['iters']} steps), native {t_n:.1f} ms, native+IR {t_nr:.1f} ms")
-            del Ag2, bg2, At2, bt2
-            torch.cuda.empty_cache()
-        out["precision_form"] = {"n": n, "workload": "A = D_r (G + sigma I) D_c, G phi=1 "
-                                 "entries, log-spaced diagonal scalings, 1 RHS U(-1,1), "
-                                 "tol 1e-15", "runs": res}
+        if n >= 32768:
+            runs += [(n, nb_p, "scaled", 1e2, 0.0, 3), (n, nb_p, "scaled", 1e6, 4.0, 4),
+                     (n, nb_p, "randsvd", 1e2, 0.0, 3), (n, nb_p, "randsvd", 1e10, 0.0, 5)]
+        else:
+            runs += [(n, nb_p, "scaled", 1e2, 1.0, 3), (n, nb_p, "scaled", 1e10, 1.0, 5),
+                     (n, nb_p, "randsvd", 1e6, 0.0, 4)]
+    res = []
+    g_rows = matgen.rng(args.seed, 98)
+    for ri, (n, nb, variant, kappa, phi, s_lo) in enumerate(runs):
+        Ag2 = _gpu_matrix(torch, n, phi, kappa, args.seed + ri, variant)
+        gb = torch.Generator(device="cuda")
+        gb.manual_seed(7 + ri)
+        bg2 = (torch.rand((1, n), generator=gb, dtype=torch.float64, device="cuda") * 2 - 1).t()
+        torch.cuda.synchronize()
+        reps = 1 if n >= 32768 else 2
+        t_e = _time(torch, lambda: emu.dgesv_ir(Ag2, bg2, nb=nb, nslices=s_lo, tol=tol),
+                    reps=reps)
+        X, inf = emu.dgesv_ir(Ag2, bg2, nb=nb, nslices=s_lo, tol=tol)
+        At2, bt2 = Ag2.contiguous(), bg2.contiguous()
+        t_n = _time(torch, lambda: _native_solve(torch, At2, bt2), reps=reps)
+        t_nr = _time(torch, lambda: _native_refined(torch, At2, bt2, tol), reps=reps)
+        xn = _native_solve(torch, At2, bt2)
+        xr = _native_refined(torch, At2, bt2, tol)
+        entry = {"n": n, "variant": variant, "kappa": kappa, "phi": phi, "nslices": s_lo,
+                 "nb": nb, "emulated_ir_ms": round(t_e, 2), "iters": inf["iters"],
+                 "s_final": inf["s_final"], "berr_fp64": inf["berr"],
+                 "native_ms": round(t_n, 2), "native_refined_ms": round(t_nr, 2),
+                 "speedup_vs_native_refined": round(t_nr / t_e, 3)}
+        if oracle is not None:
+            rows = np.sort(g_rows.choice(n, size=256, replace=False))
+            rows_d = torch.as_tensor(rows, device="cuda")
+            entry["eta_dd_sampled_rows"] = _sampled_eta(oracle, torch, Ag2, X, bg2, rows_d)
+            entry["native_eta_dd_sampled_rows"] = _sampled_eta(oracle, torch, Ag2, xn, bg2,
+                                                               rows_d)
+            entry["native_refined_eta_dd_sampled_rows"] = _sampled_eta(oracle, torch, Ag2, xr,
+                                                                       bg2, rows_d)
+        res.append(entry)
+        log(f"precision n={n} {variant} kappa={kappa:.0e} phi={phi} s={s_lo}: emu+IR "
+            f"{t_e:.1f} ms ({inf['iters']} steps, s_final {inf['s_final']}), native "
+            f"{t_n:.1f} ms, native+IR {t_nr:.1f} ms")
+        del Ag2, bg2, At2, bt2, X, xn, xr
+        torch.cuda.empty_cache()
+    if res:
+        out["precision_form"] = {"workload": "scaled: D_r (G + sigma I) D_c, G = u exp(phi g); "
+                                 "randsvd: H_u diag(1..1/kappa) H_v; 1 RHS U(-1,1); tol 1e-15; "
+                                 "generated on the GPU from seeded torch generators; eta_dd "
+                                 "over 256 sampled rows in double-double",
+                                 "runs": res}
 
     # batched form: count systems, n ~ U{64..1024}, phi ~ U(0,4), 1-8 RHS
     if args.batch_count > 0:
@@ -222,20 +301,165 @@ def bench_solvers(args, emu, torch, matgen):
             for a, b in zip(As, Bs):
                 torch.linalg.solve(a, b)
         t_nl = _time(torch, native_loop, reps=1)
+        # batched precision form: refinement of every system to 1e-15
+        s_ir = 5
+
+        def batched_ir():
+            return emu.dgesv_batched_ir(As, Bs, nb=32, nslices=s_ir, tol=tol)
+        t_bir = _time(torch, batched_ir, reps=2)
+        Xir, inf_ir = batched_ir()
+        # native, batched: each system padded to [[A, 0], [0, I]] of the next
+        # multiple of 64 and factored in batches per padded size (chunks of 64)
+        classes = {}
+        for i, (n, phi, r) in enumerate(specs):
+            classes.setdefault((n + 63) // 64 * 64, []).append(i)
+        padded = []
+        for N, idx in sorted(classes.items()):
+            for c0 in range(0, len(idx), 64):
+                ids = idx[c0:c0 + 64]
+                Ap = torch.zeros(len(ids), N, N, dtype=torch.float64, device="cuda")
+                Bp = torch.zeros(len(ids), N, 8, dtype=torch.float64, device="cuda")
+                for k, i in enumerate(ids):
+                    n, r = specs[i][0], specs[i][2]
+                    Ap[k, :n, :n] = As[i]
+                    Ap[k, n:, n:] = torch.eye(N - n, dtype=torch.float64, device="cuda")
+                    Bp[k, :n, :r] = Bs[i]
+                padded.append((Ap, Bp))
+
+        def native_padded():
+            for Ap, Bp in padded:
+                LU, piv = torch.linalg.lu_factor(Ap)
+                torch.linalg.lu_solve(LU, piv, Bp)
+        try:
+            t_np = _time(torch, native_padded, reps=2)
+        except RuntimeError as e:           # reported, not fatal
+            t_np = None
+            log(f"native padded batches failed: {e}")
+        del padded
+        its = np.array(inf_ir["iters"])
         entry = {"count": args.batch_count, "nslices": s_b, "nb": 32,
                  "emulated_ms": round(tb, 2), "tflops_equiv": round(flops / tb / 1e9, 2),
+                 "refined": {"nslices": s_ir, "ms": round(t_bir, 2), "rc": inf_ir["rc"],
+                             "berr_fp64_max": max(inf_ir["berr"]),
+                             "iters_max": int(its.max()),
+                             "iters_mean": round(float(its.mean()), 3),
+                             "s_final_counts": np.bincount(inf_ir["s_final"]).tolist()},
                  "native_looped_ms": round(t_nl, 2),
+                 "native_padded_batched_ms": None if t_np is None else round(t_np, 2),
+                 "speedup_refined_vs_native_padded": None if t_np is None
+                 else round(t_np / t_bir, 3),
                  "workload": "n ~ U{64..1024}, phi ~ U(0,4), nrhs ~ U{1..8}, seed 0"}
         if not args.no_cpu:
-            worst = 0.0
+            worst = worst_ir = 0.0
             for i in range(0, len(specs), max(1, len(specs) // 16)):
                 n, phi, r = specs[i]
                 A = matgen.phi_matrix(n, n, phi, seed=0, substream=1000 + i)
                 B = matgen.uniform(n, r, seed=0, substream=5000 + i)
                 worst = max(worst, oracle.backward_error(A, Bw[i].cpu().numpy(), B))
+                worst_ir = max(worst_ir, oracle.backward_error(A, Xir[i].cpu().numpy(), B))
             entry["max_eta_dd_sampled"] = worst
+            entry["refined"]["max_eta_dd_sampled"] = worst_ir
         out["batched"] = entry
-        log(f"batched {args.batch_count} systems: {tb:.1f} ms, native looped {t_nl:.1f} ms")
+        log(f"batched {args.batch_count} systems: {tb:.1f} ms (s={s_b}), refined to 1e-15 "
+            f"{t_bir:.1f} ms (s={s_ir}); native looped {t_nl:.1f} ms, padded batches {t_np} ms")
+    return out
+
+
+def bench_blocking(args, emu, torch, matgen):
+    """Blocking-factor study (the performance section's LU over blocking
+    factors 256..2048, with and without pivoting): the same LU code with the
+    emulated Schur update (s = 3 and 7) and with a native FP64 one (rocBLAS),
+    n = sweep_n, a diagonally dominant phi = 1 matrix (so that the LU without
+    interchanges is stable too); the eqn (9) scaled residual of each solve;
+    rocSOLVER's own LU as a reference.  Then the Cholesky variant on an SPD
+    matrix of the same size over nb, against rocBLAS dsyrk updates and
+    torch's Cholesky."""
+    n = args.sweep_n
+    A = _gpu_matrix(torch, n, 1.0, 1.0, args.seed + 50, "dominant")
+    gb = torch.Generator(device="cuda")
+    gb.manual_seed(51)
+    b = (torch.rand((1, n), generator=gb, dtype=torch.float64, device="cuda") * 2 - 1).t()
+    rows = []
+    for pivot in (1, 0):
+        for nb in (256, 512, 768, 1024, 1280, 1536, 2048):
+            row = {"pivot": bool(pivot), "nb": nb}
+            for name, s, native in (("emu_s3", 3, 0), ("emu_s7", 7, 0), ("native", 9, 1)):
+                emu.set_param("lu_pivot", pivot)
+                emu.set_param("lu_update", native)
+                try:
+                    W = A.clone()
+                    holder = {}
+
+                    def fac():
+                        W.copy_(A)
+                        holder["f"] = emu.dgetrf(W, nb=nb, nslices=s)
+                    t = _time(torch, fac, reps=1)
+                    ipiv, info = holder["f"]
+                    x = b.clone()
+                    emu.dgetrs(W, ipiv, x)
+                    sr = emu.scaled_residual(A, x, b)
+                finally:
+                    emu.set_param("lu_pivot", 1)
+                    emu.set_param("lu_update", 0)
+                row[name] = {"ms": round(t, 2), "tflops_equiv": round(2 / 3 * n ** 3 / t / 1e9, 2),
+                             "scaled_residual": sr, "info": int(info.item())}
+                del W, x
+            row["speedup_s7_vs_native_update"] = round(row["native"]["ms"] / row["emu_s7"]["ms"], 3)
+            rows.append(row)
+            log(f"blocking n={n} pivot={pivot} nb={nb}: emu s=3 {row['emu_s3']['ms']:.1f} ms, "
+                f"s=7 {row['emu_s7']['ms']:.1f} ms, native update {row['native']['ms']:.1f} ms")
+    At = A.contiguous()
+    t_rs = _time(torch, lambda: torch.linalg.lu_factor(At), reps=1)
+    try:
+        t_rs_np = _time(torch, lambda: torch.linalg.lu_factor_ex(At, pivot=False), reps=1)
+    except RuntimeError:
+        t_rs_np = None
+    out = {"n": n, "workload": "G + sigma I, G = u exp(g) (phi = 1), sigma = 2 sqrt(n) rms(G); "
+           "the emulated and native columns run the same panel, interchange and triangular-"
+           "solve kernels, only the trailing update differs", "runs": rows,
+           "rocsolver_getrf_ms": round(t_rs, 2),
+           "rocsolver_getrf_nopivot_ms": None if t_rs_np is None else round(t_rs_np, 2)}
+    del A, At
+    torch.cuda.empty_cache()
+    # Cholesky: S = G G^T / n + I (SPD), lower factor
+    g = torch.Generator(device="cuda")
+    g.manual_seed(52)
+    G = torch.rand((n, n), generator=g, dtype=torch.float64, device="cuda").mul_(2).sub_(1)
+    S = (G @ G.t()).div_(n)
+    S.diagonal().add_(1.0)
+    del G
+    S = S.t()
+    chol = []
+    for nb in (256, 512, 1024, 2048):
+        row = {"nb": nb}
+        facs = {}
+        for name, sl, native in (("emu_s3", 3, 0), ("emu_s7", 7, 0), ("native", 9, 1)):
+            emu.set_param("lu_update", native)
+            try:
+                W = S.clone()
+
+                def fac():
+                    W.copy_(S)
+                    emu.dpotrf(W, nb=nb, nslices=sl)
+                t = _time(torch, fac, reps=1)
+            finally:
+                emu.set_param("lu_update", 0)
+            facs[name] = W
+            row[name] = {"ms": round(t, 2), "tflops_equiv": round(n ** 3 / 3 / t / 1e9, 2)}
+        Ln = torch.tril(facs["native"])
+        for name in ("emu_s3", "emu_s7"):
+            row[name]["rel_diff_vs_native_factor"] = float(
+                (torch.tril(facs[name]) - Ln).abs().max() / Ln.abs().max())
+        chol.append(row)
+        log(f"cholesky n={n} nb={nb}: emu s=3 {row['emu_s3']['ms']:.1f} ms, s=7 "
+            f"{row['emu_s7']['ms']:.1f} ms, native update {row['native']['ms']:.1f} ms")
+        del facs, W, Ln
+    Sc = S.contiguous()
+    t_tc = _time(torch, lambda: torch.linalg.cholesky(Sc), reps=1)
+    del S, Sc
+    torch.cuda.empty_cache()
+    out["cholesky"] = {"workload": "S = G G^T / n + I, G ~ U(-1,1)", "runs": chol,
+                       "torch_cholesky_ms": round(t_tc, 2)}
     return out
 
 
@@ -341,8 +565,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-native", action="store_true", help="skip native FP64")
     ap.add_argument("--no-lu", action="store_true", help="skip the LU solves")
-    ap.add_argument("--lu-n", type=int, default=8192,
-                    help="size of the precision-form solve (0 skips it)")
+    ap.add_argument("--lu-sizes", type=str, default="8192,16384,32768",
+                    help="sizes of the precision-form solves ('' skips them)")
     ap.add_argument("--batch-count", type=int, default=2000,
                     help="systems in the batched solve (0 skips it)")
     ap.add_argument("--sweep-s", type=str, default="3,4,5,6,7,8",
@@ -353,6 +577,10 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first "
                          "(a reference kernel of known traffic for HBM counters)")
+    ap.add_argument("--sweep-n", type=int, default=16384,
+                    help="size of the blocking-factor and Cholesky study (0 skips it)")
+    ap.add_argument("--phi-sweep", type=str, default="4,10",
+                    help="phi values of the slice-count accuracy study at s = 9..16 ('' skips)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned slice-count leg (training on n = 8192 and "
                          "16384 emulated LUs, evaluation on an n = 16384 solve)")
@@ -601,9 +829,64 @@ def main():
     del Ag, Bg, Cg
     torch.cuda.empty_cache()
 
+    # ------------------------------- accuracy at wide dynamic range, s >= 9
+    # phi = 4 and 10 at m = n = k = n: the slice count each needs for a
+    # normwise error of 1e-15 against the double-double product (or for the
+    # error of native FP64 where that is larger), on a 16 x 2048 block
+    phis = [float(v) for v in args.phi_sweep.split(",") if v]
+    if phis:
+        acc = []
+        for pi, ph in enumerate(phis):
+            g2 = torch.Generator(device="cuda")
+            g2.manual_seed(4242 + pi)
+
+            def phi_mat():
+                M = torch.rand((n, n), generator=g2, dtype=torch.float64, device="cuda")
+                M.mul_(2.0).sub_(1.0).mul_(torch.exp(
+                    ph * torch.randn((n, n), generator=g2, dtype=torch.float64, device="cuda")))
+                return M.t()
+            Ap, Bp = phi_mat(), phi_mat()
+            Cp = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+            ref_dd = None
+            if not args.no_cpu:
+                import oracle
+                ref_dd = oracle.dgemm_dd(np.asfortranarray(Ap[r2_d].cpu().numpy()),
+                                         np.asfortranarray(Bp[:, cols_d].cpu().numpy()))
+                nat = (Ap[r2_d].contiguous() @ Bp[:, cols_d].contiguous()).cpu().numpy()
+            row = {"phi": ph, "runs": []}
+            if ref_dd is not None:
+                row["eta_F_native_fp64_vs_dd"] = oracle.rel_err_fro(nat, ref_dd)
+            for s3 in (9, 10, 11, 12, 14, 16):
+                emu.dgemm(Ap, Bp, Cp, nslices=s3)
+                torch.cuda.synchronize()
+                emu.emu_profile_start()
+                emu.dgemm(Ap, Bp, Cp, nslices=s3)
+                torch.cuda.synchronize()
+                emu.emu_profile_stop()
+                gm, gc = emu.profile_read(emu.PROF_GEMM)
+                sm, sc = emu.profile_read(emu.PROF_SLICE)
+                ent = {"s": s3, "products": pairs(s3, s3 + 1), "gemm_ms": round(gm / gc, 3),
+                       "step_ms": round(gm / gc + sm / max(sc, 1), 3)}
+                if ref_dd is not None:
+                    blk = Cp[r2_d][:, cols_d].cpu().numpy()
+                    ent["eta_F_vs_dd"] = oracle.rel_err_fro(blk, ref_dd)
+                    ent["meets_1e-15_or_native"] = bool(
+                        ent["eta_F_vs_dd"] <= max(1e-15, row["eta_F_native_fp64_vs_dd"]))
+                row["runs"].append(ent)
+                log(f"phi={ph} s={s3}: {ent['gemm_ms']:.1f} ms, eta_F "
+                    f"{ent.get('eta_F_vs_dd', float('nan')):.2e}")
+            acc.append(row)
+            del Ap, Bp, Cp
+            torch.cuda.empty_cache()
+        result["phi_accuracy"] = {"m=n=k": n, "block": f"{len(r2)}x{len(cols)}",
+                                  "inputs": "u exp(phi g) generated on the GPU (seeded)",
+                                  "rows": acc}
+
     # ------------------------------------------------------------ solvers
     if not args.no_lu:
         result["lu_solve"] = bench_solvers(args, emu, torch, matgen)
+    if not args.no_lu and args.sweep_n > 0:
+        result["blocking"] = bench_blocking(args, emu, torch, matgen)
     if not args.no_lu and not args.no_learned:
         try:
             result["learned_form"] = bench_learned(args, emu, torch, matgen)
