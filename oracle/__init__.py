@@ -30,8 +30,12 @@ Parity status of each function (what pins it, in tests/test_oracle_pins.py):
                                   distribution; central finite differences
   learned.adam_step             - first-step closed form (lr * sign(g))
   learned.decode                - hand-built cumulative distributions
-  learned.tile_labels           - small-integer inputs are exact at s = 3
-  learned.getrf_tiles           - a constant slice map equals getrf
+  learned.tile_labels           - integer tiles of known digit counts:
+                                  labels max(a + b - 1, s_lo) in closed
+                                  form (several counts in one call)
+  learned.getrf_tiles           - a constant slice map equals getrf; a one-
+                                  slice tile leaves its backward error in
+                                  that tile's columns only
 (pins of the learned part: tests/test_learned_oracle.py)
 """
 from .emu import (  # noqa: F401

@@ -83,3 +83,65 @@ def test_tiled_lu_reduces_to_plain_lu_with_a_constant_map():
         LU, piv, _ = OL.getrf_tiles(A, nb, [np.full(t, s) for t in steps])
         LU2, piv2, _ = O.getrf(A, nb=nb, s=s)
         assert np.array_equal(piv, piv2) and np.array_equal(LU, LU2)
+
+
+def test_labels_follow_the_digit_counts_of_integer_tiles():
+    # Tile-row I of L21 holds integers below 2^(7 a_I) with one entry at
+    # 2^(7 a_I) - 1 (so its rows need exactly a_I digits), tile-column J of
+    # U12 integers below 2^(7 b_J) likewise.  The emulated product of such a
+    # tile is exact exactly from s = a_I + b_J - 1 on (all pairs i <= a_I,
+    # j <= b_J lie under t = s + 1, and the pair (a_I, b_J) is dropped one
+    # count below), so with tau = 0 the label is max(a_I + b_J - 1, s_lo).
+    a = [1, 2, 3]
+    b = [3, 1]
+    k = 20
+    g = np.random.default_rng(12)
+    rows = [256, 256, 100]
+    cols = [256, 200]
+    L21 = np.vstack([g.integers(-(2 ** (7 * ai)) + 1, 2 ** (7 * ai), size=(r, k))
+                     for ai, r in zip(a, rows)]).astype(np.float64)
+    U12 = np.hstack([g.integers(-(2 ** (7 * bj)) + 1, 2 ** (7 * bj), size=(k, c))
+                     for bj, c in zip(b, cols)]).astype(np.float64)
+    r0 = 0
+    for ai, r in zip(a, rows):
+        L21[r0:r0 + r, 0] = 2.0 ** (7 * ai) - 1
+        r0 += r
+    c0 = 0
+    for bj, c in zip(b, cols):
+        U12[0, c0:c0 + c] = 2.0 ** (7 * bj) - 1
+        c0 += c
+    L21, U12 = np.asfortranarray(L21), np.asfortranarray(U12)
+    lab = OL.tile_labels(L21, U12, s_lo=1, s_hi=9, tau=0.0)
+    want = [max(a[I] + b[J] - 1, 1) for J in range(2) for I in range(3)]
+    assert list(lab) == want
+    assert len(set(want)) >= 4          # the labels span several counts
+
+
+def test_tiled_lu_puts_a_tile_error_where_the_map_says():
+    # Step 0 updates a 800 x 500 trailing block (4 x 2 tiles of 256).  Only
+    # tile (I, J) = (3, 0) gets one slice (error near 2^-7 of its entries),
+    # every other tile and every later step nine.  Blocked elimination keeps
+    # each update's error where it was made: PA - LU is large in the columns
+    # of that tile (100 .. 355) and at rounding level elsewhere, so an index
+    # that mixes up I and J (q = J + I tn gives tile (1, 1), columns 356 ..)
+    # would show it.
+    m, n, nb = 900, 600, 100
+    A = np.array(matgen.phi_matrix(m, n, 0.5, seed=13), order="F")
+    smaps = []
+    for j1 in range(nb, min(m, n), nb):
+        tm, tn = -(-(m - j1) // 256), -(-(n - j1) // 256)
+        smaps.append(np.full(tm * tn, 9))
+    assert len(smaps[0]) == 8
+    smaps[0][3 + 0 * 4] = 1
+    LU, piv, info = OL.getrf_tiles(A, nb, smaps)
+    assert info == 0
+    PA = A.copy()
+    for c in range(min(m, n)):
+        p = int(piv[c]) - 1
+        if p != c:
+            PA[[c, p], :] = PA[[p, c], :]
+    L = np.tril(LU, -1)[:, :n] + np.eye(m, n)
+    U = np.triu(LU)[:n, :]
+    E = np.abs(PA - L @ U).max(axis=0) / np.abs(A).max()
+    inside, outside = E[100:356], np.concatenate([E[:100], E[356:]])
+    assert inside.max() > 1e-6 and outside.max() < 1e-12
