@@ -113,19 +113,23 @@ def slice_digits(X: np.ndarray, e: np.ndarray, bad: np.ndarray, s: int,
 
 
 def slice_products(QA: np.ndarray, QB: np.ndarray, t: int) -> dict:
-    """D[g] = sum over i + j = g (1 <= i, j <= s) of QA[i-1] @ QB[j-1], g=2..t.
+    """D[g] = sum over i + j = g (1 <= i <= sA, 1 <= j <= sB) of
+    QA[i-1] @ QB[j-1], g = 2..t.
 
-    QA has shape (s, m, k), QB (s, k, n).  Values are exact integers stored
-    in float64 (see the module docstring for the bound that makes it so).
+    QA has shape (sA, m, k), QB (sB, k, n) (sA = sB = s in the method as the
+    paper writes it; fewer slices for one operand are the unequal splits).
+    Values are exact integers stored in float64 (see the module docstring
+    for the bound that makes it so).
     """
-    s, m, k = QA.shape
+    sa, m, k = QA.shape
+    sb = QB.shape[0]
     n = QB.shape[2]
-    pairs_max = min(s, t - 1)
+    pairs_max = min(sa, sb, t - 1)
     assert pairs_max * k * DIGIT_MAX * DIGIT_MAX < 2.0 ** 53, "slice sum bound"
     D = {}
     for g in range(2, t + 1):
         acc = np.zeros((m, n))
-        for i in range(max(1, g - s), min(s, g - 1) + 1):
+        for i in range(max(1, g - sb), min(sa, g - 1) + 1):
             j = g - i
             acc += QA[i - 1] @ QB[j - 1]
         D[g] = acc
@@ -150,11 +154,13 @@ def recombine(D: dict, t: int, e: np.ndarray, f: np.ndarray, alpha: float,
 
 
 def dgemm_emu(A, B, s: int, alpha: float = 1.0, beta: float = 0.0, C=None,
-              t: int | None = None, return_parts: bool = False):
+              t: int | None = None, return_parts: bool = False, s_b: int | None = None):
     """alpha * emul(A B) + beta * C with s slices per operand, threshold t.
 
-    Default t = s + 1.  BLAS quick returns: m = 0 or n = 0 gives C
-    unchanged; k = 0 or alpha = 0 gives beta * C (C not read when beta = 0).
+    Default t = s + 1.  s_b (default s) gives B its own slice count (unequal
+    splits, related-work section): pairs (i, j) with i <= s, j <= s_b,
+    i + j <= t.  BLAS quick returns: m = 0 or n = 0 gives C unchanged; k = 0
+    or alpha = 0 gives beta * C (C not read when beta = 0).
     """
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
@@ -175,7 +181,7 @@ def dgemm_emu(A, B, s: int, alpha: float = 1.0, beta: float = 0.0, C=None,
     e, bad_r = line_exponents(A, axis=1)
     f, bad_c = line_exponents(B, axis=0)
     QA = slice_digits(A, e, bad_r, s, axis=1)
-    QB = slice_digits(B, f, bad_c, s, axis=0)
+    QB = slice_digits(B, f, bad_c, s if s_b is None else int(s_b), axis=0)
     D = slice_products(QA, QB, t)
     out = recombine(D, t, e, f, alpha, beta, C)
     out[bad_r, :] = np.nan

@@ -437,3 +437,41 @@ def test_cholesky_against_lapack_and_symmetric_emulated_product():
     for s in (3, 9):
         P = O.dgemm_emu(X, np.asfortranarray(X.T), s)
         assert np.array_equal(P, P.T)
+
+
+# ----------------------------------------------------------- unequal splits
+
+def test_unequal_splits_reduce_products_without_changing_exact_digits():
+    # B holds integers below 2^14 with one entry of 2^14 - 1 per column, so
+    # its columns scale by 2^-14 and two 7-bit digits represent it exactly:
+    # every digit of B beyond the second is zero, and giving B two slices
+    # instead of nine leaves every diagonal sum, hence every bit, unchanged
+    # (17 slice products instead of 45)
+    g = np.random.default_rng(21)
+    B = g.integers(-(2 ** 14) + 1, 2 ** 14, size=(300, 70)).astype(np.float64)
+    B[0, :] = 2.0 ** 14 - 1
+    B = np.asfortranarray(B)
+    A = np.asfortranarray(matgen.phi_matrix(90, 300, 2.0, seed=22))
+    full = O.dgemm_emu(A, B, 9)
+    for sb in (2, 3, 5):
+        assert np.array_equal(O.dgemm_emu(A, B, 9, s_b=sb).view(np.int64), full.view(np.int64))
+    # one slice of B is too few: the second digit carries information
+    assert not np.array_equal(O.dgemm_emu(A, B, 9, s_b=1), full)
+    # s_b = s is the method itself, and the pair count is the triangle cut
+    # to s_b columns: sum over i of min(s_b, t - i)
+    assert np.array_equal(O.dgemm_emu(A, B, 9, s_b=9), full)
+    _, parts = O.dgemm_emu(A, B, 9, s_b=2, return_parts=True)
+    assert parts["QB"].shape[0] == 2
+    assert sum(min(2, 10 - i) for i in range(1, 10)) == 17
+
+
+def test_unequal_splits_exact_for_integers_against_int64():
+    # 21-bit A (three digits) times 7-bit B (one digit): exact with s = 3,
+    # s_b = 1 (pairs (1..3, 1), all under t = 4), as an int64 product says
+    g = np.random.default_rng(23)
+    A = g.integers(-(2 ** 21) + 1, 2 ** 21, size=(40, 50))
+    B = g.integers(-127, 128, size=(50, 30))
+    ref = (A @ B).astype(np.float64)
+    got = O.dgemm_emu(np.asfortranarray(A.astype(np.float64)),
+                      np.asfortranarray(B.astype(np.float64)), 3, s_b=1)
+    assert np.array_equal(got, ref)
