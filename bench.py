@@ -581,6 +581,8 @@ def main():
                     help="size of the blocking-factor and Cholesky study (0 skips it)")
     ap.add_argument("--phi-sweep", type=str, default="4,10",
                     help="phi values of the slice-count accuracy study at s = 9..16 ('' skips)")
+    ap.add_argument("--no-unequal", dest="unequal", action="store_false",
+                    help="skip the unequal-splits leg")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned slice-count leg (training on n = 8192 and "
                          "16384 emulated LUs, evaluation on an n = 16384 solve)")
@@ -828,6 +830,49 @@ def main():
         log(f"native FP64 DGEMM {nat_ms:.2f} ms")
     del Ag, Bg, Cg
     torch.cuda.empty_cache()
+
+    # --------------------------------- unequal splits (product-count reducer)
+    # B whose columns hold 14-bit integers (two 7-bit digits under per-column
+    # scaling) times the phi = 1 A: nine slices for A, two for B give the same
+    # bits as nine for both, with 17 slice products instead of 45
+    if args.unequal:
+        g3 = torch.Generator(device="cuda")
+        g3.manual_seed(777)
+        Bi = torch.randint(-(2 ** 14) + 1, 2 ** 14, (n, n), generator=g3, device="cuda",
+                           dtype=torch.int64).to(torch.float64)
+        Bi[:, 0] = 2.0 ** 14 - 1                    # storage row = column of B
+        Bi = Bi.t()
+        Ci = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+        Cf = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+        Ag2 = emu.colmajor(A)
+        res_u = {}
+        for name, kw in (("s9_full", {}), ("s9_b2", {"nslices_b": 2})):
+            out = Cf if name == "s9_full" else Ci
+            emu.dgemm(Ag2, Bi, out, nslices=s, **kw)
+            torch.cuda.synchronize()
+            emu.emu_profile_start()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                emu.dgemm(Ag2, Bi, out, nslices=s, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            emu.emu_profile_stop()
+            gm, gc = emu.profile_read(emu.PROF_GEMM)
+            step = e0.elapsed_time(e1) / 3
+            res_u[name] = {"products": pairs(s, s + 1) if not kw else
+                           sum(min(2, s + 1 - i) for i in range(1, s + 1)),
+                           "ms_per_step": round(step, 3), "gemm_ms": round(gm / gc, 3),
+                           "tflops_equiv": round(flops_equiv / (step * 1e-3) / 1e12, 2)}
+        same = bool(torch.equal(Ci.view(torch.int64), Cf.view(torch.int64)))
+        result["unequal_splits"] = {"workload": f"A phi=1 {n}x{n}, B 14-bit integers "
+                                    f"{n}x{n}, s_A = {s}", "runs": res_u,
+                                    "bit_identical_to_full_count": same}
+        log(f"unequal splits: full {res_u['s9_full']['ms_per_step']:.1f} ms, B with 2 slices "
+            f"{res_u['s9_b2']['ms_per_step']:.1f} ms, identical={same}")
+        del Bi, Ci, Cf, Ag2
+        torch.cuda.empty_cache()
 
     # ------------------------------- accuracy at wide dynamic range, s >= 9
     # phi = 4 and 10 at m = n = k = n: the slice count each needs for a

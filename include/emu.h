@@ -179,6 +179,26 @@ int emu_dgemm_noalloc(int m, int n, int k, double alpha, const double *A, int ld
                       int nslices);
 
 /*
+ * emu_dgemm_ab: emu_dgemm with unequal splits (the paper's related-work
+ * section names splits of unequal size as a way to fewer products): A is
+ * split into nslices_a slices, B into nslices_b <= nslices_a, t =
+ * nslices_a + 1, so the pairs are i <= nslices_a, j <= nslices_b, i + j <=
+ * t: sum over i of min(nslices_b, t - i) products instead of s(s+1)/2.  When
+ * every column of B is represented exactly by nslices_b digits (integers or
+ * fixed-point data below 2^(7 nslices_b) times the column's scale), the
+ * result is bit-identical to emu_dgemm with nslices_a slices.  Supported:
+ * nslices_b = nslices_a (then exactly emu_dgemm), or 1 <= nslices_b <
+ * nslices_a <= 9 with k at most the one-pass exact length for nslices_b
+ * pairs per diagonal (2^31 / (nslices_b 127^2), rounded down to 32: 14784
+ * for 9) — longer k returns EMU_ERR_UNSUPPORTED.  Scratch: at most
+ * emu_workspace_bytes(m, n, k, nslices_a).  Argument numbers as emu_dgemm,
+ * nslices_a=12, nslices_b=13.
+ */
+int emu_dgemm_ab(int m, int n, int k, double alpha, const double *A, int lda,
+                 const double *B, int ldb, double beta, double *C, int ldc, int nslices_a,
+                 int nslices_b);
+
+/*
  * emu_dgemm_t: emu_dgemm with an explicit truncation threshold t (the
  * paper's t: products A_i B_j with i + j > t are dropped).  Supported:
  * t = s + 1 for s in 1..16 and t = 2s (all s^2 products) for s in 1..5.

@@ -37,12 +37,13 @@ __all__ = [
     "colmajor", "dgemm", "dgetrf", "dgetrs", "debug_slices", "debug_products",
     "status", "emu_dgemm_noalloc", "EMU_NOALLOC_SCRATCH_BYTES",
     "emu_dpotrf", "emu_potrf_workspace_bytes", "dpotrf",
-    "emu_dgesv_batched_ir", "dgesv_batched_ir",
+    "emu_dgesv_batched_ir", "dgesv_batched_ir", "emu_dgemm_ab",
 ]
 
 EMU_MAX_SLICES = 16
 EMU_MAX_NB = 2048
 EMU_ERR_WORKSPACE = 1002
+EMU_ERR_UNSUPPORTED = 1003
 EMU_NOALLOC_SCRATCH_BYTES = 64 << 20
 EMU_ERR_NOT_CONVERGED = 1004
 EMU_ERR_PANEL_WAIT = 1005
@@ -73,6 +74,7 @@ _SIGNATURES = {
     "emu_status": ([ctypes.POINTER(_I)], _I),
     "emu_dgemm": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
     "emu_dgemm_noalloc": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I], _I),
+    "emu_dgemm_ab": ([_I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _I, _I], _I),
     "emu_dpotrf": ([_I, _P, _I, _P, _I, _I], _I),
     "emu_dgesv_batched_ir": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I, _D, _I, _P, _P, _P,
                               _P], _I),
@@ -144,6 +146,7 @@ emu_getrs_workspace_bytes = _raw("emu_getrs_workspace_bytes")
 emu_status = _raw("emu_status")
 emu_dgemm = _raw("emu_dgemm")
 emu_dgemm_noalloc = _raw("emu_dgemm_noalloc")
+emu_dgemm_ab = _raw("emu_dgemm_ab")
 emu_dpotrf = _raw("emu_dpotrf")
 emu_dgesv_batched_ir = _raw("emu_dgesv_batched_ir")
 emu_potrf_workspace_bytes = _raw("emu_potrf_workspace_bytes")
@@ -228,8 +231,9 @@ def _mat(t, name):
     return t.data_ptr(), max(ld, 1)
 
 
-def dgemm(A, B, C=None, alpha=1.0, beta=0.0, nslices=7, t=None):
-    """C <- alpha * emul(A @ B) + beta * C (column-major float64 tensors)."""
+def dgemm(A, B, C=None, alpha=1.0, beta=0.0, nslices=7, t=None, nslices_b=None):
+    """C <- alpha * emul(A @ B) + beta * C (column-major float64 tensors).
+    nslices_b: B's own slice count (unequal splits, emu_dgemm_ab)."""
     torch = _torch()
     m, k = A.shape
     k2, n = B.shape
@@ -243,7 +247,12 @@ def dgemm(A, B, C=None, alpha=1.0, beta=0.0, nslices=7, t=None):
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
     _bind_stream()
-    if t is None:
+    if nslices_b is not None:
+        if t is not None:
+            raise EmuError("dgemm: nslices_b takes t = nslices + 1")
+        rc = emu_dgemm_ab(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                          int(nslices), int(nslices_b))
+    elif t is None:
         rc = emu_dgemm(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
                        int(nslices))
     else:

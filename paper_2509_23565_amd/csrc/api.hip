@@ -610,6 +610,45 @@ int emu_dgemm_noalloc(int m, int n, int k, double alpha, const double *A, int ld
                      t, nullptr, false);
 }
 
+int emu_dgemm_ab(int m, int n, int k, double alpha, const double *A, int lda,
+                 const double *B, int ldb, double beta, double *C, int ldc, int nslices_a,
+                 int nslices_b) {
+    const int s = nslices_a, sb = nslices_b;
+    int bad = check_gemm_args(m, n, k, A, lda, B, ldb, C, ldc, s, s + 1, alpha);
+    if (bad) {
+        set_error("emu_dgemm_ab: argument %d invalid", -bad);
+        return bad;
+    }
+    if (sb < 1 || sb > s) {
+        set_error("emu_dgemm_ab: argument 13 invalid");
+        return -13;
+    }
+    if (sb == s)
+        return dgemm_impl(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, s + 1, nullptr);
+    if (s > 9) {
+        set_error("emu_dgemm_ab: unequal splits need nslices_a <= 9");
+        return EMU_ERR_UNSUPPORTED;
+    }
+    if (m == 0 || n == 0) return 0;
+    const bool quick = k == 0 || alpha == 0.0;
+    GemmScratch g = gemm_scratch(m, n, k, s, s + 1);
+    Call c;
+    EMU_TRY(c.begin(quick ? 0 : g.total));
+    if (quick) return scale_c(C, ldc, m, n, beta, c.st);
+    int *codeA = reinterpret_cast<int *>(c.ws + g.off_codeA);
+    int *codeB = reinterpret_cast<int *>(c.ws + g.off_codeB);
+    int8_t *pa = reinterpret_cast<int8_t *>(c.ws + g.off_pa);
+    int8_t *pb = reinterpret_cast<int8_t *>(c.ws + g.off_pb);
+    ProfScope ps(EMU_PROF_SLICE, c.st);
+    EMU_TRY(launch_slice(A, lda, 1, g.ga, s, codeA, pa, c.dev->status, c.st));
+    EMU_TRY(launch_slice(B, ldb, 0, g.gb, sb, codeB, pb, c.dev->status, c.st));
+    EMU_TRY(ps.close());
+    ProfScope pg(EMU_PROF_GEMM, c.st);
+    EMU_TRY(launch_slicegemm_ab(pa, g.ga, pb, g.gb, codeA, codeB, m, n, k, s, sb, alpha, beta,
+                                C, ldc, c.st));
+    return pg.close();
+}
+
 int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
                 const double *B, int ldb, double beta, double *C, int ldc,
                 int nslices, int t) {

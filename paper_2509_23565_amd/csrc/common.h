@@ -219,6 +219,11 @@ int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
                      double beta, double *C, long long ldc, int64_t *Dout,
                      int32_t *ws_part, hipStream_t stream, bool lower = false);
 bool gemm_supported(int s, int t);
+// Unequal splits: A with s slices (2..9), B with sb (1..s-1) slices, t = s + 1,
+// K within one exact pass (EMU_ERR_UNSUPPORTED otherwise).
+int launch_slicegemm_ab(const int8_t *Ap, const Planes &ga, const int8_t *Bp, const Planes &gb,
+                        const int *codeA, const int *codeB, int m, int n, int k, int s, int sb,
+                        double alpha, double beta, double *C, long long ldc, hipStream_t stream);
 // Many problems of one (s, t = s + 1) in one persistent launch: probs[q]
 // (device) holds problem q with tiles_m/tiles_n set by gemm_tile_counts;
 // tile_prefix (device, nprob + 1) is the running sum of tiles_m * tiles_n.

@@ -76,11 +76,20 @@ __host__ __device__ constexpr int diag_pairs(int s, int g) {
     return hi >= lo ? hi - lo + 1 : 0;
 }
 
-// Pairs per slot at most: s (plain), s - 1 (split longest diagonal).
-static int max_slot_pairs(int s, int t, bool split) {
+// Pairs (i <= s, j <= sb) on diagonal g.
+static int diag_pairs_ab(int s, int sb, int g) {
+    const int lo = g - sb > 1 ? g - sb : 1;
+    const int hi = g - 1 < s ? g - 1 : s;
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// Pairs per slot at most: s (plain), s - 1 (split longest diagonal); B with
+// sb slices: at most sb.
+static int max_slot_pairs(int s, int t, bool split, int sb = 0) {
+    if (sb <= 0) sb = s;
     int m = 0;
     for (int g = 2; g <= t; ++g) {
-        int p = diag_pairs(s, g);
+        int p = diag_pairs_ab(s, sb, g);
         if (split && g == t) p = (p + 1) / 2;
         if (p > m) m = p;
     }
@@ -93,8 +102,11 @@ static long long exact_len(int pairs) {
     return L / K_BLOCK * K_BLOCK;
 }
 
-template <int S, int T, bool SPLIT>
+template <int S, int T, bool SPLIT, int SB = S>
 struct Cfg {
+    // SB: B's slice count (unequal splits, SB < S: B digits beyond SB are
+    // not there, so pairs (i, j) have j <= SB)
+    static_assert(SB >= 1 && SB <= S && (SB == S || (!SPLIT && T == S + 1)), "unequal splits");
     static constexpr int NSLOT = (T - 1) + (SPLIT ? 1 : 0);
     // wave tile WM x WN blocks of 32x32; workgroup WAVES_M x WAVES_N waves.
     // Two 32x32 blocks per wave while the accumulators fit two waves per
@@ -112,7 +124,7 @@ struct Cfg {
     static constexpr int TM = WAVES_M * WM;     // 32-row blocks per tile
     static constexpr int TN = WAVES_N * WN;     // 32-column blocks per tile
     static constexpr int FRA = S * TM;
-    static constexpr int FRB = S * TN;
+    static constexpr int FRB = SB * TN;
     static constexpr int FR = FRA + FRB;        // fragments per K step
     // LDS stages (K steps in flight).  With S <= 3 a K step is too short
     // (12 MFMAs per wave at S = 3) to cover the latency of its fragment
@@ -171,10 +183,10 @@ __device__ __forceinline__ void tile_of(int L, int tiles_m, int tiles_n, int map
 // PF: read this wave's C block (beta != 0) before the K loop, so that its
 // latency overlaps the first fragment copies; for short K (the grouped
 // launches of small updates, one K step) the C read is most of a tile's time.
-template <int S, int T, bool SPLIT, int MODE, bool PF = false>
+template <int S, int T, bool SPLIT, int MODE, bool PF = false, int SB = S>
 __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, int kb0,
                                            int kb1, int chunk, int8_t *lds) {
-    using CF = Cfg<S, T, SPLIT>;
+    using CF = Cfg<S, T, SPLIT, SB>;
     static_assert(!PF || (MODE == 0 && CF::WM * CF::WN == 1), "C prefetch: one block per wave");
     constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
     constexpr int NSLOT = CF::NSLOT;
@@ -268,24 +280,29 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
                 constexpr bool TRI = (T == S + 1);
                 const int8_t *pa = cur + (wm * CF::WM + i) * FRAG_BYTES + lane * 16;
                 const int8_t *pb = cur + (FRA + wn * CF::WN + j) * FRAG_BYTES + lane * 16;
-                v4i b[S];
+                v4i b[SB];
                 v4i a = *reinterpret_cast<const v4i *>(pa + (S - 1) * TM * FRAG_BYTES);
 #pragma unroll
-                for (int d = 0; d < (TRI ? 1 : S); ++d)
+                for (int d = 0; d < (TRI ? 1 : SB); ++d)
                     b[d] = *reinterpret_cast<const v4i *>(pb + d * TN * FRAG_BYTES);
-                __builtin_amdgcn_sched_group_barrier(0x100, TRI ? 2 : S + 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, TRI ? 2 : SB + 1, 0);
 #pragma unroll
                 for (int ii = S; ii >= 1; --ii) {
                     v4i an = a;
                     if (ii > 1) {
                         an = *reinterpret_cast<const v4i *>(pa + (ii - 2) * TM * FRAG_BYTES);
-                        if (TRI)
-                            b[S + 1 - ii] = *reinterpret_cast<const v4i *>(
+                        // the next B digit, while there is one (SB < S: the
+                        // last S - SB A digits take no new B digit)
+                        if (TRI && (S + 1 - ii) < SB) {
+                            b[(S + 1 - ii) < SB ? S + 1 - ii : 0] = *reinterpret_cast<const v4i *>(
                                 pb + (S + 1 - ii) * TN * FRAG_BYTES);
-                        __builtin_amdgcn_sched_group_barrier(0x100, TRI ? 2 : 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                        } else {
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                        }
                     }
 #pragma unroll
-                    for (int jj = 1; jj <= S; ++jj)
+                    for (int jj = 1; jj <= SB; ++jj)
                         if (ii + jj <= T) {
                             const int sl = CF::slot(ii, jj);
                             acc[i][j][sl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
@@ -359,9 +376,9 @@ __device__ __forceinline__ void sgemm_tile(const GemmArgs &p, int tm, int tn, in
     }
 }
 
-template <int S, int T, bool SPLIT, int MODE>
-__global__ __launch_bounds__((Cfg<S, T, SPLIT>::THREADS)) void k_slicegemm(GemmArgs p) {
-    using CF = Cfg<S, T, SPLIT>;
+template <int S, int T, bool SPLIT, int MODE, int SB = S>
+__global__ __launch_bounds__((Cfg<S, T, SPLIT, SB>::THREADS)) void k_slicegemm(GemmArgs p) {
+    using CF = Cfg<S, T, SPLIT, SB>;
     __shared__ __attribute__((aligned(1024))) int8_t lds[CF::NST * CF::STAGE];
     int tm, tn;
     tile_of(blockIdx.x, p.tiles_m, p.tiles_n, p.map, &tm, &tn);
@@ -373,7 +390,7 @@ __global__ __launch_bounds__((Cfg<S, T, SPLIT>::THREADS)) void k_slicegemm(GemmA
         kb0 = blockIdx.y * p.chunk_kb;
         kb1 = min(p.KB, kb0 + p.chunk_kb);
     }
-    sgemm_tile<S, T, SPLIT, MODE>(p, tm, tn, kb0, kb1, blockIdx.y, lds);
+    sgemm_tile<S, T, SPLIT, MODE, false, SB>(p, tm, tn, kb0, kb1, blockIdx.y, lds);
 }
 
 // Persistent grouped form: every workgroup walks the concatenated tile list
@@ -721,6 +738,65 @@ int launch_slicegemm(const int8_t *Ap, const Planes &ga, const int8_t *Bp,
 #undef EMU_CASE
     set_error("no kernel for s=%d t=%d", s, t);
     return EMU_ERR_UNSUPPORTED;
+}
+
+// Unequal splits: A with s slices, B with sb < s, t = s + 1; one pass (no
+// K chunks: the longest slot holds sb pairs, so K up to the plain exact
+// length of sb pairs needs none).
+template <int S, int SB>
+static int launch_ab(const GemmArgs &a0, hipStream_t stream) {
+    using CF = Cfg<S, S + 1, false, SB>;
+    GemmArgs a = a0;
+    a.tiles_m = (a.M + CF::TM * 32 - 1) / (CF::TM * 32);
+    a.tiles_n = (a.N + CF::TN * 32 - 1) / (CF::TN * 32);
+    a.map = (t_map == 1 && a.tiles_m % 16 == 0 && a.tiles_n % 16 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_slicegemm<S, S + 1, false, 0, SB>), dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                       dim3(CF::THREADS), 0, stream, a);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
+template <int S, int SB>
+static int dispatch_ab(int s, int sb, const GemmArgs &a, hipStream_t stream) {
+    if constexpr (S > GROUPED_MAX_SLICES) {
+        set_error("unequal splits: s = %d, sb = %d unsupported", s, sb);
+        return EMU_ERR_UNSUPPORTED;
+    } else if constexpr (SB >= S) {
+        return dispatch_ab<S + 1, 1>(s, sb, a, stream);
+    } else {
+        if (s == S && sb == SB) return launch_ab<S, SB>(a, stream);
+        return dispatch_ab<S, SB + 1>(s, sb, a, stream);
+    }
+}
+
+int launch_slicegemm_ab(const int8_t *Ap, const Planes &ga, const int8_t *Bp, const Planes &gb,
+                        const int *codeA, const int *codeB, int m, int n, int k, int s, int sb,
+                        double alpha, double beta, double *C, long long ldc, hipStream_t stream) {
+    if (s < 2 || s > GROUPED_MAX_SLICES || sb < 1 || sb >= s) {
+        set_error("unequal splits: s = %d, sb = %d (need 1 <= sb < s <= %d)", s, sb,
+                  GROUPED_MAX_SLICES);
+        return EMU_ERR_UNSUPPORTED;
+    }
+    const long long KB = (k + K_BLOCK - 1) / K_BLOCK;
+    if (KB * K_BLOCK > exact_len(max_slot_pairs(s, s + 1, false, sb))) {
+        set_error("unequal splits: k = %d exceeds the one-pass exact length", k);
+        return EMU_ERR_UNSUPPORTED;
+    }
+    GemmArgs a{};
+    a.Ap = Ap;
+    a.Bp = Bp;
+    a.a_plane = ga.plane_bytes;
+    a.b_plane = gb.plane_bytes;
+    a.codeA = codeA;
+    a.codeB = codeB;
+    a.M = m;
+    a.N = n;
+    a.KB = ga.KB;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.C = C;
+    a.ldc = ldc;
+    return dispatch_ab<2, 1>(s, sb, a, stream);
 }
 
 void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n) {

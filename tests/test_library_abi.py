@@ -118,3 +118,12 @@ def test_batched_refinement_argument_codes():
     assert f(1, big, r, P, big, P, big, P, big, 32, 3, 1e-15, 10, it, be, sf, inf) == 1003
     assert f(0, None, None, None, None, None, None, None, None, 32, 3, 1e-15, 10, None, None,
              None, None) == 0
+
+
+def test_unequal_splits_argument_codes():
+    f = emu.emu_dgemm_ab
+    assert f(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 9, 0) == -13
+    assert f(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 5, 6) == -13
+    assert f(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 0, 1) == -12
+    assert f(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 12, 3) == 1003
+    assert f(-1, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 9, 3) == -1
