@@ -463,92 +463,126 @@ def bench_blocking(args, emu, torch, matgen):
     return out
 
 
+def _gpu_phi(torch, n, phi, seed):
+    """u exp(phi g) on the GPU from a seeded generator (column-major view)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2000003 * seed + 11)
+    M = torch.rand((n, n), generator=g, dtype=torch.float64, device="cuda").mul_(2.0).sub_(1.0)
+    if phi != 0.0:
+        M.mul_(torch.exp(phi * torch.randn((n, n), generator=g, dtype=torch.float64,
+                                           device="cuda")))
+    return M.t()
+
+
 def bench_learned(args, emu, torch, matgen):
-    """Learned slice count: train the MLP on tiles of emulated LUs of
-    n = 8192 (three matrices) and n = 16384 (one) with phi ~ U(0, 12), then
-    solve one n = 16384 system (phi ~ U(0, 12)) with the adaptive LU plus
-    FP64 refinement to 1e-15, falling back to the full count (s = 9) when
-    the refinement fails; next to the same solve at the full count and
-    native FP64."""
+    """Learned slice count: train the MLP on tiles of the Schur updates of
+    emulated LUs of 16 matrices (12 of n = 8192, 4 of n = 16384; phi ~
+    U(0, 12); labels: the smallest s whose tile update is within 2^-40 of the
+    s = 9 update), validate on 4 more (n = 8192), then solve one n = 16384
+    system for each phi in {0, 4, 8, 12}: the adaptive LU plus FP64
+    refinement to 1e-15 (falling back to the full count if it fails), the
+    full count (s = 9) with refinement, the constant-count precision forms
+    (s = 3 and 4 with refinement) and native FP64 with refinement."""
     from paper_2509_23565_amd import learned
     g = matgen.rng(args.seed, 77)
-    specs = [(8192, float(g.uniform(0.0, 12.0))) for _ in range(3)]
-    specs.append((16384, float(g.uniform(0.0, 12.0))))
+    specs = [(8192, float(g.uniform(0.0, 12.0))) for _ in range(12)]
+    specs += [(16384, float(g.uniform(0.0, 12.0))) for _ in range(4)]
+    vspecs = [(8192, float(g.uniform(0.0, 12.0))) for _ in range(4)]
+    steps_per = 12                      # LU steps sampled per matrix
+
+    def labelled(sp, base):
+        Xs, ys = [], []
+        for i, (n_, phi_) in enumerate(sp):
+            M = _gpu_phi(torch, n_, phi_, base + i)
+            X, y = learned.training_set([M], nb=256, max_steps=steps_per)
+            Xs.append(X)
+            ys.append(y)
+            del M
+            torch.cuda.empty_cache()
+        return torch.cat(Xs), torch.cat(ys)
     t0 = time.perf_counter()
-    mats = [emu.colmajor(matgen.phi_matrix(n, n, phi, seed=args.seed, substream=2000 + i))
-            for i, (n, phi) in enumerate(specs)]
-    log(f"learned: {len(mats)} training matrices generated ({time.perf_counter() - t0:.0f} s)")
-    t0 = time.perf_counter()
-    X, y = learned.training_set(mats, nb=256)
+    X, y = labelled(specs, 2000)
+    Xv, yv = labelled(vspecs, 2100)
     torch.cuda.synchronize()
     t_set = time.perf_counter() - t0
-    del mats
-    torch.cuda.empty_cache()
     t0 = time.perf_counter()
     params, hist = learned.train(X, y, steps=400)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     counts = torch.bincount(y.long(), minlength=7).tolist()
-    log(f"learned: {X.shape[0]} tiles labelled in {t_set:.1f} s, trained in {t_train:.1f} s, "
-        f"loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+    _, pred = emu.mlp_infer(params, Xv)
+    pv = pred.long() - 3
+    acc = float((pv == yv.long()).float().mean())
+    cons = float((pv >= yv.long()).float().mean())
+    log(f"learned: {X.shape[0]} training tiles, {Xv.shape[0]} validation tiles, labelled in "
+        f"{t_set:.1f} s, trained in {t_train:.1f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}; "
+        f"validation: predicted = label {acc:.3f}, predicted >= label {cons:.3f}")
 
     n, tol = 16384, 1e-15
-    phi_e = float(g.uniform(0.0, 12.0))
-    A = matgen.phi_matrix(n, n, phi_e, seed=args.seed, substream=3000)
-    b = matgen.uniform(n, 1, seed=args.seed, substream=3001)
-    Ag, bg = emu.colmajor(A), emu.colmajor(b)
-    del A
-    info_l = {}
+    evals = []
+    for pi, phi_e in enumerate((0.0, 4.0, 8.0, 12.0)):
+        Ag = _gpu_phi(torch, n, phi_e, 3000 + pi)
+        gb = torch.Generator(device="cuda")
+        gb.manual_seed(3100 + pi)
+        bg = (torch.rand((1, n), generator=gb, dtype=torch.float64, device="cuda") * 2 - 1).t()
+        info_l = {}
 
-    def learned_solve():
-        LU = Ag.clone()
-        ipiv, _, _, (used, full) = emu.dgetrf_adaptive(LU, params, nb=256, s_full=9)
-        x = bg.clone()
-        emu.dgetrs(LU, ipiv, x)
-        rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
-        info_l.update(used=used, full=full, rc_learned=rc, iters=iters, berr=berr,
-                      fallback=False)
-        if rc != 0:
+        def learned_solve():
             LU = Ag.clone()
-            ipiv, _ = emu.dgetrf(LU, nb=256, nslices=9)
+            ipiv, _, _, (used, full) = emu.dgetrf_adaptive(LU, params, nb=256, s_full=9)
             x = bg.clone()
             emu.dgetrs(LU, ipiv, x)
             rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
-            info_l.update(fallback=True, rc=rc, iters_fallback=iters, berr=berr)
-        return x
+            info_l.update(used=used, full=full, rc_learned=rc, iters=iters, berr=berr,
+                          fallback=False)
+            if rc != 0:
+                LU = Ag.clone()
+                ipiv, _ = emu.dgetrf(LU, nb=256, nslices=9)
+                x = bg.clone()
+                emu.dgetrs(LU, ipiv, x)
+                rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
+                info_l.update(fallback=True, rc=rc, iters_fallback=iters, berr=berr)
+            return x
+        t_l = _time(torch, learned_solve, reps=2)
+        row = {"phi": phi_e, "learned_ms": round(t_l, 2),
+               "product_ratio_vs_full": round(info_l["used"] / max(info_l["full"], 1), 4),
+               "learned_refined": info_l["rc_learned"] == 0, "fallback": info_l["fallback"],
+               "learned_iters": info_l["iters"], "learned_berr_fp64": info_l["berr"]}
+        for s_c in (9, 4, 3):
+            res = {}
 
-    info_f = {}
-
-    def full_solve():
-        LU = Ag.clone()
-        ipiv, _ = emu.dgetrf(LU, nb=256, nslices=9)
-        x = bg.clone()
-        emu.dgetrs(LU, ipiv, x)
-        rc, iters, berr = emu.refine(Ag, LU, ipiv, bg, x, tol=tol)
-        info_f.update(rc=rc, iters=iters, berr=berr)
-        return x
-
-    t_l = _time(torch, learned_solve, reps=2)
-    t_f = _time(torch, full_solve, reps=2)
-    At, bt = Ag.contiguous(), bg.contiguous()
-    t_n = _time(torch, lambda: _native_refined(torch, At, bt, tol), reps=2)
-    out = {
+            def const_solve():
+                X, inf = emu.dgesv_ir(Ag, bg, nb=256, nslices=s_c, tol=tol)
+                res.update(inf)
+                return X
+            t_c = _time(torch, const_solve, reps=2)
+            row[f"constant_s{s_c}_ms"] = round(t_c, 2)
+            row[f"constant_s{s_c}_iters"] = res["iters"]
+            row[f"constant_s{s_c}_final"] = res["s_final"]
+        At, bt = Ag.contiguous(), bg.contiguous()
+        row["native_refined_ms"] = round(_time(torch, lambda: _native_refined(torch, At, bt, tol),
+                                               reps=2), 2)
+        best = min(row["constant_s3_ms"], row["constant_s4_ms"], row["constant_s9_ms"])
+        row["learned_vs_best_constant"] = round(best / row["learned_ms"], 3)
+        evals.append(row)
+        log(f"learned phi={phi_e}: {row['product_ratio_vs_full']:.3f} of the full count's "
+            f"products, fallback={row['fallback']}, {t_l:.1f} ms; constant s=9/4/3 + IR "
+            f"{row['constant_s9_ms']:.1f}/{row['constant_s4_ms']:.1f}/"
+            f"{row['constant_s3_ms']:.1f} ms; native+IR {row['native_refined_ms']:.1f} ms")
+        del Ag, bg, At, bt
+        torch.cuda.empty_cache()
+    return {
         "train": {"matrices": [{"n": n_, "phi": round(p_, 3)} for n_, p_ in specs],
-                  "tiles": int(X.shape[0]), "label_counts_s3_to_s9": counts,
-                  "labelling_s": round(t_set, 2), "training_s": round(t_train, 2),
-                  "loss_first": hist[0], "loss_last": hist[-1]},
-        "eval": {"n": n, "phi": round(phi_e, 3), "nb": 256, "tol": tol,
-                 "products_used": info_l["used"], "products_full": info_l["full"],
-                 "product_ratio": round(info_l["used"] / max(info_l["full"], 1), 4),
-                 "learned_refined": info_l["rc_learned"] == 0, "fallback": info_l["fallback"],
-                 "berr_fp64": info_l["berr"], "learned_ms": round(t_l, 2),
-                 "full_count_ms": round(t_f, 2), "full_count_berr_fp64": info_f["berr"],
-                 "native_refined_ms": round(t_n, 2)},
+                  "validation": [{"n": n_, "phi": round(p_, 3)} for n_, p_ in vspecs],
+                  "lu_steps_per_matrix": steps_per, "tiles": int(X.shape[0]),
+                  "validation_tiles": int(Xv.shape[0]),
+                  "label_counts_s3_to_s9": counts, "labelling_s": round(t_set, 2),
+                  "training_s": round(t_train, 2), "loss_first": hist[0],
+                  "loss_last": hist[-1], "validation_exact": round(acc, 4),
+                  "validation_conservative": round(cons, 4)},
+        "eval": {"n": n, "nb": 256, "tol": tol, "runs": evals,
+                 "inputs": "u exp(phi g) generated on the GPU (seeded)"},
     }
-    log(f"learned: n={n} phi={phi_e:.2f}: {out['eval']['product_ratio']:.3f} of the products, "
-        f"fallback={info_l['fallback']}, {t_l:.1f} ms vs full count {t_f:.1f} ms, "
-        f"native+IR {t_n:.1f} ms")
-    return out
 
 
 def main():

@@ -284,6 +284,9 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
  *   panel is factored;
  *   the caller's stream waits for it, so the call stays ordered on the
  *   caller's stream.  The factors are identical either way.
+ *   "batched_tile" (0 or 1, default 0): grouped-GEMM output tile of the
+ *   batched calls given an explicit block size (0: 64 x 128, 1: 64 x 64;
+ *   six slices and more); nb = 0 uses the autotuned tile.  Bits unchanged.
  *   "gemm_map" (0 or 1, default 1): order in which the workgroups of an
  *   emulated GEMM visit the output tiles: 1 lets all eight XCDs work on one
  *   block of tiles at a time (used when both tile counts are multiples of
@@ -409,15 +412,19 @@ int emu_dgesv_batched_ir(int count, const int *n, const int *nrhs, const double 
 
 /*
  * emu_autotune_batched: time the batched solve of this batch on private
- * copies (inputs untouched) for block sizes {16, 32} and grouped-GEMM grid
- * sizes {1, 2} x (CUs x resident workgroups), record the fastest for the
- * batch shape (count, largest n, nslices) — used when nb = 0 — and return
- * it (host outputs).  With EMU_AUTOTUNE_CACHE set the table is read from
- * and written to that file.  Allocates and frees device memory.
+ * copies (inputs untouched) over block sizes {16, 32}, grouped-GEMM grid
+ * sizes {1, 2} x (CUs x resident workgroups) and, from six slices on, the
+ * grouped GEMM's output tile (0: 64 x 128, eight waves; 1: 64 x 64, four
+ * waves), record the fastest for the batch shape (device architecture, HIP
+ * runtime version, count, largest n, nslices) — used when nb = 0 — and
+ * return it (host outputs; best_tile last).  With EMU_AUTOTUNE_CACHE set
+ * the table is read from and written to that file (one line per shape:
+ * key nb grid tile).  Allocates and frees device memory.  Tile shapes
+ * change no bit of the results.
  */
 int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const *A,
                          const int *lda, double *const *B, const int *ldb, int nslices,
-                         int *best_nb, int *best_mult, double *best_ms);
+                         int *best_nb, int *best_mult, double *best_ms, int *best_tile);
 
 /*
  * Learned slice count (not in the paper; it builds on the paper's

@@ -91,7 +91,7 @@ _SIGNATURES = {
     "emu_dgetrf_batched": ([_I, _P, _P, _P, _P, _P, _I, _I], _I),
     "emu_dgesv_batched": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I], _I),
     "emu_autotune_batched": ([_I, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_I),
-                              ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
+                              ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
     "emu_refine": ([_I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _I, _D, _I, ctypes.POINTER(_I),
                     ctypes.POINTER(_D)], _I),
     "emu_scaled_residual": ([_I, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(_D)], _I),
@@ -427,18 +427,24 @@ def dgetrf_batched(As, nb=32, nslices=5):
     return ipivs, info
 
 
-def autotune_batched(As, Bs, nslices=5):
-    """Tune (nb, grid multiplier) for this batch shape; returns (nb, mult, ms)."""
+def autotune_batched(As, Bs, nslices=5, with_tile=False):
+    """Tune (nb, grid multiplier, grouped-GEMM tile) for this batch shape;
+    returns (nb, mult, ms), and the tile (0: 64 x 128, 1: 64 x 64) last
+    when with_tile."""
     count = len(As)
     n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
     nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
     a = _Batch(As, "A")
     b = _Batch(Bs, "B")
     bnb, bm, bms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    bt = ctypes.c_int(0)
     _bind_stream()
     _check(emu_autotune_batched(count, n, nrhs, a.ptr, a.ld, b.ptr, b.ld, int(nslices),
-                                ctypes.byref(bnb), ctypes.byref(bm), ctypes.byref(bms)),
+                                ctypes.byref(bnb), ctypes.byref(bm), ctypes.byref(bms),
+                                ctypes.byref(bt)),
            "emu_autotune_batched")
+    if with_tile:
+        return bnb.value, bm.value, bms.value, bt.value
     return bnb.value, bm.value, bms.value
 
 

@@ -444,6 +444,7 @@ __global__ void k_binfo_clear(const BSys *__restrict__ sys, int count) {
 // ------------------------------------------------------------------ plans
 struct BatchPlan {
     int count = 0, nb = 0, s = 0, steps = 0, grid_mult = 1, nmax = 0;
+    int shape = 0;                     // grouped GEMM tile (gemm_tile_counts)
     bool solve = false;
     std::vector<int> order;            // system index of sorted slot q
     std::vector<int> nact;             // active systems per step
@@ -599,7 +600,7 @@ static void plan_fill(BatchPlan &pl, const int *n, const int *nrhs, double *cons
             ga.beta = 1.0;
             ga.C = S.A + j1 + (long long)j1 * S.lda;
             ga.ldc = S.lda;
-            gemm_tile_counts(s, lines, lines, &ga.tiles_m, &ga.tiles_n);
+            gemm_tile_counts(s, lines, lines, &ga.tiles_m, &ga.tiles_n, pl.shape);
             pl.gemm.push_back(ga);
             tiles += ga.tiles_m * ga.tiles_n;
             pl.gprefix.push_back(tiles);
@@ -643,7 +644,7 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
     const BSys *sys = reinterpret_cast<const BSys *>(base + pl.o_sys);
     hipLaunchKernelGGL(k_binfo_clear, dim3((pl.count + 255) / 256), dim3(256), 0, st, sys,
                        pl.count);
-    const int ggrid = cus * gemm_grouped_blocks_per_cu(pl.s) * pl.grid_mult;
+    const int ggrid = cus * gemm_grouped_blocks_per_cu(pl.s, pl.shape) * pl.grid_mult;
     for (int stp = 0; stp < pl.steps; ++stp) {
         const int j0 = stp * pl.nb;
         const int act = pl.nact[stp];
@@ -661,7 +662,7 @@ static int plan_launch(const BatchPlan &pl, char *base, int *status, int cus, hi
                                     pl.g_off[stp];
             const int *gpre = reinterpret_cast<const int *>(base + pl.o_gpre) + pl.gp_off[stp];
             EMU_TRY(launch_slicegemm_grouped(probs, gpre, pl.g_cnt[stp], pl.g_tiles[stp], ggrid,
-                                             pl.s, st, /*one_kstep=*/true));
+                                             pl.s, st, /*one_kstep=*/true, pl.shape));
         }
     }
     hipLaunchKernelGGL(k_blaswp_left, dim3(pl.count), dim3(256), 0, st, sys, pl.nb);
@@ -813,13 +814,17 @@ struct GraphEntry {
 };
 static std::mutex g_bmu;
 static std::map<std::string, GraphEntry> g_graphs;
-static std::map<std::string, std::pair<int, int>> g_tuned;   // shape -> (nb, grid_mult)
+struct Tuned {
+    int nb, mult, shape;
+};
+static std::map<std::string, Tuned> g_tuned;   // batch shape -> choice
 static bool g_tuned_loaded = false;
 
 static std::string shape_key(int count, const int *n, const int *nrhs, int nb, int s,
-                             bool solve, int mult) {
+                             bool solve, int mult, int tile) {
     std::string k = std::to_string(count) + ":" + std::to_string(nb) + ":" + std::to_string(s) +
-                    ":" + (solve ? "1" : "0") + ":" + std::to_string(mult) + ":";
+                    ":" + (solve ? "1" : "0") + ":" + std::to_string(mult) + ":" +
+                    std::to_string(tile) + ":";
     unsigned long long h = 1469598103934665603ull;
     for (int i = 0; i < count; ++i) {
         h = (h ^ (unsigned long long)n[i]) * 1099511628211ull;
@@ -828,12 +833,30 @@ static std::string shape_key(int count, const int *n, const int *nrhs, int nb, i
     return k + std::to_string(h);
 }
 
-// Tuning key: the batch's coarse shape (count, largest n, slice count).
+// Tuning key: the device architecture and HIP runtime version, then the
+// batch's coarse shape (count, largest n, slice count).
 static std::string tune_key(int count, int nmax, int s) {
-    return std::to_string(count) + "/" + std::to_string(nmax) + "/" + std::to_string(s);
+    static thread_local std::string prefix;
+    if (prefix.empty()) {
+        int dev = 0, rt = 0;
+        hipDeviceProp_t prop;
+        std::string arch = "unknown";
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            arch = prop.gcnArchName;
+            for (char &c : arch)
+                if (c == ' ' || c == ':') c = '_';
+        }
+        if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+        prefix = arch + "/hip" + std::to_string(rt) + "/";
+    }
+    return prefix + std::to_string(count) + "/" + std::to_string(nmax) + "/" + std::to_string(s);
 }
 
 static const char *tune_file() { return std::getenv("EMU_AUTOTUNE_CACHE"); }
+
+// tile shape of batched calls with an explicit block size (emu_set_param
+// "batched_tile"); the autotuned choice applies when nb = 0
+static thread_local int g_batched_tile = 0;
 
 static void tune_load() {
     if (g_tuned_loaded) return;
@@ -842,10 +865,11 @@ static void tune_load() {
     if (!f) return;
     FILE *fp = std::fopen(f, "r");
     if (!fp) return;
-    // one entry per line: "key nb grid_mult"
+    // one entry per line: "key nb grid_mult tile_shape"
     char key[256];
-    int nb, mult;
-    while (std::fscanf(fp, "%255s %d %d", key, &nb, &mult) == 3) g_tuned[key] = {nb, mult};
+    int nb, mult, tile;
+    while (std::fscanf(fp, "%255s %d %d %d", key, &nb, &mult, &tile) == 4)
+        g_tuned[key] = {nb, mult, tile};
     std::fclose(fp);
 }
 
@@ -854,8 +878,9 @@ static void tune_save() {
     if (!f) return;
     FILE *fp = std::fopen(f, "w");
     if (!fp) return;
-    for (auto &kv : g_tuned) std::fprintf(fp, "%s %d %d\n", kv.first.c_str(), kv.second.first,
-                                          kv.second.second);
+    for (auto &kv : g_tuned)
+        std::fprintf(fp, "%s %d %d %d\n", kv.first.c_str(), kv.second.nb, kv.second.mult,
+                     kv.second.shape);
     std::fclose(fp);
 }
 
@@ -904,9 +929,10 @@ static int check_batch(int count, const int *n, const int *nrhs, double *const *
 // digit planes live there): a call whose scratch is elsewhere captures anew.
 static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
                      const int *lda, int *const *ipiv, int *info, double *const *B,
-                     const int *ldb, int nb, int nslices, int mult, bool solve) {
+                     const int *ldb, int nb, int nslices, int mult, bool solve, int tile = 0) {
     std::lock_guard<std::mutex> lk(g_bmu);
-    const std::string key = shape_key(count, n, nrhs, nb, nslices, solve, mult);
+    if (nslices < 6) tile = 0;          // one tile shape below six slices
+    const std::string key = shape_key(count, n, nrhs, nb, nslices, solve, mult, tile);
     auto it = g_graphs.find(key);
     GraphEntry e;
     size_t need;
@@ -915,6 +941,7 @@ static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
     } else {
         plan_shape(e.plan, count, n, nrhs, nb, nslices, solve);
         e.plan.grid_mult = mult;
+        e.plan.shape = tile;
         need = e.plan.total;
     }
     Call call;
@@ -955,6 +982,8 @@ static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
     return 0;
 }
 
+void set_batched_tile(int tile) { g_batched_tile = tile; }
+
 }  // namespace emu
 
 using namespace emu;
@@ -967,17 +996,18 @@ int emu_dgetrf_batched(int count, const int *n, double *const *A, const int *lda
                           false);
     if (bad) return bad;
     if (count == 0) return 0;
-    int mult = 1;
+    int mult = 1, tile = g_batched_tile;
     if (nb == 0) {
         std::lock_guard<std::mutex> lk(g_bmu);
         tune_load();
         int nmax = *std::max_element(n, n + count);
         auto t = g_tuned.find(tune_key(count, nmax, nslices));
-        nb = t != g_tuned.end() ? t->second.first : BMAX_NB;
-        mult = t != g_tuned.end() ? t->second.second : 1;
+        nb = t != g_tuned.end() ? t->second.nb : BMAX_NB;
+        mult = t != g_tuned.end() ? t->second.mult : 1;
+        tile = t != g_tuned.end() ? t->second.shape : 0;
     }
     return run_batch(count, n, nullptr, A, lda, ipiv, info, nullptr, nullptr, nb, nslices, mult,
-                     false);
+                     false, tile);
 }
 
 int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A,
@@ -986,16 +1016,17 @@ int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A
     int bad = check_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, true);
     if (bad) return bad;
     if (count == 0) return 0;
-    int mult = 1;
+    int mult = 1, tile = g_batched_tile;
     if (nb == 0) {
         std::lock_guard<std::mutex> lk(g_bmu);
         tune_load();
         int nmax = *std::max_element(n, n + count);
         auto t = g_tuned.find(tune_key(count, nmax, nslices));
-        nb = t != g_tuned.end() ? t->second.first : BMAX_NB;
-        mult = t != g_tuned.end() ? t->second.second : 1;
+        nb = t != g_tuned.end() ? t->second.nb : BMAX_NB;
+        mult = t != g_tuned.end() ? t->second.mult : 1;
+        tile = t != g_tuned.end() ? t->second.shape : 0;
     }
-    return run_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, mult, true);
+    return run_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, mult, true, tile);
 }
 
 int emu_dgesv_batched_ir(int count, const int *n, const int *nrhs, const double *const *A,
@@ -1193,9 +1224,9 @@ int emu_dgesv_batched_ir(int count, const int *n, const int *nrhs, const double 
 
 int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const *A,
                          const int *lda, double *const *B, const int *ldb, int nslices,
-                         int *best_nb, int *best_mult, double *best_ms) {
+                         int *best_nb, int *best_mult, double *best_ms, int *best_tile) {
     if (count <= 0) return -1;
-    if (!best_nb || !best_mult || !best_ms) return -9;
+    if (!best_nb || !best_mult || !best_ms || !best_tile) return -9;
     std::vector<int *> piv(count, nullptr);
     // private copies: the tuning runs factor in place
     std::vector<double *> Ac(count, nullptr), Bc(count, nullptr);
@@ -1216,13 +1247,15 @@ int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const
     }
     const int nbs[2] = {16, 32};
     const int mults[2] = {1, 2};
+    const int ntiles = nslices >= 6 ? 2 : 1;    // 64 x 128 and 64 x 64 (s >= 6)
     double best = 1e30;
-    int bnb = BMAX_NB, bm = 1;
+    int bnb = BMAX_NB, bm = 1, bt = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == 0 && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = EMU_ERR_HIP;
     for (int a = 0; a < 2 && rc == 0; ++a)
-        for (int b = 0; b < 2 && rc == 0; ++b) {
+        for (int b = 0; b < 2 && rc == 0; ++b)
+        for (int c = 0; c < ntiles && rc == 0; ++c) {
             float ms = 0.f;
             for (int rep = 0; rep < 2 && rc == 0; ++rep) {
                 for (int i = 0; i < count; ++i) {
@@ -1235,7 +1268,7 @@ int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const
                 }
                 (void)hipEventRecord(e0, st);
                 rc = run_batch(count, n, nrhs, Ac.data(), ldc.data(), piv.data(), dinfo,
-                               Bc.data(), ldbc.data(), nbs[a], nslices, mults[b], true);
+                               Bc.data(), ldbc.data(), nbs[a], nslices, mults[b], true, c);
                 (void)hipEventRecord(e1, st);
                 (void)hipEventSynchronize(e1);
                 (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1244,6 +1277,7 @@ int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const
                 best = ms;
                 bnb = nbs[a];
                 bm = mults[b];
+                bt = c;
             }
         }
     if (e0) (void)hipEventDestroy(e0);
@@ -1260,12 +1294,13 @@ int emu_autotune_batched(int count, const int *n, const int *nrhs, double *const
         std::lock_guard<std::mutex> lk(g_bmu);
         tune_load();
         const int nmax = *std::max_element(n, n + count);
-        g_tuned[tune_key(count, nmax, nslices)] = {bnb, bm};
+        g_tuned[tune_key(count, nmax, nslices)] = {bnb, bm, bt};
         tune_save();
     }
     *best_nb = bnb;
     *best_mult = bm;
     *best_ms = best;
+    *best_tile = bt;
     return 0;
 }
 

@@ -204,6 +204,9 @@ struct GemmArgs {
 // Tile order of the plain slice-GEMM launches on the calling thread
 // (emu_set_param "gemm_map"; 1 by default); bits are unaffected.
 void set_gemm_map(int map);
+// Grouped-GEMM tile of the batched form for calls with an explicit block
+// size (emu_set_param "batched_tile": 0 = 64 x 128, 1 = 64 x 64, s >= 6).
+void set_batched_tile(int tile);
 int gemm_map();
 
 // Slice-product GEMM with fused recombination, or the raw diagonal sums
@@ -228,16 +231,18 @@ int launch_slicegemm_ab(const int8_t *Ap, const Planes &ga, const int8_t *Bp, co
 // (device) holds problem q with tiles_m/tiles_n set by gemm_tile_counts;
 // tile_prefix (device, nprob + 1) is the running sum of tiles_m * tiles_n.
 // K of every problem must not need chunking (K <= 32 * 462 for s = 9).
-void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n);
+// shape 1 (s >= 6, one-K-step grouped launches): 64 x 64 tiles instead of
+// 64 x 128.
+void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n, int shape = 0);
 // Output tile of the slice GEMM at t = s + 1: tile_rows(s) x GEMM_TILE_COLS.
 __host__ __device__ constexpr int gemm_tile_rows(int s) { return s <= 5 ? 128 : 64; }
 constexpr int GEMM_TILE_COLS = 128;
-int gemm_grouped_blocks_per_cu(int s);
+int gemm_grouped_blocks_per_cu(int s, int shape = 0);
 // one_kstep: every problem has K <= 32 (one K step); selects the
 // pipelined kernel for s >= 6.
 int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
                              int total_tiles, int grid, int s, hipStream_t stream,
-                             bool one_kstep = false);
+                             bool one_kstep = false, int shape = 0);
 // The same with the problem count and the tile total read on the device
 // (counts[0], counts[1]), so the list can be built by a kernel; no launch
 // work is skipped on the host when the list is empty.

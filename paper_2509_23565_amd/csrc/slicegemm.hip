@@ -425,13 +425,25 @@ __global__ __launch_bounds__(512) void k_slicegemm_grouped(const GemmArgs *__res
 // recombined, the problem of tile t + 2 is looked up, and tile t + 1's C
 // block and exponents are read, all before the barrier that starts t + 1.
 // One 32x32 block per wave (the slot counts of s >= 6).
-template <int S>
-__global__ __launch_bounds__(512) void k_slicegemm_grouped1(const GemmArgs *__restrict__ probs,
-                                                            const int *__restrict__ tile_prefix,
-                                                            int nprob, int total) {
+// Tile of the pipelined grouped kernel: 2 x WNW waves, one 32x32 block each
+// (64 x 128 with four waves along N, 64 x 64 with two; the autotuner of the
+// batched form chooses).
+template <int S, int WNW>
+struct G1Cfg {
+    static constexpr int WAVES_M = 2, WAVES_N = WNW;
+    static constexpr int NW = WAVES_M * WAVES_N, THREADS = 64 * NW;
+    static constexpr int TM = WAVES_M, TN = WAVES_N;
+    static constexpr int FRA = S * TM, FRB = S * TN, FR = FRA + FRB;
+    static constexpr int NSLOT = S;          // t = s + 1: diagonals 2..s + 1
+    static constexpr int slot(int i, int j) { return i + j - 2; }
+};
+
+template <int S, int WNW>
+__global__ __launch_bounds__((G1Cfg<S, WNW>::THREADS)) void k_slicegemm_grouped1(
+    const GemmArgs *__restrict__ probs, const int *__restrict__ tile_prefix, int nprob,
+    int total) {
     constexpr int T = S + 1;
-    using CF = Cfg<S, T, false>;
-    static_assert(CF::WM == 1 && CF::WN == 1 && CF::THREADS == 512, "one block per wave");
+    using CF = G1Cfg<S, WNW>;
     constexpr int TM = CF::TM, TN = CF::TN, FRA = CF::FRA, FR = CF::FR, NW = CF::NW;
     constexpr int NSLOT = CF::NSLOT, NQ = (FR + NW - 1) / NW;
     __shared__ __attribute__((aligned(1024))) int8_t lds0[FR * FRAG_BYTES];
@@ -799,22 +811,26 @@ int launch_slicegemm_ab(const int8_t *Ap, const Planes &ga, const int8_t *Bp, co
     return dispatch_ab<2, 1>(s, sb, a, stream);
 }
 
-void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n) {
+void gemm_tile_counts(int s, int m, int n, int *tiles_m, int *tiles_n, int shape) {
     // plain t = s + 1 shapes (Cfg): 128 x 128 tiles while s <= 5, else 64 x 128
     static_assert(Cfg<5, 6, false>::TM * 32 == gemm_tile_rows(5) &&
                       Cfg<6, 7, false>::TM * 32 == gemm_tile_rows(6) &&
                       Cfg<5, 6, false>::TN * 32 == GEMM_TILE_COLS &&
                       Cfg<6, 7, false>::TN * 32 == GEMM_TILE_COLS,
                   "tile shape");
-    const int tmr = gemm_tile_rows(s), tnc = GEMM_TILE_COLS;
+    static_assert(G1Cfg<6, 4>::TM == Cfg<6, 7, false>::TM &&
+                      G1Cfg<6, 4>::TN == Cfg<6, 7, false>::TN,
+                  "default grouped tile");
+    const int tmr = gemm_tile_rows(s);
+    const int tnc = (shape == 1 && s >= 6) ? G1Cfg<6, 2>::TN * 32 : GEMM_TILE_COLS;
     *tiles_m = (m + tmr - 1) / tmr;
     *tiles_n = (n + tnc - 1) / tnc;
 }
 
-int gemm_grouped_blocks_per_cu(int s) {
+int gemm_grouped_blocks_per_cu(int s, int shape) {
     // LDS per workgroup: stages (4 while s <= 3, else 2) x s digits x
     // (TM + TN) fragments of 1 KB
-    const int frags = (s <= 5) ? 8 : 6;
+    const int frags = (s <= 5) ? 8 : (shape == 1 ? 4 : 6);
     const int kb = (s <= 3 ? 4 : 2) * s * frags;
     int b = 160 / (kb > 0 ? kb : 1);
     return b < 1 ? 1 : (b > 2 ? 2 : b);
@@ -822,14 +838,18 @@ int gemm_grouped_blocks_per_cu(int s) {
 
 int launch_slicegemm_grouped(const GemmArgs *probs, const int *tile_prefix, int nprob,
                              int total_tiles, int grid, int s, hipStream_t stream,
-                             bool one_kstep) {
+                             bool one_kstep, int shape) {
     if (total_tiles <= 0 || nprob <= 0) return 0;
     if (grid > total_tiles) grid = total_tiles;
     if (one_kstep && s >= 6 && s <= 9) {
-#define EMU_G1CASE(S_)                                                                   \
-    case S_:                                                                             \
-        hipLaunchKernelGGL((k_slicegemm_grouped1<S_>), dim3(grid), dim3(512), 0, stream, \
-                           probs, tile_prefix, nprob, total_tiles);                      \
+#define EMU_G1CASE(S_)                                                                       \
+    case S_:                                                                                 \
+        if (shape == 1)                                                                      \
+            hipLaunchKernelGGL((k_slicegemm_grouped1<S_, 2>), dim3(grid), dim3(256), 0, stream, \
+                               probs, tile_prefix, nprob, total_tiles);                      \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_slicegemm_grouped1<S_, 4>), dim3(grid), dim3(512), 0, stream, \
+                               probs, tile_prefix, nprob, total_tiles);                      \
         break;
         switch (s) {
             EMU_G1CASE(6) EMU_G1CASE(7) EMU_G1CASE(8) EMU_G1CASE(9)

@@ -99,6 +99,11 @@ def test_adaptive_lu_bit_exact_given_its_maps(m, n, nb, lookahead):
 
 
 def test_learned_gain_with_refinement():
+    # The maps target the full count's accuracy (tau = 2^-40 against s = 9),
+    # so the adaptive LU must reach 1e-15 with at most two refinement steps,
+    # without the full-count fallback, on clearly fewer slice products than
+    # the full count.  A model that predicts s = 9 everywhere, or one whose
+    # factors need the fallback, fails here.
     p = _trained_params()
     n = 1024
     A = matgen.phi_matrix(n, n, 5.0, seed=61)
@@ -108,19 +113,11 @@ def test_learned_gain_with_refinement():
     ipiv, info, smaps, (used, full) = emu.dgetrf_adaptive(LUg, p, nb=256, s_full=9)
     Xg = emu.colmajor(b)
     emu.dgetrs(LUg, ipiv, Xg)
-    rc, iters, berr = emu.refine(Ag, LUg, ipiv, emu.colmajor(b), Xg, tol=1e-15)
+    rc, iters, berr = emu.refine(Ag, LUg, ipiv, emu.colmajor(b), Xg, tol=1e-15, maxiter=2)
     eta = O.backward_error(A, _host(Xg), b)
     ratio = used / full
     print(f"learned slice counts: {ratio:.3f} of the full-count products, {iters} "
-          f"refinement steps, eta {eta:.2e} (rc {rc})")
-    if rc == 0:
-        assert eta <= 1e-15
-        assert ratio < 1.0
-    else:
-        # the residual check failed: the method falls back to the full count
-        LU9 = Ag.clone()
-        ip9, _ = emu.dgetrf(LU9, nb=256, nslices=9)
-        X9 = emu.colmajor(b)
-        emu.dgetrs(LU9, ip9, X9)
-        rc9, _, _ = emu.refine(Ag, LU9, ip9, emu.colmajor(b), X9, tol=1e-15)
-        assert rc9 == 0
+          f"refinement steps, eta {eta:.2e} (rc {rc}), counts {np.bincount(smaps)}")
+    assert int(_host(info)[0]) == 0
+    assert rc == 0 and iters <= 2 and eta <= 1e-15
+    assert ratio <= 0.9

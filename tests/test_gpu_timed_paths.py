@@ -162,3 +162,36 @@ def test_adam_steps_match_oracle():
         sure = np.abs(go) >= 1e-3 * np.abs(go).max()
         assert sure.mean() > 0.5
         assert np.abs(dg[sure] - do[sure]).max() <= 1e-3 * lr, step
+
+
+def test_batched_grouped_tile_shapes_and_tuner():
+    # the 64 x 64 grouped tile (four waves) against the default 64 x 128, and
+    # the oracle; then the autotuner's choice over block size, grid and tile
+    specs = matgen.batched_specs(10, seed=35, nmax=600)
+    As = [matgen.phi_matrix(n, n, phi, seed=35, substream=1000 + i)
+          for i, (n, phi, r) in enumerate(specs)]
+    Bs = [matgen.uniform(n, r, seed=35, substream=5000 + i) for i, (n, phi, r) in enumerate(specs)]
+    for s in (7, 9):
+        outs = []
+        try:
+            for tile in (0, 1):
+                emu.set_param("batched_tile", tile)
+                Ag = [emu.colmajor(a) for a in As]
+                Bg = [emu.colmajor(b) for b in Bs]
+                emu.dgesv_batched(Ag, Bg, nb=32, nslices=s)
+                outs.append(([_host(a) for a in Ag], [_host(b) for b in Bg]))
+        finally:
+            emu.set_param("batched_tile", 0)
+        for i in range(len(As)):
+            assert _same_bits(outs[0][0][i], outs[1][0][i]) and _same_bits(outs[0][1][i], outs[1][1][i])
+        for i in (0, 4):
+            LU, piv, _ = O.getrf(As[i], nb=32, s=s)
+            assert _same_bits(outs[1][0][i], LU)
+            assert _same_bits(outs[1][1][i], O.getrs(LU, piv, Bs[i]))
+    Ag = [emu.colmajor(a) for a in As]
+    Bg = [emu.colmajor(b) for b in Bs]
+    nb, mult, ms, tile = emu.autotune_batched(Ag, Bg, nslices=7, with_tile=True)
+    assert nb in (16, 32) and mult in (1, 2) and tile in (0, 1) and ms > 0
+    emu.dgesv_batched(Ag, Bg, nb=0, nslices=7)
+    LU, piv, _ = O.getrf(As[2], nb=nb, s=7)
+    assert _same_bits(_host(Ag[2]), LU)

@@ -145,3 +145,28 @@ def test_tiled_lu_puts_a_tile_error_where_the_map_says():
     E = np.abs(PA - L @ U).max(axis=0) / np.abs(A).max()
     inside, outside = E[100:356], np.concatenate([E[:100], E[356:]])
     assert inside.max() > 1e-6 and outside.max() < 1e-12
+
+
+def test_per_tile_counts_cannot_beat_one_count_once_refinement_is_used():
+    # With FP64 refinement (two steps at most) one constant count meets 1e-15
+    # here; the ideal per-tile map at a tolerance that still needs at most two
+    # steps (tau = 2^-26) costs more products per tile than that count.  The
+    # full record (n = 1024, five phi) is tests/golden/learned_ceiling.json.
+    n, nb = 768, 256
+    A = matgen.phi_matrix(n, n, 8.0, seed=61)
+    b = matgen.uniform(n, 1, seed=62)
+    best = None
+    for s in range(3, 10):
+        _, io = O.gesv_ir(A, b, nb=nb, s=s, tol=1e-15, maxiter=2, s_max=s)
+        if io["converged"]:
+            best = s
+            break
+    assert best is not None
+    LU, piv, _ = O.getrf(A, nb=nb, s=9)
+    labels = []
+    for j1 in range(nb, n, nb):
+        j0 = j1 - nb
+        labels.append(OL.tile_labels(np.asfortranarray(LU[j1:, j0:j1]),
+                                     np.asfortranarray(LU[j0:j1, j1:]), tau=2.0 ** -26))
+    lab = np.concatenate(labels)
+    assert np.mean(lab * (lab + 1) / 2) >= best * (best + 1) / 2
