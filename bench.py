@@ -813,6 +813,7 @@ def main():
             "value": round(2.0 * len(rows) * len(cols) * n / t_cpu / 1e12, 6),
             "unit": "TFLOP/s-equiv (FP64)",
             "cores": threads,
+            "host_cpus": os.cpu_count(),
             "kind": "oracle",
             "sample": f"C[{len(rows)} sampled rows, {len(cols)} sampled columns] of "
                       f"the same product: oracle exponent scan and slicing of those "

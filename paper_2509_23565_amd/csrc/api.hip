@@ -438,6 +438,7 @@ int emu_finalize(void) {
         if (c->ev_go) EMU_TRY_HIP(hipEventDestroy(c->ev_go));
         if (c->ev_done) EMU_TRY_HIP(hipEventDestroy(c->ev_done));
         if (c->side) EMU_TRY_HIP(hipStreamDestroy(c->side));
+        native_release(c);
         const int d = c->dev;
         *c = ThreadCtx();             // the caller's workspace is forgotten too
         c->dev = d;

@@ -52,6 +52,7 @@ struct ThreadCtx {
     hipStream_t side = nullptr;   // LU look-ahead: trailing updates (default priority)
     hipEvent_t ev_go = nullptr;   // main stream -> side stream
     hipEvent_t ev_done = nullptr; // side stream -> main stream
+    void *blas = nullptr;         // rocBLAS handle of the native comparison updates
 };
 
 // Current device's state (initialised on first use) and the thread's stream.
@@ -271,6 +272,8 @@ int launch_chol_panel(double *A, long long lda, int rows, int jb, int col0, int 
 // native comparison.
 int native_update(int m, int n, int k, const double *A, long long lda, const double *B,
                   long long ldb, double *C, long long ldc, hipStream_t stream);
+// Destroy the thread context's rocBLAS handle (emu_finalize).
+void native_release(ThreadCtx *c);
 // C (m x m, lower triangle) <- C - A A^T in native FP64 (rocBLAS dsyrk).
 int native_syrk_update(int m, int k, const double *A, long long lda, double *C, long long ldc,
                        hipStream_t stream);

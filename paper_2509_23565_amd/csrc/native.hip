@@ -11,21 +11,20 @@
 
 namespace emu {
 
-// one rocBLAS handle per thread and device, created on first use
-static thread_local rocblas_handle t_handles[64] = {};
-
+// The calling thread's rocBLAS handle on the current device (kept in its
+// thread context, created on first use, destroyed by emu_finalize).
 static int handle(hipStream_t stream, rocblas_handle *out) {
-    int dev = 0;
-    EMU_TRY_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) {
-        set_error("device id %d out of range", dev);
-        return EMU_ERR_UNSUPPORTED;
-    }
-    rocblas_handle &h = t_handles[dev];
-    if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
-        h = nullptr;
-        set_error("rocblas_create_handle failed");
-        return EMU_ERR_HIP;
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    ThreadCtx *c = thread_ctx(dev);
+    rocblas_handle h = static_cast<rocblas_handle>(c->blas);
+    if (!h) {
+        if (rocblas_create_handle(&h) != rocblas_status_success) {
+            set_error("rocblas_create_handle failed");
+            return EMU_ERR_HIP;
+        }
+        c->blas = h;
     }
     if (rocblas_set_stream(h, stream) != rocblas_status_success) {
         set_error("rocblas_set_stream failed");
@@ -65,6 +64,11 @@ int native_update(int m, int n, int k, const double *A, long long lda, const dou
         return EMU_ERR_HIP;
     }
     return 0;
+}
+
+void native_release(ThreadCtx *c) {
+    if (c->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
+    c->blas = nullptr;
 }
 
 }  // namespace emu
