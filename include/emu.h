@@ -385,6 +385,26 @@ int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A
                       const int *ldb, int nb, int nslices);
 
 /*
+ * emu_dgetrs_batched: solve A_i X_i = B_i for every system of a batch from
+ * factors and pivots that emu_dgetrf_batched (or emu_dgetrf with the same
+ * layout) left: LU[i] (host array of DEVICE pointers, lda[i] >= n[i],
+ * read only), ipiv[i] (host array of DEVICE int32[n[i]], 1-based), B[i]
+ * (host array of DEVICE pointers, ldb[i] >= n[i], nrhs[i] in 1..8
+ * columns) overwritten with X_i; n[i] in 1..1024.  Row interchanges, then
+ * forward substitution with the unit lower factor and back substitution
+ * with the upper one (the solve step of the solvers section, eqn (8)), one
+ * workgroup per system, in the per-element order of emu_dgetrs, so the
+ * results equal emu_dgesv_batched's solve bit for bit.  No check of the
+ * factors: an exactly zero U(j,j) gives Inf/NaN as in LAPACK's getrs.
+ * Synchronizes the stream once to upload the descriptors, then enqueues
+ * one launch.  Argument numbers: count=1 n=2 nrhs=3 LU=4 lda=5 ipiv=6 B=7
+ * ldb=8.
+ */
+int emu_dgetrs_batched(int count, const int *n, const int *nrhs, const double *const *LU,
+                       const int *lda, const int *const *ipiv, double *const *B,
+                       const int *ldb);
+
+/*
  * emu_dgesv_batched_ir: the precision form for a batch (the single-system
  * form is emu_dgesv_ir): A[i] and B[i] (host arrays of DEVICE pointers,
  * n[i] in 1..1024, nrhs[i] in 1..8) are left untouched; X[i] (ldx[i] >=

@@ -38,6 +38,7 @@ __all__ = [
     "status", "emu_dgemm_noalloc", "EMU_NOALLOC_SCRATCH_BYTES",
     "emu_dpotrf", "emu_potrf_workspace_bytes", "dpotrf",
     "emu_dgesv_batched_ir", "dgesv_batched_ir", "emu_dgemm_ab",
+    "emu_dgetrs_batched", "dgetrs_batched",
 ]
 
 EMU_MAX_SLICES = 16
@@ -90,6 +91,7 @@ _SIGNATURES = {
                       ctypes.POINTER(_I)], _I),
     "emu_dgetrf_batched": ([_I, _P, _P, _P, _P, _P, _I, _I], _I),
     "emu_dgesv_batched": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I], _I),
+    "emu_dgetrs_batched": ([_I, _P, _P, _P, _P, _P, _P, _P], _I),
     "emu_autotune_batched": ([_I, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_I),
                               ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
     "emu_refine": ([_I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _I, _D, _I, ctypes.POINTER(_I),
@@ -159,6 +161,7 @@ emu_set_param = _raw("emu_set_param")
 emu_dgesv_ir = _raw("emu_dgesv_ir")
 emu_dgetrf_batched = _raw("emu_dgetrf_batched")
 emu_dgesv_batched = _raw("emu_dgesv_batched")
+emu_dgetrs_batched = _raw("emu_dgetrs_batched")
 emu_autotune_batched = _raw("emu_autotune_batched")
 emu_refine = _raw("emu_refine")
 emu_scaled_residual = _raw("emu_scaled_residual")
@@ -425,6 +428,21 @@ def dgetrf_batched(As, nb=32, nslices=5):
     _check(emu_dgetrf_batched(count, n, a.ptr, a.ld, pp, info.data_ptr(), int(nb),
                               int(nslices)), "emu_dgetrf_batched")
     return ipivs, info
+
+
+def dgetrs_batched(LUs, ipivs, Bs):
+    """Solve every system of a batch in place (B_i -> X_i) from the factors
+    and pivots of dgetrf_batched."""
+    count = len(LUs)
+    n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in LUs])
+    nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
+    pp = (ctypes.c_void_p * count)(*[p.data_ptr() for p in ipivs])
+    a = _Batch(LUs, "LU")
+    b = _Batch(Bs, "B")
+    _bind_stream()
+    _check(emu_dgetrs_batched(count, n, nrhs, a.ptr, a.ld, pp, b.ptr, b.ld),
+           "emu_dgetrs_batched")
+    return Bs
 
 
 def autotune_batched(As, Bs, nslices=5, with_tile=False):

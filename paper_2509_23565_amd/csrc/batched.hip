@@ -617,8 +617,7 @@ static void plan_fill(BatchPlan &pl, const int *n, const int *nrhs, double *cons
 static void *g_pinned = nullptr;
 static size_t g_pinned_bytes = 0;
 
-static int plan_upload(const BatchPlan &pl, char *base, hipStream_t st) {
-    const size_t bytes = pl.o_planes;
+static int pinned_reserve(size_t bytes) {
     if (bytes > g_pinned_bytes) {
         if (g_pinned) EMU_TRY_HIP(hipHostFree(g_pinned));
         g_pinned = nullptr;
@@ -626,6 +625,12 @@ static int plan_upload(const BatchPlan &pl, char *base, hipStream_t st) {
         EMU_TRY_HIP(hipHostMalloc(&g_pinned, bytes, hipHostMallocDefault));
         g_pinned_bytes = bytes;
     }
+    return 0;
+}
+
+static int plan_upload(const BatchPlan &pl, char *base, hipStream_t st) {
+    const size_t bytes = pl.o_planes;
+    EMU_TRY(pinned_reserve(bytes));
     char *h = static_cast<char *>(g_pinned);
     std::memcpy(h + pl.o_sys, pl.sys.data(), pl.sys.size() * sizeof(BSys));
     if (!pl.gemm.empty()) {
@@ -1027,6 +1032,61 @@ int emu_dgesv_batched(int count, const int *n, const int *nrhs, double *const *A
         tile = t != g_tuned.end() ? t->second.shape : 0;
     }
     return run_batch(count, n, nrhs, A, lda, ipiv, info, B, ldb, nb, nslices, mult, true, tile);
+}
+
+int emu_dgetrs_batched(int count, const int *n, const int *nrhs, const double *const *LU,
+                       const int *lda, const int *const *ipiv, double *const *B,
+                       const int *ldb) {
+    if (count < 0) return -1;
+    if (count == 0) return 0;
+    if (!n) return -2;
+    if (!nrhs) return -3;
+    if (!LU) return -4;
+    if (!lda) return -5;
+    if (!ipiv) return -6;
+    if (!B) return -7;
+    if (!ldb) return -8;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 1 || n[i] > BMAX_N) {
+            set_error("batched solve: system %d has n = %d (supported 1..%d)", i, n[i], BMAX_N);
+            return EMU_ERR_UNSUPPORTED;
+        }
+        if (nrhs[i] < 1 || nrhs[i] > BMAX_RHS) {
+            set_error("batched solve: system %d has %d right-hand sides (1..%d)", i, nrhs[i],
+                      BMAX_RHS);
+            return EMU_ERR_UNSUPPORTED;
+        }
+        if (!LU[i]) return -4;
+        if (lda[i] < n[i]) return -5;
+        if (!ipiv[i]) return -6;
+        if (!B[i]) return -7;
+        if (ldb[i] < n[i]) return -8;
+    }
+    std::vector<BSys> sys(count);
+    for (int i = 0; i < count; ++i) {
+        BSys &S = sys[i];
+        S.A = const_cast<double *>(LU[i]);        // read only by the solve
+        S.lda = lda[i];
+        S.n = n[i];
+        S.nrhs = nrhs[i];
+        S.ipiv = const_cast<int *>(ipiv[i]);
+        S.info = nullptr;
+        S.B = B[i];
+        S.ldb = ldb[i];
+    }
+    const size_t bytes = (size_t)count * sizeof(BSys);
+    std::lock_guard<std::mutex> lk(g_bmu);     // guards the pinned staging buffer
+    Call call;
+    EMU_TRY(call.begin(bytes));
+    EMU_TRY(pinned_reserve(bytes));
+    std::memcpy(g_pinned, sys.data(), bytes);
+    EMU_TRY_HIP(hipMemcpyAsync(call.ws, g_pinned, bytes, hipMemcpyHostToDevice, call.st));
+    // the staging buffer is refilled on the next call: wait for the copy
+    EMU_TRY_HIP(hipStreamSynchronize(call.st));
+    hipLaunchKernelGGL(k_bgetrs, dim3(count), dim3(1024), 0, call.st,
+                       reinterpret_cast<const BSys *>(call.ws));
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
 }
 
 int emu_dgesv_batched_ir(int count, const int *n, const int *nrhs, const double *const *A,

@@ -453,6 +453,35 @@ def test_batched_solve_bit_exact_vs_oracle_and_single(nb, s):
         assert _same_bits(_host(A1), LU) and np.array_equal(_host(p1), piv)
 
 
+def test_batched_solve_from_stored_factors():
+    # factor once, solve two sets of right-hand sides from the stored factors;
+    # sizes from 1 to the largest supported, ragged against the 32-column
+    # panels and the 64-row solve blocks, one to eight right-hand sides
+    sizes = [(1, 1), (2, 8), (63, 3), (64, 2), (65, 5), (300, 1), (1024, 4)]
+    As = [matgen.phi_matrix(n, n, 1.5, seed=35, substream=1000 + i)
+          for i, (n, r) in enumerate(sizes)]
+    Bs = [matgen.uniform(n, r, seed=35, substream=5000 + i) for i, (n, r) in enumerate(sizes)]
+    Ag = [emu.colmajor(a) for a in As]
+    ipivs, info = emu.dgetrf_batched(Ag, nb=32, nslices=6)
+    assert not _host(info).any()
+    facts = [O.getrf(A, nb=32, s=6) for A in As]
+    for rep in range(2):
+        Bs2 = [b * (1.0 - 0.5 * rep) + rep for b in Bs]
+        Bg = [emu.colmajor(b) for b in Bs2]
+        emu.dgetrs_batched(Ag, ipivs, Bg)
+        for i, (LU, piv, _) in enumerate(facts):
+            assert np.array_equal(_host(ipivs[i]), piv), i
+            assert _same_bits(_host(Bg[i]), O.getrs(LU, piv, Bs2[i])), (rep, i)
+    # the same results as the factor-and-solve call
+    Ag2 = [emu.colmajor(a) for a in As]
+    Bg2 = [emu.colmajor(b) for b in Bs]
+    emu.dgesv_batched(Ag2, Bg2, nb=32, nslices=6)
+    Bg3 = [emu.colmajor(b) for b in Bs]
+    emu.dgetrs_batched(Ag, ipivs, Bg3)
+    for i in range(len(As)):
+        assert _same_bits(_host(Bg3[i]), _host(Bg2[i])), i
+
+
 def test_batched_graph_replay_with_new_matrices():
     specs, As, Bs = _batch(10, seed=32, nmin=30, nmax=500)
     for rep in range(3):

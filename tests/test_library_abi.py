@@ -120,6 +120,29 @@ def test_batched_refinement_argument_codes():
              None, None) == 0
 
 
+def test_batched_solve_argument_codes():
+    n = (ctypes.c_int * 1)(8)
+    r = (ctypes.c_int * 1)(1)
+    ld = (ctypes.c_int * 1)(8)
+    short = (ctypes.c_int * 1)(7)
+    P = (ctypes.c_void_p * 1)(0x1000)
+    Z = (ctypes.c_void_p * 1)(0)
+    f = emu.emu_dgetrs_batched
+    assert f(-1, n, r, P, ld, P, P, ld) == -1
+    assert f(0, None, None, None, None, None, None, None) == 0
+    assert f(1, None, r, P, ld, P, P, ld) == -2
+    assert f(1, n, None, P, ld, P, P, ld) == -3
+    assert f(1, n, r, Z, ld, P, P, ld) == -4
+    assert f(1, n, r, P, short, P, P, ld) == -5
+    assert f(1, n, r, P, ld, Z, P, ld) == -6
+    assert f(1, n, r, P, ld, P, Z, ld) == -7
+    assert f(1, n, r, P, ld, P, P, short) == -8
+    big = (ctypes.c_int * 1)(1025)
+    assert f(1, big, r, P, big, P, P, big) == 1003
+    many = (ctypes.c_int * 1)(9)
+    assert f(1, n, many, P, ld, P, P, ld) == 1003
+
+
 def test_unequal_splits_argument_codes():
     f = emu.emu_dgemm_ab
     assert f(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 9, 0) == -13
