@@ -245,12 +245,12 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         xr = L.xrow[buf];
     } else {
         const int G = (int)gridDim.x;
+        const unsigned long long tag = (unsigned long long)(base + (unsigned)c + 1u) << 32;
         if (wid == 0) {
             const long long wkv = (long long)(((unsigned long long)(unsigned)
                                                    __builtin_amdgcn_readfirstlane((int)(wk >> 32))
                                                << 32) |
                                               (unsigned)__builtin_amdgcn_readfirstlane((int)wk));
-            const unsigned long long tag = (unsigned long long)(base + (unsigned)c + 1u) << 32;
             // publish: words 0..35 (and 36..67 from workgroup 0), tagged
             unsigned long long *mine = x.rec + ((long long)buf * LF_MAX_G + g) * RW;
             const double *wrow = L.row[buf][((wi - base_row) % NT) / 64];
@@ -273,46 +273,49 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                 }
                 __hip_atomic_store(mine + e, tag | pl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // collect: read every record's words until all carry this tag;
-            // validated payloads go straight to LDS
+        }
+        // collect: every wave reads its share of the records' words (64-word
+        // blocks dealt round-robin over the waves), all loads of a poll in
+        // flight together, until all carry this tag; validated payloads go
+        // straight to LDS
+        {
             const unsigned long long *recs = x.rec + (long long)buf * LF_MAX_G * RW;
             unsigned *grow_w = reinterpret_cast<unsigned *>(&L.grow[buf][0][0]);
             unsigned *xr_w = reinterpret_cast<unsigned *>(&L.xr[buf][0]);
             const int nw = RW_MAIN * G + 32;            // words to read
+            constexpr int NWV = NT / 64;
+            constexpr int NBLK = (RW_MAIN * LF_MAX_G + 32 + 63) / 64;
+            constexpr int NLD = (NBLK + NWV - 1) / NWV;  // loads per lane, at most
             int spins = 0;
             for (;;) {
                 bool ok = true;
-#pragma unroll 1
-                for (int e0 = 0; e0 < nw; e0 += 4 * 64) {
-                    unsigned long long wd[4];
+                unsigned long long wd[NLD];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = e0 + u * 64 + lane;
-                        const int sl = e < RW_MAIN * G ? e / RW_MAIN : 0;
-                        const int wo = e < RW_MAIN * G ? e % RW_MAIN : RW_MAIN + (e - RW_MAIN * G);
-                        wd[u] = e < nw ? __hip_atomic_load(recs + (long long)sl * RW + wo,
-                                                           __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : tag;
+                for (int u = 0; u < NLD; ++u) {
+                    const int e = (u * NWV + wid) * 64 + lane;
+                    const int sl = e < RW_MAIN * G ? e / RW_MAIN : 0;
+                    const int wo = e < RW_MAIN * G ? e % RW_MAIN : RW_MAIN + (e - RW_MAIN * G);
+                    wd[u] = e < nw ? __hip_atomic_load(recs + (long long)sl * RW + wo,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                   : tag;
+                }
+#pragma unroll
+                for (int u = 0; u < NLD; ++u) {
+                    const int e = (u * NWV + wid) * 64 + lane;
+                    if (e >= nw) continue;
+                    if ((wd[u] & 0xFFFFFFFF00000000ull) != tag) {
+                        ok = false;
+                        continue;
                     }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = e0 + u * 64 + lane;
-                        if (e >= nw) continue;
-                        if ((wd[u] & 0xFFFFFFFF00000000ull) != tag) {
-                            ok = false;
-                            continue;
-                        }
-                        const unsigned pl = (unsigned)wd[u];
-                        if (e < RW_MAIN * G) {
-                            const int sl = e / RW_MAIN, wo = e % RW_MAIN;
-                            if (wo < 3)
-                                L.gkey[buf][sl][wo] = pl;
-                            else if (wo >= 4)
-                                grow_w[sl * 2 * LEAF_W + (wo - 4)] = pl;
-                        } else {
-                            xr_w[e - RW_MAIN * G] = pl;
-                        }
+                    const unsigned pl = (unsigned)wd[u];
+                    if (e < RW_MAIN * G) {
+                        const int sl = e / RW_MAIN, wo = e % RW_MAIN;
+                        if (wo < 3)
+                            L.gkey[buf][sl][wo] = pl;
+                        else if (wo >= 4)
+                            grow_w[sl * 2 * LEAF_W + (wo - 4)] = pl;
+                    } else {
+                        xr_w[e - RW_MAIN * G] = pl;
                     }
                 }
                 if (__ballot(!ok) == 0ull) break;
@@ -333,11 +336,11 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            // lanes read what other lanes staged
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            // the grid's winner from the staged keys
+        }
+        __syncthreads();
+        if (L.abort) return false;
+        // the grid's winner from the staged keys (every wave, same result)
+        {
             const int l = lane & (LF_MAX_G - 1);
             long long gv = -1;
             int gi = INT_MAX;
@@ -347,11 +350,8 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                 gi = (int)L.gkey[buf][l][2];
             }
             key_best<LF_MAX_G>(gv, gi);
-            if (lane == 0) L.p[buf] = gi;
+            p = __builtin_amdgcn_readfirstlane(gi);
         }
-        __syncthreads();
-        if (L.abort) return false;
-        p = __builtin_amdgcn_readfirstlane(L.p[buf]);
         const int gp = (p >= 0 && p < G * (NT * LF_R)) ? p / (NT * LF_R) : 0;
         // the grid winner's row: lane l < 32 reads word l, lane reads make
         // it wave-uniform (scalar registers)
