@@ -302,11 +302,12 @@ static size_t getrs_scratch_bytes(int n, int nrhs) {
 
 // Right-looking blocked LU on reserved scratch `ws` (getrf_scratch_bytes).
 //
-// Look-ahead: after panel k is factored and its interchanges applied, the
-// columns of panel k + 1 are updated first; the update of every column to
-// the right of them is queued on the device's side stream, where it runs
-// while panel k + 1 is factored on the caller's stream, and the caller's
-// stream waits for it before panel k + 1's interchanges.  Each element
+// Look-ahead: after panel k is factored, the columns of panel k + 1 take
+// its interchanges and are updated first; the interchanges of every other
+// column (left of panel k and right of panel k + 1) and the update of the
+// columns right of panel k + 1 are queued on the device's side stream, where
+// they run while panel k + 1 is factored on the caller's stream, and the
+// caller's stream waits for them before panel k + 1's interchanges.  Each element
 // receives exactly the same operations as without look-ahead (exponents are
 // per row of L21 and per column of U12, so splitting the update by columns
 // changes no bit).  The two updates of a step never overlap, so they share
@@ -349,11 +350,19 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
     for (int j0 = 0; j0 < mn; j0 += nb) {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         const int j1 = j0 + jb;
-        if (pivot)
+        const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
+        // With look-ahead and one interchange plan for the panel, only the
+        // next panel's columns take the interchanges on this stream; the
+        // columns left of the panel and right of the next one take them on
+        // the side stream, before its update (the plan stays valid: this
+        // stream waits for the side stream before the next plan is made).
+        const bool far_swaps = pivot && la && jn > 0 && j1 + jn < n && jb <= LASWP_CHUNK;
+        if (far_swaps)
+            EMU_TRY(launch_laswp(A, ld, m, 0, j1, jn, ipiv, j0, j1, 0, plan, st));
+        else if (pivot)
             for (int k1 = j0; k1 < j1; k1 += LASWP_CHUNK)
                 EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, k1,
                                      k1 + LASWP_CHUNK < j1 ? k1 + LASWP_CHUNK : j1, 0, plan, st));
-        const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
         if (!la || jn == 0) {
             EMU_TRY(update(j0, jb, j1, n, st));
             if (jn > 0) EMU_TRY(panel(j1));
@@ -364,6 +373,8 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
         if (j2 < n) {
             EMU_TRY_HIP(hipEventRecord(tc->ev_go, st));
             EMU_TRY_HIP(hipStreamWaitEvent(tc->side, tc->ev_go, 0));
+            if (far_swaps)
+                EMU_TRY(launch_laswp_apply(A, ld, m, j0, j2, n - j2, j0, j1, plan, tc->side));
             EMU_TRY(update(j0, jb, j2, n, tc->side));
             EMU_TRY_HIP(hipEventRecord(tc->ev_done, tc->side));
         }

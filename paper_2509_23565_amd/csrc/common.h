@@ -283,6 +283,10 @@ size_t laswp_plan_bytes(int nrows);
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
                  int ncols_right, const int *ipiv, int k1, int k2, int row0, int *plan,
                  hipStream_t stream);
+// The apply step alone, with the plan a launch_laswp call of the same
+// (nrows, k1, k2) left in `plan` (ordered after it on the device).
+int launch_laswp_apply(double *A, long long lda, int nrows, int ncols_left, int col_right,
+                       int ncols_right, int k1, int k2, const int *plan, hipStream_t stream);
 int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
                      long long ldb, int ncols, hipStream_t stream);
 // perm_ws holds the composed row permutation after a call; perm_ready

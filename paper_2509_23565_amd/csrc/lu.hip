@@ -197,6 +197,14 @@ int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_ri
                                          align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int)));
     hipLaunchKernelGGL(k_swap_plan, dim3(1), dim3(64), 0, stream, ipiv, k1, k2, nrows, row0,
                        plan, gperm);
+    return launch_laswp_apply(A, lda, nrows, ncols_left, col_right, ncols_right, k1, k2, plan,
+                              stream);
+}
+
+int launch_laswp_apply(double *A, long long lda, int nrows, int ncols_left, int col_right,
+                       int ncols_right, int k1, int k2, const int *plan, hipStream_t stream) {
+    const int total = ncols_left + ncols_right;
+    if (total <= 0 || k2 <= k1 || nrows <= k1) return 0;
     // columns per workgroup from the largest possible plan (2 per interchange)
     const int nslot_max = 2 * (k2 - k1);
     const int cw = nslot_max < SW_TILE ? SW_TILE / nslot_max : 1;
