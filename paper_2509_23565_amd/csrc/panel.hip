@@ -92,7 +92,6 @@ struct LeafLds {
     double grow[2][LF_MAX_G][LEAF_W];   // multi-workgroup: every record's row
     unsigned gkey[2][LF_MAX_G][3];      // and its key (high, low) and row
     double xr[2][LEAF_W];
-    int p[2];
     int abort;
     int piv[LEAF_W];          // pivot row (leaf coordinates) of each column
     int srow[2 * LEAF_W];     // panel-row interchanges: row of each slot
