@@ -27,9 +27,10 @@
 //     every wave picks the winner and reads both rows without a second
 //     round.  Leaves taller than 2048 rows run as one launch of up to 32
 //     workgroups that exchange their candidates the same way through global
-//     memory, with one grid-wide wait per column (bounded: a wait that
-//     exceeds its bound aborts the leaf, sets info to EMU_INFO_ABORTED and
-//     raises EMU_STATUS_PANEL_WAIT).
+//     memory, with one grid-wide wait per column: every wave reads a share
+//     of all workgroups' records, then a workgroup barrier (bounded: a wait
+//     that exceeds its bound aborts the leaf, sets info to EMU_INFO_ABORTED
+//     and raises EMU_STATUS_PANEL_WAIT).
 #include "common.h"
 #include "devutil.h"
 
