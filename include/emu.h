@@ -116,7 +116,8 @@ int emu_set_workspace(void *dptr, size_t bytes);
 
 /* Scratch bytes emu_dgemm needs for that shape (0 for invalid arguments). */
 size_t emu_workspace_bytes(int m, int n, int k, int nslices);
-/* Scratch bytes emu_dgetrf needs (nb <= 0: 64; 0 for invalid arguments). */
+/* Scratch bytes emu_dgetrf needs (nb <= 0: the block size emu_dgetrf would
+ * select; 0 for invalid arguments). */
 size_t emu_getrf_workspace_bytes(int m, int n, int nb, int nslices);
 /* Scratch bytes emu_dgetrs needs (0 for invalid arguments). */
 size_t emu_getrs_workspace_bytes(int n, int nrhs);
@@ -210,9 +211,10 @@ int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
 
 /*
  * emu_dgetrf: PA = LU of the m x n matrix A (lda >= max(1,m)) in place,
- * right-looking blocked with block size nb (nb <= 0 selects 64, at most
- * EMU_MAX_NB; interchanges are applied to the other columns in chunks of
- * 1024, in order), partial
+ * right-looking blocked with block size nb (at most EMU_MAX_NB; nb <= 0
+ * selects the block size emu_autotune_getrf recorded for (m, n, nslices) on
+ * this device and runtime, else 64; interchanges are applied to the other
+ * columns in chunks of 1024, in order), partial
  * pivoting (paper: solvers section, eqns (5)-(8)).  Per block column:
  * FP64 panel factorization (first row of largest magnitude is the pivot;
  * the column below is scaled by the reciprocal of the pivot, or divided
@@ -230,6 +232,24 @@ int emu_dgemm_t(int m, int n, int k, double alpha, const double *A, int lda,
  */
 int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info,
                int nb, int nslices);
+
+/*
+ * emu_autotune_getrf: time emu_dgetrf of a private copy of A (m x n,
+ * lda >= m, device; A itself is not modified) once per candidate block size
+ * (count > 0: nbs[0..count) on the host, each in 1..EMU_MAX_NB; count = 0:
+ * 256, 512, 768 and 1024 up to min(m, n), or min(m, n, 64) when none is),
+ * after one untimed run with the candidate of the largest scratch; record
+ * the fastest for (device architecture, HIP runtime version, m, n,
+ * nslices), which emu_dgetrf, emu_dgesv_ir and emu_getrf_workspace_bytes
+ * then use for nb <= 0, and return it with its time (host outputs).  The
+ * paper leaves the block size open; its figures compare block sizes.  With
+ * EMU_AUTOTUNE_CACHE set the record joins the batched form's table in that
+ * file.  Allocates and frees device memory for the copy; synchronizes.
+ * Argument numbers: m=1 n=2 A=3 lda=4 nslices=5 nbs=6 count=7 best_nb=8
+ * best_ms=9.
+ */
+int emu_autotune_getrf(int m, int n, const double *A, int lda, int nslices, const int *nbs,
+                       int count, int *best_nb, double *best_ms);
 
 /*
  * emu_dpotrf: Cholesky A = L L^T of the symmetric positive definite n x n
@@ -307,7 +327,8 @@ int emu_set_param(const char *key, long long value);
  * stalls (this form is not in the paper; the stopping quantity is eqn (9)'s
  * scaled residual without its n eps factor).
  *   1. LU of a copy of A (A itself is not modified) with `nslices` slices and
- *      block size nb (nb <= 0: 64); X = getrs(B).
+ *      block size nb (nb <= 0: as emu_dgetrf selects it for (n, n, nslices),
+ *      kept for the fallback factorizations); X = getrs(B).
  *   2. Repeat: R = B - A X in FP64; eta = max over columns of
  *      ||R||_inf / (||A||_inf ||X||_inf + ||B||_inf).  Stop when eta <= tol.
  *      Otherwise, if eta did not fall below half its previous value, or

@@ -38,7 +38,7 @@ __all__ = [
     "status", "emu_dgemm_noalloc", "EMU_NOALLOC_SCRATCH_BYTES",
     "emu_dpotrf", "emu_potrf_workspace_bytes", "dpotrf",
     "emu_dgesv_batched_ir", "dgesv_batched_ir", "emu_dgemm_ab",
-    "emu_dgetrs_batched", "dgetrs_batched",
+    "emu_dgetrs_batched", "dgetrs_batched", "emu_autotune_getrf", "autotune_getrf",
 ]
 
 EMU_MAX_SLICES = 16
@@ -92,6 +92,8 @@ _SIGNATURES = {
     "emu_dgetrf_batched": ([_I, _P, _P, _P, _P, _P, _I, _I], _I),
     "emu_dgesv_batched": ([_I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I], _I),
     "emu_dgetrs_batched": ([_I, _P, _P, _P, _P, _P, _P, _P], _I),
+    "emu_autotune_getrf": ([_I, _I, _P, _I, _I, _P, _I, ctypes.POINTER(_I),
+                            ctypes.POINTER(_D)], _I),
     "emu_autotune_batched": ([_I, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_I),
                               ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_I)], _I),
     "emu_refine": ([_I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _I, _D, _I, ctypes.POINTER(_I),
@@ -162,6 +164,7 @@ emu_dgesv_ir = _raw("emu_dgesv_ir")
 emu_dgetrf_batched = _raw("emu_dgetrf_batched")
 emu_dgesv_batched = _raw("emu_dgesv_batched")
 emu_dgetrs_batched = _raw("emu_dgetrs_batched")
+emu_autotune_getrf = _raw("emu_autotune_getrf")
 emu_autotune_batched = _raw("emu_autotune_batched")
 emu_refine = _raw("emu_refine")
 emu_scaled_residual = _raw("emu_scaled_residual")
@@ -428,6 +431,22 @@ def dgetrf_batched(As, nb=32, nslices=5):
     _check(emu_dgetrf_batched(count, n, a.ptr, a.ld, pp, info.data_ptr(), int(nb),
                               int(nslices)), "emu_dgetrf_batched")
     return ipivs, info
+
+
+def autotune_getrf(A, nslices=3, nbs=None):
+    """Time the LU of a copy of A over candidate block sizes (nbs None: 256,
+    512, 768, 1024 up to min(m, n)) and record the fastest for nb = 0 calls
+    of this shape; returns (nb, ms)."""
+    m, n = A.shape
+    pa, lda = _mat(A, "A")
+    cand = list(nbs) if nbs else []
+    arr = (ctypes.c_int * max(len(cand), 1))(*cand) if cand else None
+    nb = ctypes.c_int(0)
+    ms = ctypes.c_double(0.0)
+    _bind_stream()
+    _check(emu_autotune_getrf(m, n, pa, lda, int(nslices), arr, len(cand), ctypes.byref(nb),
+                              ctypes.byref(ms)), "emu_autotune_getrf")
+    return nb.value, ms.value
 
 
 def dgetrs_batched(LUs, ipivs, Bs):

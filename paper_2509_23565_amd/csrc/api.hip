@@ -290,8 +290,15 @@ static size_t getrf_gemm_bytes(int m, int n, int nb, int s) {
                                  s, s + 1).total);
 }
 
+// Block size of an LU call given nb <= 0: the autotuned one for this shape
+// and slice count if recorded, else 64.
+static int resolve_nb(int m, int n, int s) {
+    const int nb = tuned_getrf_nb(m, n, s);
+    return nb > 0 ? nb : 64;
+}
+
 static size_t getrf_scratch_bytes(int m, int n, int nb, int s) {
-    if (nb <= 0) nb = 64;
+    if (nb <= 0) nb = resolve_nb(m, n, s);
     return getrf_gemm_bytes(m, n, nb, s) + align256(panel_scratch_bytes(m)) +
            laswp_plan_bytes(m);
 }
@@ -477,7 +484,7 @@ size_t emu_workspace_bytes(int m, int n, int k, int nslices) {
 
 size_t emu_getrf_workspace_bytes(int m, int n, int nb, int nslices) {
     if (m < 0 || n < 0 || nb > EMU_MAX_NB || nslices < 1 || nslices > EMU_MAX_SLICES) return 0;
-    return getrf_scratch_bytes(m, n, nb <= 0 ? 64 : nb, nslices);
+    return getrf_scratch_bytes(m, n, nb, nslices);
 }
 
 size_t emu_getrs_workspace_bytes(int n, int nrhs) {
@@ -717,10 +724,81 @@ int emu_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info, int nb,
     if (!info) return -6;
     if (nb > EMU_MAX_NB) return -7;
     if (nslices < 1 || nslices > EMU_MAX_SLICES) return -8;
-    if (nb <= 0) nb = 64;
+    if (nb <= 0) nb = resolve_nb(m, n, nslices);
     Call c;
     EMU_TRY(c.begin(getrf_scratch_bytes(m, n, nb, nslices)));
     return getrf_impl(c.dev, c.ws, c.st, m, n, A, lda, ipiv, info, nb, nslices);
+}
+
+int emu_autotune_getrf(int m, int n, const double *A, int lda, int nslices, const int *nbs,
+                       int count, int *best_nb, double *best_ms) {
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < m) return -4;
+    if (nslices < 1 || nslices > EMU_MAX_SLICES) return -5;
+    if (count < 0) return -7;
+    if (count > 0 && !nbs) return -6;
+    for (int i = 0; i < count; ++i)
+        if (nbs[i] < 1 || nbs[i] > EMU_MAX_NB) return -6;
+    if (!best_nb) return -8;
+    if (!best_ms) return -9;
+    const int mn = m < n ? m : n;
+    std::vector<int> cand;
+    if (count > 0) {
+        cand.assign(nbs, nbs + count);
+    } else {
+        for (int nb : {256, 512, 768, 1024})
+            if (nb <= mn) cand.push_back(nb);
+        if (cand.empty()) cand.push_back(mn < 64 ? mn : 64);
+    }
+    Device *dev;
+    hipStream_t st;
+    EMU_TRY(current(&dev, &st));
+    // private copy of A (leading dimension m), pivots, info, two timing events
+    struct Res {
+        double *W = nullptr;
+        int *piv = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Res() {
+            if (W) (void)hipFree(W);
+            if (piv) (void)hipFree(piv);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } r;
+    EMU_TRY_HIP(hipMalloc(&r.W, (size_t)m * n * sizeof(double)));
+    EMU_TRY_HIP(hipMalloc(&r.piv, (size_t)(mn + 1) * sizeof(int)));
+    EMU_TRY_HIP(hipEventCreate(&r.e0));
+    EMU_TRY_HIP(hipEventCreate(&r.e1));
+    // warm-up with the candidate of the largest scratch, so that no timed run
+    // grows the library's scratch
+    int warm = cand[0];
+    for (int nb : cand)
+        if (getrf_scratch_bytes(m, n, nb, nslices) > getrf_scratch_bytes(m, n, warm, nslices))
+            warm = nb;
+    double best = 0.0;
+    int bnb = 0;
+    for (int i = -1; i < (int)cand.size(); ++i) {
+        const int nb = i < 0 ? warm : cand[i];
+        EMU_TRY_HIP(hipMemcpy2DAsync(r.W, (size_t)m * sizeof(double), A,
+                                     (size_t)lda * sizeof(double), (size_t)m * sizeof(double),
+                                     n, hipMemcpyDeviceToDevice, st));
+        EMU_TRY_HIP(hipEventRecord(r.e0, st));
+        EMU_TRY(emu_dgetrf(m, n, r.W, m, r.piv, r.piv + mn, nb, nslices));
+        EMU_TRY_HIP(hipEventRecord(r.e1, st));
+        EMU_TRY_HIP(hipEventSynchronize(r.e1));
+        float ms = 0.0f;
+        EMU_TRY_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+        if (i >= 0 && (bnb == 0 || ms < best)) {
+            best = ms;
+            bnb = nb;
+        }
+    }
+    record_getrf_nb(m, n, nslices, bnb);
+    *best_nb = bnb;
+    *best_ms = best;
+    return 0;
 }
 
 int emu_dpotrf(int n, double *A, int lda, int *info, int nb, int nslices) {
@@ -820,7 +898,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     if (!berr) return -14;
     if (!s_final) return -15;
     if (!info) return -16;
-    if (nb <= 0) nb = 64;
+    if (nb <= 0) nb = resolve_nb(n, n, nslices);
     *iters = 0;
     *berr = 0.0;
     *s_final = nslices;

@@ -840,7 +840,9 @@ static std::string shape_key(int count, const int *n, const int *nrhs, int nb, i
 
 // Tuning key: the device architecture and HIP runtime version, then the
 // batch's coarse shape (count, largest n, slice count).
-static std::string tune_key(int count, int nmax, int s) {
+// Key prefix of the tuning table: device architecture and HIP runtime
+// version, so a table file written on other hardware or software is not used.
+static std::string tune_prefix() {
     static thread_local std::string prefix;
     if (prefix.empty()) {
         int dev = 0, rt = 0;
@@ -854,7 +856,17 @@ static std::string tune_key(int count, int nmax, int s) {
         if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
         prefix = arch + "/hip" + std::to_string(rt) + "/";
     }
-    return prefix + std::to_string(count) + "/" + std::to_string(nmax) + "/" + std::to_string(s);
+    return prefix;
+}
+
+static std::string tune_key(int count, int nmax, int s) {
+    return tune_prefix() + std::to_string(count) + "/" + std::to_string(nmax) + "/" +
+           std::to_string(s);
+}
+
+static std::string getrf_key(int m, int n, int s) {
+    return tune_prefix() + "getrf/" + std::to_string(m) + "/" + std::to_string(n) + "/" +
+           std::to_string(s);
 }
 
 static const char *tune_file() { return std::getenv("EMU_AUTOTUNE_CACHE"); }
@@ -988,6 +1000,20 @@ static int run_batch(int count, const int *n, const int *nrhs, double *const *A,
 }
 
 void set_batched_tile(int tile) { g_batched_tile = tile; }
+
+int tuned_getrf_nb(int m, int n, int s) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    tune_load();
+    auto it = g_tuned.find(getrf_key(m, n, s));
+    return it != g_tuned.end() ? it->second.nb : 0;
+}
+
+void record_getrf_nb(int m, int n, int s, int nb) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    tune_load();
+    g_tuned[getrf_key(m, n, s)] = {nb, 0, 0};
+    tune_save();
+}
 
 }  // namespace emu
 

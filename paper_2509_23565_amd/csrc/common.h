@@ -208,6 +208,11 @@ void set_gemm_map(int map);
 // Grouped-GEMM tile of the batched form for calls with an explicit block
 // size (emu_set_param "batched_tile": 0 = 64 x 128, 1 = 64 x 64, s >= 6).
 void set_batched_tile(int tile);
+// Block size emu_autotune_getrf recorded for an LU of this shape and slice
+// count on this device and runtime (0: none), and recording one (kept in the
+// same table, and file, as the batched form's choices).
+int tuned_getrf_nb(int m, int n, int s);
+void record_getrf_nb(int m, int n, int s, int nb);
 int gemm_map();
 
 // Slice-product GEMM with fused recombination, or the raw diagonal sums

@@ -12,7 +12,10 @@ to 2048, and times it without pivoting):
   backward-error bound of Gaussian elimination, |PA - LU| <= gamma_n |L||U|
   (any summation order of the updates meets it; without pivoting the growth
   makes two orders differ far beyond their rounding, so the factors are not
-  compared entry by entry).
+  compared entry by entry);
+* the block-size autotuner: the recorded choice is what nb = 0 selects in
+  emu_dgetrf, emu_dgesv_ir and the workspace query, bit for bit, and the
+  input is left untouched.
 """
 import numpy as np
 import pytest
@@ -123,3 +126,26 @@ def test_native_update_lu_matches_fp64_oracle(pivot):
     # the factorization's own error and that of forming L U here: 2 gamma_n
     # |L||U| (Higham, Accuracy and Stability, Thm 9.3 and Sec. 3.5)
     assert np.all(np.abs(PA - L @ U) <= 2 * gam * (np.abs(L) @ np.abs(U)))
+
+
+def test_getrf_autotune_selects_recorded_block_size():
+    n = 1500
+    A = matgen.phi_matrix(n, n, 1.0, seed=41)
+    Ag = emu.colmajor(A)
+    nb, ms = emu.autotune_getrf(Ag, nslices=3, nbs=[128, 256])
+    assert nb in (128, 256) and ms > 0.0
+    assert _same_bits(_host(Ag), A)                      # the input is untouched
+    A0, A1 = emu.colmajor(A), emu.colmajor(A)
+    p0, i0 = emu.dgetrf(A0, nb=0, nslices=3)
+    p1, i1 = emu.dgetrf(A1, nb=nb, nslices=3)
+    LU, piv, _ = O.getrf(A, nb=nb, s=3)
+    assert _same_bits(_host(A0), LU) and _same_bits(_host(A1), LU)
+    assert np.array_equal(_host(p0), piv) and np.array_equal(_host(p1), piv)
+    L = emu.lib()
+    assert L.emu_getrf_workspace_bytes(n, n, 0, 3) == L.emu_getrf_workspace_bytes(n, n, nb, 3)
+    # the precision form with nb = 0 factors with the recorded block size too
+    b = emu.colmajor(matgen.uniform(n, 1, seed=42))
+    X0, r0 = emu.dgesv_ir(Ag, b, nb=0, nslices=3)
+    X1, r1 = emu.dgesv_ir(Ag, b, nb=nb, nslices=3)
+    assert r0["rc"] == 0 and r0["iters"] == r1["iters"]
+    assert _same_bits(_host(X0), _host(X1))

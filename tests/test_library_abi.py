@@ -143,6 +143,24 @@ def test_batched_solve_argument_codes():
     assert f(1, n, many, P, ld, P, P, ld) == 1003
 
 
+def test_getrf_autotune_argument_codes():
+    f = emu.emu_autotune_getrf
+    nb, ms = ctypes.c_int(0), ctypes.c_double(0.0)
+    bn, bm = ctypes.byref(nb), ctypes.byref(ms)
+    assert f(0, 4, _p(), 4, 3, None, 0, bn, bm) == -1
+    assert f(4, 0, _p(), 4, 3, None, 0, bn, bm) == -2
+    assert f(4, 4, None, 4, 3, None, 0, bn, bm) == -3
+    assert f(4, 4, _p(), 3, 3, None, 0, bn, bm) == -4
+    assert f(4, 4, _p(), 4, 0, None, 0, bn, bm) == -5
+    assert f(4, 4, _p(), 4, 17, None, 0, bn, bm) == -5
+    assert f(4, 4, _p(), 4, 3, None, 2, bn, bm) == -6
+    assert f(4, 4, _p(), 4, 3, (ctypes.c_int * 1)(4096), 1, bn, bm) == -6
+    assert f(4, 4, _p(), 4, 3, (ctypes.c_int * 1)(0), 1, bn, bm) == -6
+    assert f(4, 4, _p(), 4, 3, None, -1, bn, bm) == -7
+    assert f(4, 4, _p(), 4, 3, None, 0, None, bm) == -8
+    assert f(4, 4, _p(), 4, 3, None, 0, bn, None) == -9
+
+
 def test_unequal_splits_argument_codes():
     f = emu.emu_dgemm_ab
     assert f(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 9, 0) == -13
