@@ -262,7 +262,7 @@ __device__ __forceinline__ double lane_bcast(double v, int k) {
 // in LDS).
 __device__ __forceinline__ void load_diag_block(const double *__restrict__ LU, long long lda,
                                                 int k0, int kb, double *Ds) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     // all loads issued before the first store (no serialized round trips)
     double col[TRSV_NB];
 #pragma unroll
@@ -293,25 +293,42 @@ __global__ __launch_bounds__(64) void k_fwd_diag(const double *__restrict__ LU,
     if (lane < kb) x[i] = b;
 }
 
-// Rows [r0, r1) after the diagonal block: x_i -= l_ik x_k, k increasing.
+// Rows [r0, n) after the diagonal block [k0, k0+kb): x_i -= l_ik x_k, k
+// increasing.  Workgroup 0's first wave holds rows r0 .. r0+63, the next
+// diagonal block (kb2 rows): once they are updated it solves that block in
+// registers as k_fwd_diag does, so the sweep needs no diagonal launch of
+// its own after the first.
 __global__ __launch_bounds__(256) void k_fwd_update(const double *__restrict__ LU,
                                                     long long lda, int n, int k0,
-                                                    int kb, int r0,
+                                                    int kb, int r0, int kb2,
                                                     double *__restrict__ X) {
     __shared__ double xs[TRSV_NB];
+    __shared__ double Ds[TRSV_NB * TRSV_NB];
     double *x = X + (long long)blockIdx.y * n;
+    const bool diag = blockIdx.x == 0 && kb2 > 0 && threadIdx.x < 64;
     if (threadIdx.x < kb) xs[threadIdx.x] = x[k0 + threadIdx.x];
+    if (diag) load_diag_block(LU, lda, r0, kb2, Ds);
     __syncthreads();
     const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double l[TRSV_NB];
+    double b = 0.0;
+    if (i < n) {
+        double l[TRSV_NB];
 #pragma unroll
-    for (int k = 0; k < TRSV_NB; ++k) l[k] = k < kb ? LU[i + (long long)(k0 + k) * lda] : 0.0;
-    double b = x[i];
+        for (int k = 0; k < TRSV_NB; ++k)
+            l[k] = k < kb ? LU[i + (long long)(k0 + k) * lda] : 0.0;
+        b = x[i];
 #pragma unroll
-    for (int k = 0; k < TRSV_NB; ++k)
-        if (k < kb) b = b - l[k] * xs[k];
-    x[i] = b;
+        for (int k = 0; k < TRSV_NB; ++k)
+            if (k < kb) b = b - l[k] * xs[k];
+    }
+    if (diag) {
+        const int lane = threadIdx.x;
+        for (int k = 0; k < kb2 - 1; ++k) {
+            const double xk = lane_bcast(b, k);
+            if (lane > k && lane < kb2) b = b - Ds[k * TRSV_NB + lane] * xk;
+        }
+    }
+    if (i < n) x[i] = b;
 }
 
 // Back substitution, diagonal block [k0, k0+kb): for k decreasing,
@@ -333,15 +350,22 @@ __global__ __launch_bounds__(64) void k_bwd_diag(const double *__restrict__ LU,
     if (lane < kb) x[i] = b;
 }
 
-// Rows [0, k0) above the diagonal block: x_i -= u_ik x_k, k decreasing.
+// Rows [0, k0) above the diagonal block [k0, k0+kb): x_i -= u_ik x_k, k
+// decreasing.  k0 is a multiple of 64, so rows k0-64 .. k0-1, the previous
+// diagonal block, are one whole wave of the last workgroup: once they are
+// updated that wave solves the block in registers as k_bwd_diag does.
 __global__ __launch_bounds__(256) void k_bwd_update(const double *__restrict__ LU,
                                                     long long lda, int n, int k0,
                                                     int kb, double *__restrict__ X) {
     __shared__ double xs[TRSV_NB];
+    __shared__ double Ds[TRSV_NB * TRSV_NB];
     double *x = X + (long long)blockIdx.y * n;
-    if (threadIdx.x < kb) xs[threadIdx.x] = x[k0 + threadIdx.x];
-    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // the wave holding rows [k0 - 64, k0) (uniform per wave)
+    const bool diag = i >= k0 - TRSV_NB && i - (int)(threadIdx.x & 63) + TRSV_NB <= k0;
+    if (threadIdx.x < kb) xs[threadIdx.x] = x[k0 + threadIdx.x];
+    if (diag) load_diag_block(LU, lda, k0 - TRSV_NB, TRSV_NB, Ds);
+    __syncthreads();
     if (i >= k0) return;
     double u[TRSV_NB];
 #pragma unroll
@@ -350,6 +374,14 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double *__restrict__ L
 #pragma unroll
     for (int k = TRSV_NB - 1; k >= 0; --k)
         if (k < kb) b = b - u[k] * xs[k];
+    if (diag) {
+        const int lane = threadIdx.x & 63;
+        for (int k = TRSV_NB - 1; k >= 0; --k) {
+            if (lane == k) b = b / Ds[k * TRSV_NB + k];
+            const double xk = lane_bcast(b, k);
+            if (lane < k) b = b - Ds[k * TRSV_NB + lane] * xk;
+        }
+    }
     x[i] = b;
 }
 
@@ -363,27 +395,29 @@ int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ip
         hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm);
     dim3 gcol((n + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_gather_rows, gcol, dim3(256), 0, stream, B, ldb, n, perm, X);
+    // forward: the first diagonal block, then per block the update of the
+    // rows below it together with the next diagonal block
+    hipLaunchKernelGGL(k_fwd_diag, dim3(nrhs), dim3(64), 0, stream, LU, lda, n, 0,
+                       n < TRSV_NB ? n : TRSV_NB, X);
     for (int k0 = 0; k0 < n; k0 += TRSV_NB) {
-        int kb = n - k0 < TRSV_NB ? n - k0 : TRSV_NB;
-        hipLaunchKernelGGL(k_fwd_diag, dim3(nrhs), dim3(64), 0, stream, LU, lda, n, k0,
-                           kb, X);
-        int r0 = k0 + kb;
+        const int kb = n - k0 < TRSV_NB ? n - k0 : TRSV_NB;
+        const int r0 = k0 + kb;
         if (r0 < n) {
+            const int kb2 = n - r0 < TRSV_NB ? n - r0 : TRSV_NB;
             dim3 g((n - r0 + 255) / 256, nrhs);
             hipLaunchKernelGGL(k_fwd_update, g, dim3(256), 0, stream, LU, lda, n, k0, kb,
-                               r0, X);
+                               r0, kb2, X);
         }
     }
-    int last0 = (n - 1) / TRSV_NB * TRSV_NB;
-    for (int k0 = last0; k0 >= 0; k0 -= TRSV_NB) {
-        int kb = n - k0 < TRSV_NB ? n - k0 : TRSV_NB;
-        hipLaunchKernelGGL(k_bwd_diag, dim3(nrhs), dim3(64), 0, stream, LU, lda, n, k0,
-                           kb, X);
-        if (k0 > 0) {
-            dim3 g((k0 + 255) / 256, nrhs);
-            hipLaunchKernelGGL(k_bwd_update, g, dim3(256), 0, stream, LU, lda, n, k0, kb,
-                               X);
-        }
+    // backward: the last diagonal block, then per block the update of the
+    // rows above it together with the previous diagonal block
+    const int last0 = (n - 1) / TRSV_NB * TRSV_NB;
+    hipLaunchKernelGGL(k_bwd_diag, dim3(nrhs), dim3(64), 0, stream, LU, lda, n, last0,
+                       n - last0, X);
+    for (int k0 = last0; k0 > 0; k0 -= TRSV_NB) {
+        const int kb = n - k0 < TRSV_NB ? n - k0 : TRSV_NB;
+        dim3 g((k0 + 255) / 256, nrhs);
+        hipLaunchKernelGGL(k_bwd_update, g, dim3(256), 0, stream, LU, lda, n, k0, kb, X);
     }
     hipLaunchKernelGGL(k_copy_cols, gcol, dim3(256), 0, stream, X, n, B, ldb);
     EMU_TRY_HIP(hipGetLastError());
