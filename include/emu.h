@@ -73,6 +73,12 @@ extern "C" {
                                         exceeded its bound; those LU factors are
                                         invalid */
 
+#define EMU_STATUS_SOLVE_WAIT  4     /* a triangular solve (emu_dgetrs and the
+                                        solves inside emu_dgesv_ir, emu_refine)
+                                        gave up a wait between its blocks that
+                                        exceeded its bound; that solution is
+                                        invalid */
+
 /* Value an LU writes to its device *info when a multi-workgroup panel leaf
  * gave up its bounded grid-wide wait (the factors are then invalid; the
  * status word also carries EMU_STATUS_PANEL_WAIT).  Entry points that wait
@@ -277,7 +283,12 @@ size_t emu_potrf_workspace_bytes(int n, int nb, int nslices);
  * emu_dgetrs: solve A X = B (no transpose) with the factors of emu_dgetrf:
  * row interchanges, forward substitution with unit L, back substitution
  * with U, all FP64 (paper: eqn (5)).  LU n x n (lda >= max(1,n)), ipiv
- * device int32[n], B n x nrhs (ldb >= max(1,n)) overwritten with X.
+ * device int32[n], B n x nrhs (ldb >= max(1,n)) overwritten with X.  Each
+ * element receives its updates in the order of column-by-column
+ * substitution.  With at most four right-hand sides each sweep is one
+ * launch whose 64-row blocks wait for the earlier blocks' solutions (the
+ * wait is bounded: see EMU_STATUS_SOLVE_WAIT); with more, one launch per
+ * 64-row block and sweep.
  * Argument numbers: n=1 nrhs=2 LU=3 lda=4 ipiv=5 B=6 ldb=7.
  */
 int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,

@@ -24,6 +24,7 @@ __all__ = [
     "emu_version", "emu_init", "emu_finalize", "emu_set_stream", "emu_last_error",
     "emu_set_workspace", "emu_workspace_bytes", "emu_getrf_workspace_bytes",
     "emu_getrs_workspace_bytes", "set_workspace", "EMU_INFO_ABORTED", "EMU_ERR_PANEL_WAIT",
+    "EMU_STATUS_NONFINITE", "EMU_STATUS_PANEL_WAIT", "EMU_STATUS_SOLVE_WAIT",
     "emu_status", "emu_dgemm", "emu_dgemm_t", "emu_dgetrf", "emu_dgetrs",
     "emu_debug_slices", "emu_debug_products", "emu_profile_start",
     "emu_profile_stop", "emu_profile_read", "profile_read", "PROF_SLICE", "PROF_GEMM",
@@ -49,6 +50,9 @@ EMU_NOALLOC_SCRATCH_BYTES = 64 << 20
 EMU_ERR_NOT_CONVERGED = 1004
 EMU_ERR_PANEL_WAIT = 1005
 EMU_INFO_ABORTED = -1000
+EMU_STATUS_NONFINITE = 1
+EMU_STATUS_PANEL_WAIT = 2
+EMU_STATUS_SOLVE_WAIT = 4
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libemu.so")
 

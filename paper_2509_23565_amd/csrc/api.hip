@@ -303,9 +303,7 @@ static size_t getrf_scratch_bytes(int m, int n, int nb, int s) {
            laswp_plan_bytes(m);
 }
 
-static size_t getrs_scratch_bytes(int n, int nrhs) {
-    return align256((size_t)n * sizeof(int)) + align256((size_t)n * nrhs * sizeof(double));
-}
+static size_t getrs_scratch_bytes(int n, int nrhs) { return getrs_ws_bytes(n, nrhs); }
 
 // Right-looking blocked LU on reserved scratch `ws` (getrf_scratch_bytes).
 //
@@ -835,7 +833,8 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv, doub
     }
     Call c;
     EMU_TRY(c.begin(getrs_scratch_bytes(n, nrhs)));
-    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, reinterpret_cast<int *>(c.ws), c.st);
+    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, reinterpret_cast<int *>(c.ws), c.st,
+                        false, c.dev->status);
 }
 
 int emu_set_param(const char *key, long long value) {
@@ -965,7 +964,8 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
         }
         if (hinfo > 0) return 0;       // exactly singular U: nothing to refine
         EMU_TRY(launch_copy_mat(B, ldb, X, ldx, n, nrhs, st));
-        EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, X, ldx, reinterpret_cast<int *>(subws), st));
+        EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, X, ldx, reinterpret_cast<int *>(subws), st,
+                             false, dev->status));
         double prev = -1.0;
         bool fallback = false;
         for (int it = 0;; ++it) {
@@ -996,7 +996,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
             }
             prev = eta;
             EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, R, n, reinterpret_cast<int *>(subws), st,
-                                 true));
+                                 true, dev->status));
             EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
             ++total_iters;
         }
@@ -1074,7 +1074,7 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
         }
         prev = eta;
         EMU_TRY(launch_getrs(n, nrhs, LU, ldlu, ipiv, R, n, reinterpret_cast<int *>(ws + o_sub),
-                             st, it > 0));
+                             st, it > 0, dev->status));
         EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
     }
 }

@@ -296,9 +296,13 @@ int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
                      long long ldb, int ncols, hipStream_t stream);
 // perm_ws holds the composed row permutation after a call; perm_ready
 // reuses it (same factors) instead of composing it again.
+// status: the device status word; with it (and at most four right-hand
+// sides) each sweep runs as one persistent launch.
 int launch_getrs(int n, int nrhs, const double *LU, long long lda,
                  const int *ipiv, double *B, long long ldb, int *perm_ws,
-                 hipStream_t stream, bool perm_ready = false);
+                 hipStream_t stream, bool perm_ready = false, int *status = nullptr);
+// Scratch bytes of launch_getrs.
+size_t getrs_ws_bytes(int n, int nrhs);
 
 // Precision form (refine.hip).
 size_t refine_partial_bytes(int n, int nrhs);

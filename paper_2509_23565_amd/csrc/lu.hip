@@ -385,16 +385,190 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double *__restrict__ L
     x[i] = b;
 }
 
+// ------------------------------------------- persistent triangular solves
+// One launch per sweep for up to PT_RHS right-hand sides: one workgroup per
+// 64-row block, one wave per right-hand side.  A workgroup takes its place
+// in the sweep from a ticket (in the order workgroups start, so it waits
+// only on blocks held by workgroups already running: no deadlock whatever
+// the occupancy).  Each lane owns a row: it subtracts the earlier blocks'
+// contributions in sweep order as their solutions appear, 64 columns at a
+// time (the block's columns loaded before its solution is awaited), then the
+// wave resolves its own diagonal block in registers, with the block in LDS,
+// as the blocked kernels do, and publishes its 64 solutions as tagged
+// 64-bit words (32-bit payload, the sweep's tag in the high half, written by
+// relaxed stores and validated one by one, so one read follows the last
+// write).  Every element receives the same operations in the same order as
+// in the column-by-column substitution.  The wait is bounded: a wave that
+// exceeds PT_SPIN_LIMIT polls raises EMU_STATUS_SOLVE_WAIT and the abort
+// flag, and the waves still waiting leave; the solution is then invalid.
+constexpr int PT_RHS = 4;
+constexpr int PT_SPIN_LIMIT = 1 << 21;
+constexpr int PT_WORDS = 2 * TRSV_NB;                 // words per block and rhs
+
+__device__ __forceinline__ unsigned long long pt_load(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool FWD>
+__global__ __launch_bounds__(64 * PT_RHS) void k_trsv_persist(
+    const double *__restrict__ LU, long long lda, int n, int nrhs, double *__restrict__ X,
+    unsigned long long *__restrict__ words, int *__restrict__ ctr, int *__restrict__ status,
+    unsigned tag) {
+    extern __shared__ double Dsh[];                   // TRSV_NB^2 doubles per wave
+    __shared__ int s_q;
+    const int t = threadIdx.x, lane = t & 63;
+    const int r = __builtin_amdgcn_readfirstlane(t >> 6);   // right-hand side of this wave
+    if (t == 0) s_q = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    const int nblk = (n + TRSV_NB - 1) / TRSV_NB;
+    const int q = s_q;                                // place of this block in the sweep
+    if (q >= nblk || r >= nrhs) return;               // whole waves
+    const int blk = FWD ? q : nblk - 1 - q;
+    const int r0 = blk * TRSV_NB;
+    const int nb = n - r0 < TRSV_NB ? n - r0 : TRSV_NB;
+    const int i = r0 + lane;
+    double *x = X + (long long)r * n;
+    double *Ds = Dsh + (size_t)r * TRSV_NB * TRSV_NB;
+    // the diagonal block into LDS (lane i reads row i of every column)
+    {
+        double col[TRSV_NB];
+#pragma unroll
+        for (int k = 0; k < TRSV_NB; ++k)
+            col[k] = (k < nb && lane < nb) ? LU[i + (long long)(r0 + k) * lda] : 0.0;
+#pragma unroll
+        for (int k = 0; k < TRSV_NB; ++k) Ds[k * TRSV_NB + lane] = col[k];
+    }
+    double acc = lane < nb ? x[i] : 0.0;
+    const unsigned long long tg = (unsigned long long)tag << 32;
+    for (int p = 0; p < q; ++p) {
+        const int bj = FWD ? p : nblk - 1 - p;        // earlier block of the sweep
+        const int c0 = bj * TRSV_NB;
+        const int cb = n - c0 < TRSV_NB ? n - c0 : TRSV_NB;
+        double l[TRSV_NB];
+#pragma unroll
+        for (int k = 0; k < TRSV_NB; ++k)
+            l[k] = (lane < nb && k < cb) ? LU[i + (long long)(c0 + k) * lda] : 0.0;
+        const unsigned long long *wj = words + ((long long)bj * PT_RHS + r) * PT_WORDS;
+        unsigned long long w0 = 0ull, w1 = 0ull;
+        int spins = 0;
+        for (;;) {
+            if (lane < cb) {
+                w0 = pt_load(wj + 2 * lane);
+                w1 = pt_load(wj + 2 * lane + 1);
+            }
+            const bool ok = lane >= cb || ((w0 >> 32) == (tg >> 32) && (w1 >> 32) == (tg >> 32));
+            if (__ballot(!ok) == 0ull) break;
+            if ((++spins & 63) == 0) {
+                if (__hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                    return;
+                if (spins > PT_SPIN_LIMIT) {
+                    if (lane == 0) {
+                        __hip_atomic_store(&ctr[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_or(status, EMU_STATUS_SOLVE_WAIT, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    return;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        const double xv = __longlong_as_double(
+            (long long)(((w1 & 0xFFFFFFFFull) << 32) | (w0 & 0xFFFFFFFFull)));
+        if constexpr (FWD) {
+#pragma unroll
+            for (int k = 0; k < TRSV_NB; ++k) {
+                if (k < cb) {
+                    const double xk = lane_bcast(xv, k);
+                    acc = acc - l[k] * xk;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = TRSV_NB - 1; k >= 0; --k) {
+                if (k < cb) {
+                    const double xk = lane_bcast(xv, k);
+                    acc = acc - l[k] * xk;
+                }
+            }
+        }
+    }
+    if constexpr (FWD) {
+        for (int k = 0; k < nb - 1; ++k) {
+            const double xk = lane_bcast(acc, k);
+            if (lane > k && lane < nb) acc = acc - Ds[k * TRSV_NB + lane] * xk;
+        }
+    } else {
+        for (int k = nb - 1; k >= 0; --k) {
+            if (lane == k) acc = acc / Ds[k * TRSV_NB + k];
+            const double xk = lane_bcast(acc, k);
+            if (lane < k) acc = acc - Ds[k * TRSV_NB + lane] * xk;
+        }
+    }
+    if (lane < nb) {
+        x[i] = acc;
+        unsigned long long *wb = words + ((long long)blk * PT_RHS + r) * PT_WORDS;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+        __hip_atomic_store(wb + 2 * lane, tg | (bits & 0xFFFFFFFFull), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(wb + 2 * lane + 1, tg | (bits >> 32), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Scratch of launch_getrs: the permutation, X, and the persistent solves'
+// records and counters.
+static size_t getrs_words_bytes(int n) {
+    const size_t nblk = (size_t)(n + TRSV_NB - 1) / TRSV_NB;
+    return align256(nblk * PT_RHS * PT_WORDS * sizeof(unsigned long long));
+}
+
+size_t getrs_ws_bytes(int n, int nrhs) {
+    return align256((size_t)n * sizeof(int)) + align256((size_t)n * nrhs * sizeof(double)) +
+           getrs_words_bytes(n) + 256;
+}
+
 int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ipiv,
-                 double *B, long long ldb, int *perm_ws, hipStream_t stream, bool perm_ready) {
+                 double *B, long long ldb, int *perm_ws, hipStream_t stream, bool perm_ready,
+                 int *status) {
     if (n <= 0 || nrhs <= 0) return 0;
     int *perm = perm_ws;
-    double *X = reinterpret_cast<double *>(
-        reinterpret_cast<char *>(perm_ws) + align256((size_t)n * sizeof(int)));
+    char *base = reinterpret_cast<char *>(perm_ws);
+    double *X = reinterpret_cast<double *>(base + align256((size_t)n * sizeof(int)));
     if (!perm_ready)
         hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm);
     dim3 gcol((n + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_gather_rows, gcol, dim3(256), 0, stream, B, ldb, n, perm, X);
+    if (nrhs <= PT_RHS && status) {
+        char *wbase = base + align256((size_t)n * sizeof(int)) +
+                      align256((size_t)n * nrhs * sizeof(double));
+        unsigned long long *words = reinterpret_cast<unsigned long long *>(wbase);
+        int *ctr = reinterpret_cast<int *>(wbase + getrs_words_bytes(n));
+        const int nblk = (n + TRSV_NB - 1) / TRSV_NB;
+        // records (tag 0: not written) and both sweeps' tickets and abort flags
+        EMU_TRY(launch_fill_int(reinterpret_cast<int *>(words), 0,
+                                (int)(getrs_words_bytes(n) / sizeof(int)), stream));
+        EMU_TRY(launch_fill_int(ctr, 0, 4, stream));
+        const size_t lds = (size_t)nrhs * TRSV_NB * TRSV_NB * sizeof(double);
+        // up to PT_RHS diagonal blocks of dynamic LDS (128 KB): allowed once
+        static const hipError_t attr = [] {
+            const int mx = PT_RHS * TRSV_NB * TRSV_NB * (int)sizeof(double);
+            hipError_t e = hipFuncSetAttribute(
+                reinterpret_cast<const void *>(&k_trsv_persist<true>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trsv_persist<false>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+            return e;
+        }();
+        if (attr != hipSuccess) return fail_hip(attr, "hipFuncSetAttribute");
+        hipLaunchKernelGGL(k_trsv_persist<true>, dim3(nblk), dim3(64 * nrhs), lds, stream, LU,
+                           lda, n, nrhs, X, words, ctr, status, 1u);
+        hipLaunchKernelGGL(k_trsv_persist<false>, dim3(nblk), dim3(64 * nrhs), lds, stream,
+                           LU, lda, n, nrhs, X, words, ctr + 2, status, 2u);
+        hipLaunchKernelGGL(k_copy_cols, gcol, dim3(256), 0, stream, X, n, B, ldb);
+        EMU_TRY_HIP(hipGetLastError());
+        return 0;
+    }
     // forward: the first diagonal block, then per block the update of the
     // rows below it together with the next diagonal block
     hipLaunchKernelGGL(k_fwd_diag, dim3(nrhs), dim3(64), 0, stream, LU, lda, n, 0,

@@ -332,19 +332,22 @@ def test_getrs_bit_exact(n, nrhs):
     assert _same_bits(_host(Bg), x)
 
 
-@pytest.mark.parametrize("n", [2048, 2100])
-def test_getrs_bit_exact_large(n):
-    # many 64-row blocks, a ragged last block at n = 2100; synthetic factors
-    # (any LU array and valid pivots define a solve)
+@pytest.mark.parametrize("n,nrhs", [(2048, 2), (2100, 2), (4133, 1), (4133, 3), (4133, 4),
+                                    (4133, 5), (64, 4), (65, 1)])
+def test_getrs_bit_exact_large(n, nrhs):
+    # many 64-row blocks, ragged last blocks; one to four right-hand sides
+    # take the one-launch-per-sweep solves, five the per-block launches;
+    # synthetic factors (any LU array and valid pivots define a solve)
     g = matgen.rng(17, n)
     LU = np.asfortranarray(g.uniform(-1.0, 1.0, size=(n, n)))
     LU[np.diag_indices(n)] += float(n)
     piv = (np.arange(n) + (g.random(n) * (n - np.arange(n))).astype(np.int64)) + 1
-    B = matgen.uniform(n, 2, seed=18)
+    B = matgen.uniform(n, nrhs, seed=18)
     x = O.getrs(LU, piv, B)
     Bg = emu.colmajor(B)
     emu.dgetrs(emu.colmajor(LU), torch.as_tensor(piv.astype(np.int32), device="cuda"), Bg)
     assert _same_bits(_host(Bg), x)
+    assert emu.status() & emu.EMU_STATUS_SOLVE_WAIT == 0
 
 
 def test_getrf_singular_reports_info():
