@@ -318,8 +318,12 @@ static size_t getrs_scratch_bytes(int n, int nrhs) { return getrs_ws_bytes(n, nr
 // changes no bit).  The two updates of a step never overlap, so they share
 // the GEMM scratch; the panel's scratch is separate.
 static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, double *A,
-                      long long ld, int *ipiv, int *info, int nb, int s) {
+                      long long ld, int *ipiv, int *info, int nb, int s,
+                      int *perm = nullptr) {
     EMU_TRY(launch_fill_int(info, 0, 1, st));
+    // perm (optional, m ints): the row permutation, kept up to date from each
+    // panel's interchange plan
+    if (perm) EMU_TRY(launch_perm_init(perm, m, st));
     char *pws = ws + getrf_gemm_bytes(m, n, nb, s);
     int *plan = reinterpret_cast<int *>(pws + align256(panel_scratch_bytes(m)));
     const int mn = m < n ? m : n;
@@ -363,11 +367,12 @@ static int getrf_impl(Device *dev, char *ws, hipStream_t st, int m, int n, doubl
         // stream waits for the side stream before the next plan is made).
         const bool far_swaps = pivot && la && jn > 0 && j1 + jn < n && jb <= LASWP_CHUNK;
         if (far_swaps)
-            EMU_TRY(launch_laswp(A, ld, m, 0, j1, jn, ipiv, j0, j1, 0, plan, st));
+            EMU_TRY(launch_laswp(A, ld, m, 0, j1, jn, ipiv, j0, j1, 0, plan, st, perm));
         else if (pivot)
             for (int k1 = j0; k1 < j1; k1 += LASWP_CHUNK)
                 EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, k1,
-                                     k1 + LASWP_CHUNK < j1 ? k1 + LASWP_CHUNK : j1, 0, plan, st));
+                                     k1 + LASWP_CHUNK < j1 ? k1 + LASWP_CHUNK : j1, 0, plan, st,
+                                     perm));
         if (!la || jn == 0) {
             EMU_TRY(update(j0, jb, j1, n, st));
             if (jn > 0) EMU_TRY(panel(j1));
@@ -907,11 +912,14 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
         set_error("emu_dgesv_ir: nrhs above 65535");
         return EMU_ERR_UNSUPPORTED;
     }
-    // scratch: LU copy | ipiv | info | R | partials | norm + stats | LU/solve scratch
+    // scratch: LU copy | ipiv | row permutation | info | R | partials | norm +
+    // stats | LU/solve scratch
     size_t off = 0;
     const size_t o_lu = off;
     off += align256((size_t)n * n * sizeof(double));
     const size_t o_ipiv = off;
+    off += align256((size_t)n * sizeof(int));
+    const size_t o_perm = off;
     off += align256((size_t)n * sizeof(int));
     const size_t o_info = off;
     off += align256(sizeof(int));
@@ -936,6 +944,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     char *ws = call.ws;
     double *LU = reinterpret_cast<double *>(ws + o_lu);
     int *ipiv = reinterpret_cast<int *>(ws + o_ipiv);
+    int *perm = reinterpret_cast<int *>(ws + o_perm);
     int *dinfo = reinterpret_cast<int *>(ws + o_info);
     double *R = reinterpret_cast<double *>(ws + o_r);
     double *part = reinterpret_cast<double *>(ws + o_part);
@@ -952,7 +961,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     for (;;) {
         // factor a copy of A with s slices and solve
         EMU_TRY(launch_copy_mat(A, lda, LU, n, n, n, st));
-        EMU_TRY(getrf_impl(dev, subws, st, n, n, LU, n, ipiv, dinfo, nb, s));
+        EMU_TRY(getrf_impl(dev, subws, st, n, n, LU, n, ipiv, dinfo, nb, s, perm));
         int hinfo = 0;
         EMU_TRY_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, st));
         EMU_TRY_HIP(hipStreamSynchronize(st));
@@ -965,7 +974,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
         if (hinfo > 0) return 0;       // exactly singular U: nothing to refine
         EMU_TRY(launch_copy_mat(B, ldb, X, ldx, n, nrhs, st));
         EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, X, ldx, reinterpret_cast<int *>(subws), st,
-                             false, dev->status));
+                             false, dev->status, perm));
         double prev = -1.0;
         bool fallback = false;
         for (int it = 0;; ++it) {
@@ -996,7 +1005,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
             }
             prev = eta;
             EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, R, n, reinterpret_cast<int *>(subws), st,
-                                 true, dev->status));
+                                 true, dev->status, perm));
             EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
             ++total_iters;
         }

@@ -285,9 +285,13 @@ int native_syrk_update(int m, int k, const double *A, long long lda, double *C, 
 // Interchanges ipiv[k1..k2) on columns [0, ncols_left) and [col_right,
 // col_right + ncols_right); plan: laswp_plan_bytes(nrows) bytes of scratch.
 size_t laswp_plan_bytes(int nrows);
+// perm (optional, nrows ints): the row permutation so far, updated by these
+// interchanges (the plan is then made even when no other column moves).
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
                  int ncols_right, const int *ipiv, int k1, int k2, int row0, int *plan,
-                 hipStream_t stream);
+                 hipStream_t stream, int *perm = nullptr);
+// perm <- identity (n ints).
+int launch_perm_init(int *perm, int n, hipStream_t stream);
 // The apply step alone, with the plan a launch_laswp call of the same
 // (nrows, k1, k2) left in `plan` (ordered after it on the device).
 int launch_laswp_apply(double *A, long long lda, int nrows, int ncols_left, int col_right,
@@ -295,12 +299,14 @@ int launch_laswp_apply(double *A, long long lda, int nrows, int ncols_left, int 
 int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
                      long long ldb, int ncols, hipStream_t stream);
 // perm_ws holds the composed row permutation after a call; perm_ready
-// reuses it (same factors) instead of composing it again.
+// reuses it (same factors) instead of composing it again; perm_ext gives
+// the permutation itself (the factorization tracked it).
 // status: the device status word; with it (and at most four right-hand
 // sides) each sweep runs as one persistent launch.
 int launch_getrs(int n, int nrhs, const double *LU, long long lda,
                  const int *ipiv, double *B, long long ldb, int *perm_ws,
-                 hipStream_t stream, bool perm_ready = false, int *status = nullptr);
+                 hipStream_t stream, bool perm_ready = false, int *status = nullptr,
+                 const int *perm_ext = nullptr);
 // Scratch bytes of launch_getrs.
 size_t getrs_ws_bytes(int n, int nrhs);
 

@@ -184,11 +184,43 @@ __global__ __launch_bounds__(256) void k_swap_apply(double *__restrict__ A, long
     }
 }
 
+// perm[r] <- perm[source of r] for the rows a plan lists (all reads first):
+// the row permutation of a factorization, kept up to date panel by panel.
+__global__ __launch_bounds__(1024) void k_perm_apply(int *__restrict__ perm,
+                                                     const int *__restrict__ plan) {
+    const int nslot = plan[0];
+    int v[SW_SLOTS / 1024];
+#pragma unroll
+    for (int r = 0; r < SW_SLOTS / 1024; ++r) {
+        const int e = threadIdx.x + 1024 * r;
+        v[r] = e < nslot ? perm[plan[1 + SW_SLOTS + e]] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SW_SLOTS / 1024; ++r) {
+        const int e = threadIdx.x + 1024 * r;
+        if (e < nslot) perm[plan[1 + e]] = v[r];
+    }
+}
+
+__global__ void k_perm_init(int *__restrict__ perm, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = i;
+}
+
+int launch_perm_init(int *perm, int n, hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_perm_init, dim3((n + 255) / 256), dim3(256), 0, stream, perm, n);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
 int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_right,
                  int ncols_right, const int *ipiv, int k1, int k2, int row0, int *plan,
-                 hipStream_t stream) {
+                 hipStream_t stream, int *perm) {
     const int total = ncols_left + ncols_right;
-    if (total <= 0 || k2 <= k1 || nrows <= k1) return 0;
+    if (k2 <= k1 || nrows <= k1) return 0;
+    if (total <= 0 && !perm) return 0;
     if (k2 - k1 > SW_MAX) {
         set_error("more than %d interchanges in one call", SW_MAX);
         return EMU_ERR_UNSUPPORTED;
@@ -197,6 +229,7 @@ int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_ri
                                          align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int)));
     hipLaunchKernelGGL(k_swap_plan, dim3(1), dim3(64), 0, stream, ipiv, k1, k2, nrows, row0,
                        plan, gperm);
+    if (perm) hipLaunchKernelGGL(k_perm_apply, dim3(1), dim3(1024), 0, stream, perm, plan);
     return launch_laswp_apply(A, lda, nrows, ncols_left, col_right, ncols_right, k1, k2, plan,
                               stream);
 }
@@ -529,13 +562,13 @@ size_t getrs_ws_bytes(int n, int nrhs) {
 
 int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ipiv,
                  double *B, long long ldb, int *perm_ws, hipStream_t stream, bool perm_ready,
-                 int *status) {
+                 int *status, const int *perm_ext) {
     if (n <= 0 || nrhs <= 0) return 0;
-    int *perm = perm_ws;
+    const int *perm = perm_ext ? perm_ext : perm_ws;
     char *base = reinterpret_cast<char *>(perm_ws);
     double *X = reinterpret_cast<double *>(base + align256((size_t)n * sizeof(int)));
-    if (!perm_ready)
-        hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm);
+    if (!perm_ready && !perm_ext)
+        hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm_ws);
     dim3 gcol((n + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_gather_rows, gcol, dim3(256), 0, stream, B, ldb, n, perm, X);
     if (nrhs <= PT_RHS && status) {
