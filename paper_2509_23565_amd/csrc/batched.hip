@@ -710,10 +710,17 @@ struct BCopy {
 
 __global__ __launch_bounds__(256) void k_bcopy(const BCopy *__restrict__ jobs) {
     const BCopy J = jobs[blockIdx.x];
-    const long long total = (long long)J.rows * J.cols;
-    for (long long e = threadIdx.x; e < total; e += blockDim.x) {
-        const int i = (int)(e % J.rows), j = (int)(e / J.rows);
-        J.dst[i + (long long)j * J.ldd] = J.src[i + (long long)j * J.lds];
+    // four columns per pass, all loads of a pass before its stores
+    for (int j0 = 0; j0 < J.cols; j0 += 4) {
+        for (int i = threadIdx.x; i < J.rows; i += 256) {
+            double v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[c] = j0 + c < J.cols ? J.src[i + (long long)(j0 + c) * J.lds] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (j0 + c < J.cols) J.dst[i + (long long)(j0 + c) * J.ldd] = v[c];
+        }
     }
 }
 
@@ -731,23 +738,44 @@ __global__ __launch_bounds__(256) void k_bresid(const BIr *__restrict__ sys,
     double mA = 0.0, mR[BMAX_RHS], mX[BMAX_RHS], mB[BMAX_RHS];
 #pragma unroll
     for (int r = 0; r < BMAX_RHS; ++r) mR[r] = mX[r] = mB[r] = 0.0;
-    for (int i = t; i < n; i += blockDim.x) {
-        double ax[BMAX_RHS], ra = 0.0;
+    // the thread's rows i = t + 256 q walk the columns together, so their
+    // loads are in flight at once; each row's sums run over j in order
+    constexpr int RPT = BMAX_N / 256;
+    double ax[RPT][BMAX_RHS], ra[RPT];
 #pragma unroll
-        for (int r = 0; r < BMAX_RHS; ++r) ax[r] = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const double a = S.A[i + (long long)j * S.lda];
-            ra += fabs(a);
+    for (int q = 0; q < RPT; ++q) {
+        ra[q] = 0.0;
+#pragma unroll
+        for (int r = 0; r < BMAX_RHS; ++r) ax[q][r] = 0.0;
+    }
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) {
+        double a[RPT], xv[BMAX_RHS];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = t + 256 * q;
+            a[q] = i < n ? S.A[i + (long long)j * S.lda] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < BMAX_RHS; ++r) xv[r] = r < nr ? xs[r * BMAX_N + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            ra[q] += fabs(a[q]);
 #pragma unroll
             for (int r = 0; r < BMAX_RHS; ++r)
-                if (r < nr) ax[r] = fma(a, xs[r * BMAX_N + j], ax[r]);
+                if (r < nr) ax[q][r] = fma(a[q], xv[r], ax[q][r]);
         }
-        mA = fmax(mA, ra);
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = t + 256 * q;
+        if (i >= n) continue;
+        mA = fmax(mA, ra[q]);
 #pragma unroll
         for (int r = 0; r < BMAX_RHS; ++r) {
             if (r < nr) {
                 const double b = S.B[i + (long long)r * S.ldb];
-                const double rv = b - ax[r];
+                const double rv = b - ax[q][r];
                 S.R[i + (long long)r * n] = rv;
                 mR[r] = (rv != rv || mR[r] != mR[r]) ? __builtin_nan("") : fmax(mR[r], fabs(rv));
                 mX[r] = fmax(mX[r], fabs(xs[r * BMAX_N + i]));
