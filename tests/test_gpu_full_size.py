@@ -13,14 +13,20 @@ cannot repeat the whole factorization; properties that hold at any size:
   from wrong operands give errors many orders larger);
 * the look-ahead (updates on a second stream) changes no bit of the factors;
 * the precision form (three slices and FP64 refinement) reaches 1e-15 in
-  the same double-double measure.
+  the same double-double measure;
+* the benchmark's batch (2000 systems, n ~ U{64..1024}, phi ~ U(0, 4), 1-8
+  right-hand sides, seed 0): the plain batched solve is bit-identical to
+  the oracle's LU and solve on sampled systems (the first, the last and the
+  largest), and the batched precision form brings every system to 1e-15.
 
-Inputs: U(-1, 1) entries from a seeded torch generator on the GPU.
+Inputs: U(-1, 1) entries from a seeded torch generator on the GPU; the
+batch from the seeded host generators.
 """
 import numpy as np
 import pytest
 import torch
 
+import matgen
 import oracle as O
 import paper_2509_23565_amd as emu
 
@@ -85,3 +91,30 @@ def test_precision_form_full_size_reaches_1e15():
     eta = _sampled_eta(A, X, b, seed=12)
     print(f"n={n} s=3 + IR: {inf['iters']} steps, s_final {inf['s_final']}, sampled eta {eta:.2e}")
     assert eta <= 1e-15
+
+
+def _same_bits(a, b):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    return a.shape == b.shape and np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+def test_batched_full_batch():
+    specs = matgen.batched_specs(2000, seed=0)
+    As = [matgen.phi_matrix(n, n, phi, seed=0, substream=1000 + i)
+          for i, (n, phi, r) in enumerate(specs)]
+    Bs = [matgen.uniform(n, r, seed=0, substream=5000 + i) for i, (n, phi, r) in enumerate(specs)]
+    Ag = [emu.colmajor(a) for a in As]
+    Bg = [emu.colmajor(b) for b in Bs]
+    # precision form first (inputs untouched), then the plain solve in place
+    Xs, inf = emu.dgesv_batched_ir(Ag, Bg, nb=32, nslices=5, tol=1e-15)
+    assert inf["rc"] == 0 and max(inf["berr"]) <= 1e-15 and not any(inf["info"])
+    ipivs, info = emu.dgesv_batched(Ag, Bg, nb=32, nslices=7)
+    torch.cuda.synchronize()
+    assert not info.cpu().numpy().any()
+    largest = max(range(len(specs)), key=lambda i: specs[i][0])
+    for i in (0, largest, len(specs) - 1):
+        LU, piv, _ = O.getrf(As[i], nb=32, s=7)
+        assert np.array_equal(ipivs[i].cpu().numpy(), piv), i
+        assert _same_bits(Ag[i].cpu().numpy(), LU), i
+        assert _same_bits(Bg[i].cpu().numpy(), O.getrs(LU, piv, Bs[i])), i
