@@ -631,8 +631,10 @@ def main():
                     help="skip the learned slice-count leg (training on n = 8192 and "
                          "16384 emulated LUs, evaluation on an n = 16384 solve)")
     ap.add_argument("--lu-trace", type=str, default="",
-                    help="N,NB,S[,ir|,batch]: only factor one N x N phi=1 matrix twice "
-                         "with emu_dgetrf (block NB, S slices); with ',ir' solve the "
+                    help="N,NB,S[,ir|,batch|,learned]: only factor one N x N phi=1 matrix "
+                         "twice with emu_dgetrf (block NB, S slices); with ',learned' "
+                         "factor a phi=4 matrix twice with emu_dgetrf_adaptive (a model "
+                         "trained briefly, S the full count); with ',ir' solve the "
                          "precision-form kappa=1e2 system twice with emu_dgesv_ir; with "
                          "',batch' solve N systems of the batched workload twice with "
                          "emu_dgesv_batched; then exit (for kernel traces)")
@@ -670,6 +672,19 @@ def main():
             for _ in range(2):
                 emu.dgesv_batched([a.clone() for a in As], [b.clone() for b in Bs], nb=lnb,
                                   nslices=ls)
+        elif len(fields) > 3 and fields[3] == "learned":
+            # a model trained briefly on one phi = 6 matrix of n = 8192, then
+            # the adaptive LU of an ln x ln phi = 4 matrix, twice
+            from paper_2509_23565_amd import learned
+            Mt = _gpu_phi(torch, 8192, 6.0, 2000)
+            X, y = learned.training_set([Mt], nb=256, max_steps=12)
+            del Mt
+            params, _ = learned.train(X, y, steps=200)
+            Al = _gpu_phi(torch, ln, 4.0, 3001)
+            torch.cuda.synchronize()
+            print("trained", flush=True)
+            for _ in range(2):
+                emu.dgetrf_adaptive(Al.clone(), params, nb=lnb, s_full=ls)
         elif len(fields) > 3 and fields[3] == "ir":
             Al = emu.colmajor(matgen.kappa_matrix(ln, 1.0, 1e2, seed=args.seed))
             bl = emu.colmajor(matgen.uniform(ln, 1, seed=args.seed, substream=1))

@@ -1264,12 +1264,13 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     const int jb0 = nb < mn ? nb : mn;
     const int M0 = m - jb0 > 0 ? m - jb0 : 1, N0 = n - jb0 > 0 ? n - jb0 : 1;
     const int tm0 = (M0 + 255) / 256, tn0 = (N0 + 255) / 256, nt0 = tm0 * tn0;
-    // scratch: getrf pieces | features | probs | smap | tile problems | prefix
+    // scratch: getrf pieces | line statistics (rows of L21, columns of U12)
+    // | features | probs | smap | tile problems | prefix
     size_t off = 0;
     const size_t o_lu = off;
     off += align256(getrf_scratch_bytes(m, n, nb, s_full));
     const size_t o_fs = off;
-    off += align256(features_ws_bytes(M0, N0));
+    off += align256(align256(feat_stat_bytes(M0)) + feat_stat_bytes(N0));
     const size_t o_feat = off;
     off += align256((size_t)nt0 * 16 * sizeof(float));
     const size_t o_prob = off;
@@ -1313,10 +1314,14 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     // problem lists, the operands are sliced once at s_full (a tile of
     // count s reads the first s digit planes: truncated digits are prefixes
     // of each other), and one grouped launch per count s runs its tiles
-    // (an empty list ends at once).  Look-ahead as in the plain LU: the
-    // tiles over the next panel's columns are updated first, the others on
-    // the side stream while the next panel is factored (each tile receives
-    // the same operations either way).  The maps are copied back at the end.
+    // (an empty list ends at once).  Look-ahead as in the plain LU: the tile
+    // columns holding the next panel's columns ("part 0") take the
+    // interchanges, the TRSM, their features, map, slicing and update on
+    // this stream, and the next panel follows at once; the other columns
+    // ("part 1") take the same steps on the side stream meanwhile.  Features
+    // are per row of L21 and per column of U12, exponents likewise, so each
+    // tile receives the same operations and the same slice count either
+    // way.  The maps are copied back at the end.
     struct StepTiles {
         int M, N, tm, nt;
         long long rec;
@@ -1331,6 +1336,8 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     const bool la_on = g_lu_lookahead != 0 && mn > nb;
     ThreadCtx *tc = thread_ctx(dev);
     if (la_on) EMU_TRY(side_stream(tc));
+    char *rstat = ws + o_fs;
+    char *cstat = rstat + align256(feat_stat_bytes(M0));
     auto panel = [&](int j0) -> int {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         return launch_panel(A + j0 + (long long)j0 * ld, ld, m - j0, jb, ipiv + j0, j0, info,
@@ -1360,51 +1367,74 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
         const int j1 = j0 + jb;
         const int jn = j1 < mn ? (nb < mn - j1 ? nb : mn - j1) : 0;   // next panel
         double *Ajj = A + j0 + (long long)j0 * ld;
-        EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
-        if (j1 >= n) {
-            if (jn > 0) EMU_TRY(panel(j1));
-            continue;
-        }
-        double *U12 = A + j0 + (long long)j1 * ld;
-        EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U12, ld, n - j1, st));
-        if (j1 >= m) {                 // no rows below the panel (then jn = 0)
+        if (j1 >= n || j1 >= m) {
+            // no update (no columns right of the panel, or no rows below it)
+            EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
+            if (j1 < n)
+                EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, A + j0 + (long long)j1 * ld, ld, n - j1,
+                                         st));
             if (jn > 0) EMU_TRY(panel(j1));
             continue;
         }
         const int M = m - j1, N = n - j1;
         const double *L21 = A + j1 + (long long)j0 * ld;
         const int tm = (M + 255) / 256, tn = (N + 255) / 256, nt = tm * tn;
-        EMU_TRY(launch_features(L21, ld, U12, ld, M, N, jb, feat, ws + o_fs, st));
-        EMU_TRY(launch_mlp_infer(params, feat, nt, prob, smap, conf, st));
-        EMU_TRY_HIP(hipMemcpyAsync(drec + rec, smap, nt * sizeof(int), hipMemcpyDeviceToDevice,
-                                   st));
-        steps.push_back({M, N, tm, nt, rec});
-        rec += nt;
-        GemmScratch g = gemm_scratch(M, N, jb, s_full, s_full + 1);
-        int *codeA = reinterpret_cast<int *>(lws + g.off_codeA);
-        int *codeB = reinterpret_cast<int *>(lws + g.off_codeB);
-        int8_t *pa = reinterpret_cast<int8_t *>(lws + g.off_pa);
-        int8_t *pb = reinterpret_cast<int8_t *>(lws + g.off_pb);
-        EMU_TRY(launch_slice(L21, ld, 1, g.ga, s_full, codeA, pa, dev->status, st));
-        EMU_TRY(launch_slice(U12, ld, 0, g.gb, s_full, codeB, pb, dev->status, st));
-        AdaptiveTiles at{pa, pb, g.ga.plane_bytes, g.gb.plane_bytes, g.ga.KB, codeA, codeB,
-                         A + j1 + (long long)j1 * ld, ld, M, N, tm};
-        // tile columns holding the next panel's columns
+        // part 0: tile columns [0, jsplit) holding the next panel's columns
         const int jla = (jn + 255) / 256;
         const bool la = la_on && jn > 0 && jla < tn;
         const int jsplit = la ? jla : tn;
-        EMU_TRY(launch_adaptive_lists(smap, nt, s_full, at, 0, jsplit, dprob, dpre, dcnt, st));
-        if (la)
-            EMU_TRY(launch_adaptive_lists(smap, nt, s_full, at, jsplit, tn,
-                                          dprob + (size_t)9 * nt0, dpre + (size_t)9 * (nt0 + 1),
-                                          dcnt + 18, st));
-        EMU_TRY(gemms(0, nt, st));
+        const int c_split = la ? jsplit * 256 : N;
+        steps.push_back({M, N, tm, nt, rec});
+        GemmScratch g = gemm_scratch(M, N, jb, s_full, s_full + 1);
+        int *codeA = reinterpret_cast<int *>(lws + g.off_codeA);
+        int8_t *pa = reinterpret_cast<int8_t *>(lws + g.off_pa);
+        // Interchanges, TRSM, features, map, slicing and update of the
+        // columns [c0, c0 + nc) of U12 (tile columns from c0 / 256 on), on
+        // stream sx; L21's statistics and digits are ready.  The part's B
+        // digits and codes sit after those of the columns before it.
+        auto part = [&](int p, int c0, int nc, hipStream_t sx) -> int {
+            double *U = A + j0 + (long long)(j1 + c0) * ld;
+            EMU_TRY(launch_trsm_llnu(Ajj, ld, jb, U, ld, nc, sx));
+            const int q0 = (c0 / 256) * tm, ntp = tm * ((nc + 255) / 256);
+            char *cs = cstat + feat_stat_bytes(c0);
+            EMU_TRY(launch_feat_lines(U, ld, nc, jb, 0, cs, sx));
+            EMU_TRY(launch_feat_tiles(rstat, cs, M, nc, feat + (size_t)q0 * 16, sx));
+            EMU_TRY(launch_mlp_infer(params, feat + (size_t)q0 * 16, ntp, prob + (size_t)q0 * 7,
+                                     smap + q0, conf, sx));
+            EMU_TRY_HIP(hipMemcpyAsync(drec + rec + q0, smap + q0, ntp * sizeof(int),
+                                       hipMemcpyDeviceToDevice, sx));
+            const Planes gb = plane_geom(nc, jb);
+            const Planes g0 = plane_geom(c0, jb);
+            int *codeB = reinterpret_cast<int *>(lws + g.off_codeB) + c0;
+            int8_t *pb = reinterpret_cast<int8_t *>(lws + g.off_pb) +
+                         (c0 > 0 ? (size_t)s_full * g0.plane_bytes : 0);
+            EMU_TRY(launch_slice(U, ld, 0, gb, s_full, codeB, pb, dev->status, sx));
+            AdaptiveTiles at{pa, pb, g.ga.plane_bytes, gb.plane_bytes, g.ga.KB, codeA, codeB,
+                             A + j1 + (long long)(j1 + c0) * ld, ld, M, nc, tm};
+            EMU_TRY(launch_adaptive_lists(smap + q0, ntp, s_full, at, 0, (nc + 255) / 256,
+                                          dprob + (size_t)p * 9 * nt0,
+                                          dpre + (size_t)p * 9 * (nt0 + 1), dcnt + 18 * p, sx));
+            return gemms(p, ntp, sx);
+        };
+        if (la) {
+            // part 0's columns take the interchanges now, the rest on the side
+            // stream (the plan stays valid until this stream waits for it)
+            EMU_TRY(launch_laswp(A, ld, m, 0, j1, c_split, ipiv, j0, j1, 0, plan, st));
+        } else {
+            EMU_TRY(launch_laswp(A, ld, m, j0, j1, n - j1, ipiv, j0, j1, 0, plan, st));
+        }
+        EMU_TRY(launch_feat_lines(L21, ld, M, jb, 1, rstat, st));
+        EMU_TRY(launch_slice(L21, ld, 1, g.ga, s_full, codeA, pa, dev->status, st));
+        EMU_TRY(part(0, 0, c_split, st));
         if (la) {
             EMU_TRY_HIP(hipEventRecord(tc->ev_go, st));
             EMU_TRY_HIP(hipStreamWaitEvent(tc->side, tc->ev_go, 0));
-            EMU_TRY(gemms(1, nt, tc->side));
+            EMU_TRY(launch_laswp_apply(A, ld, m, j0, j1 + c_split, N - c_split, j0, j1, plan,
+                                       tc->side));
+            EMU_TRY(part(1, c_split, N - c_split, tc->side));
             EMU_TRY_HIP(hipEventRecord(tc->ev_done, tc->side));
         }
+        rec += nt;
         if (jn > 0) EMU_TRY(panel(j1));
         if (la) EMU_TRY_HIP(hipStreamWaitEvent(st, tc->ev_done, 0));
     }

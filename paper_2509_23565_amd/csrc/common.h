@@ -325,6 +325,14 @@ int launch_copy_mat(const double *src, long long lds_, double *dst, long long ld
 // Learned slice count (learned.hip).
 int learned_nparam();
 size_t features_ws_bytes(int m, int n);
+// line statistics of `lines` rows (by_rows) or columns of an operand with
+// k elements per line; tile features of an m x n update from the row and
+// column statistics (tile (I, J) at I + J ceil(m / 256))
+size_t feat_stat_bytes(int lines);
+int launch_feat_lines(const double *X, long long ldx, int lines, int k, int by_rows,
+                      void *stats, hipStream_t st);
+int launch_feat_tiles(const void *row_stats, const void *col_stats, int m, int n, float *feat,
+                      hipStream_t st);
 int launch_features(const double *L21, long long ldl, const double *U12, long long ldu, int m,
                     int n, int k, float *feat, void *stat_ws, hipStream_t st);
 size_t mlp_train_ws_bytes(int B);

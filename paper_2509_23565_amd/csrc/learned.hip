@@ -46,18 +46,22 @@ __device__ __forceinline__ int fexp(double x) {   // frexp exponent (x != 0, fin
 
 __device__ __forceinline__ bool usable(double x) { return x != 0.0 && isfinite(x); }
 
-// Statistics of one block of up to 256 lines of an operand.  by_rows: lines
-// are rows of X (rows x k), else columns of X (k x cols).  Four threads per
-// line, each over a quarter of K with eight loads in flight: the line's
-// largest exponent first (combined through LDS), then the integer sums.
+// Statistics of one block of up to FL = 64 lines of an operand (a feature
+// tile's 256 lines are four such blocks, combined exactly when the tile's
+// features are formed).  by_rows: lines are rows of X (rows x k), else
+// columns of X (k x cols).  Four threads per line, each over a quarter of K
+// with eight loads in flight: the line's largest exponent first (combined
+// through LDS), then the integer sums.
+constexpr int FL = 64;
 constexpr int FQ = 4;
-__global__ __launch_bounds__(FT * FQ) void k_feat_lines(const double *__restrict__ X,
+static_assert(FT % FL == 0, "line blocks tile a feature tile");
+__global__ __launch_bounds__(FL * FQ) void k_feat_lines(const double *__restrict__ X,
                                                         long long ldx, int lines, int k,
                                                         int by_rows, Stat *__restrict__ out) {
     __shared__ long long s_cnt, s_sum, s_sq;
     __shared__ int s_mn, s_mx, s_hist[NBIN];
-    __shared__ int s_e[FQ][FT];
-    const int t = threadIdx.x, tl = t % FT, qk = t / FT;
+    __shared__ int s_e[FQ][FL];
+    const int t = threadIdx.x, tl = t % FL, qk = t / FL;
     if (t == 0) {
         s_cnt = 0;
         s_sum = 0;
@@ -66,7 +70,7 @@ __global__ __launch_bounds__(FT * FQ) void k_feat_lines(const double *__restrict
         s_mx = INT_MIN;
     }
     if (t < NBIN) s_hist[t] = 0;
-    const int line = blockIdx.x * FT + tl;
+    const int line = blockIdx.x * FL + tl;
     const int kq = (k + FQ - 1) / FQ, k0 = qk * kq, k1 = min(k, k0 + kq);
     auto load8 = [&](int kk0, double (&xv)[8]) {
 #pragma unroll
@@ -136,27 +140,42 @@ __global__ __launch_bounds__(FT * FQ) void k_feat_lines(const double *__restrict
     }
 }
 
-// Tile (I, J) features from row block I of L21 and column block J of U12.
-__global__ void k_feat_tiles(const Stat *__restrict__ rs, const Stat *__restrict__ cs, int tiles_m,
-                             int tiles_n, float *__restrict__ feat) {
+// Tile (I, J) features from the line blocks of row block I of L21 (m rows)
+// and of column block J of U12 (n columns): integer sums, then the floats.
+__global__ void k_feat_tiles(const Stat *__restrict__ rs, const Stat *__restrict__ cs, int m,
+                             int n, float *__restrict__ feat) {
+    const int tiles_m = (m + FT - 1) / FT, tiles_n = (n + FT - 1) / FT;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= tiles_m * tiles_n) return;
     const int I = idx % tiles_m, J = idx / tiles_m;
-    const Stat &a = rs[I], &b = cs[J];
-    const long long cnt = a.cnt + b.cnt;
+    constexpr int PER = FT / FL;
+    const int nr = (m + FL - 1) / FL, nc = (n + FL - 1) / FL;
+    long long cnt = 0, sum = 0, sq = 0;
+    int mn = INT_MAX, mx = INT_MIN;
+    long long hist[NBIN] = {};
+    auto take = [&](const Stat &a) {
+        cnt += a.cnt;
+        sum += a.sum;
+        sq += a.sumsq;
+        mn = min(mn, a.mn);
+        mx = max(mx, a.mx);
+        for (int q = 0; q < NBIN; ++q) hist[q] += a.hist[q];
+    };
+    for (int b = I * PER; b < min(nr, (I + 1) * PER); ++b) take(rs[b]);
+    for (int b = J * PER; b < min(nc, (J + 1) * PER); ++b) take(cs[b]);
     float *f = feat + (long long)idx * NFEAT;
     if (cnt == 0) {
         for (int q = 0; q < NFEAT; ++q) f[q] = 0.0f;
         return;
     }
     const double c = (double)cnt;
-    const double mean = (double)(a.sum + b.sum) / c;
-    const double var = (double)(a.sumsq + b.sumsq) / c - mean * mean;
-    f[0] = (float)min(a.mn, b.mn);
-    f[1] = (float)max(a.mx, b.mx);
+    const double mean = (double)sum / c;
+    const double var = (double)sq / c - mean * mean;
+    f[0] = (float)mn;
+    f[1] = (float)mx;
     f[2] = (float)mean;
     f[3] = (float)sqrt(var > 0.0 ? var : 0.0);
-    for (int q = 0; q < NBIN; ++q) f[4 + q] = (float)((double)(a.hist[q] + b.hist[q]) / c);
+    for (int q = 0; q < NBIN; ++q) f[4 + q] = (float)((double)hist[q] / c);
 }
 
 // ------------------------------------------------------------------- MLP
@@ -449,22 +468,38 @@ int launch_adaptive_lists(const int *smap, int nt, int s_cap, const AdaptiveTile
     return 0;
 }
 
-int launch_features(const double *L21, long long ldl, const double *U12, long long ldu, int m,
-                    int n, int k, float *feat, void *stat_ws, hipStream_t st) {
-    const int tm = (m + FT - 1) / FT, tn = (n + FT - 1) / FT;
-    Stat *rs = static_cast<Stat *>(stat_ws);
-    Stat *cs = rs + tm;
-    hipLaunchKernelGGL(k_feat_lines, dim3(tm), dim3(FT * FQ), 0, st, L21, ldl, m, k, 1, rs);
-    hipLaunchKernelGGL(k_feat_lines, dim3(tn), dim3(FT * FQ), 0, st, U12, ldu, n, k, 0, cs);
-    hipLaunchKernelGGL(k_feat_tiles, dim3((tm * tn + 255) / 256), dim3(256), 0, st, rs, cs, tm,
-                       tn, feat);
+size_t feat_stat_bytes(int lines) { return sizeof(Stat) * (size_t)((lines + FL - 1) / FL); }
+
+int launch_feat_lines(const double *X, long long ldx, int lines, int k, int by_rows,
+                      void *stats, hipStream_t st) {
+    if (lines <= 0) return 0;
+    hipLaunchKernelGGL(k_feat_lines, dim3((lines + FL - 1) / FL), dim3(FL * FQ), 0, st, X, ldx,
+                       lines, k, by_rows, static_cast<Stat *>(stats));
     EMU_TRY_HIP(hipGetLastError());
     return 0;
 }
 
-size_t features_ws_bytes(int m, int n) {
-    return sizeof(Stat) * (size_t)((m + FT - 1) / FT + (n + FT - 1) / FT);
+int launch_feat_tiles(const void *row_stats, const void *col_stats, int m, int n, float *feat,
+                      hipStream_t st) {
+    const int nt = ((m + FT - 1) / FT) * ((n + FT - 1) / FT);
+    if (nt <= 0) return 0;
+    hipLaunchKernelGGL(k_feat_tiles, dim3((nt + 255) / 256), dim3(256), 0, st,
+                       static_cast<const Stat *>(row_stats), static_cast<const Stat *>(col_stats),
+                       m, n, feat);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
 }
+
+int launch_features(const double *L21, long long ldl, const double *U12, long long ldu, int m,
+                    int n, int k, float *feat, void *stat_ws, hipStream_t st) {
+    char *rs = static_cast<char *>(stat_ws);
+    char *cs = rs + feat_stat_bytes(m);
+    EMU_TRY(launch_feat_lines(L21, ldl, m, k, 1, rs, st));
+    EMU_TRY(launch_feat_lines(U12, ldu, n, k, 0, cs, st));
+    return launch_feat_tiles(rs, cs, m, n, feat, st);
+}
+
+size_t features_ws_bytes(int m, int n) { return feat_stat_bytes(m) + feat_stat_bytes(n); }
 
 size_t mlp_train_ws_bytes(int B) {
     return sizeof(float) * (size_t)B * (4 * H + NCLS + NCLS + 1) + sizeof(float) * NPARAM;

@@ -11,43 +11,89 @@
 
 namespace emu {
 
-// Orders the LDS / memory accesses of one wave's lanes around it.
-__device__ __forceinline__ void wave_sync_mem() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // ------------------------------------------------- composed interchanges
-// A run of row interchanges (c <-> p_c, c increasing, p_c >= c) is
-// sequential by definition.  One wave composes it into a permutation pm of
-// the rows it touches, 32 interchanges at a time: the 32 interchanges of a
-// block touch at most 64 rows, which get one lane ("slot") each; the swaps
-// are replayed on the slot contents with lane broadcasts, and the block's
-// net effect is applied to pm in one gather/scatter.  pm[r] is the row
-// whose old contents end up in row r (rows relative to the run's first).
-// Pivot c is piv[c] - 1 - piv_base relative to that row; values outside
-// [c, R) mean no interchange.
-__device__ void compose_interchanges(int *pm, int R, int J, const int *__restrict__ piv,
-                                     int piv_base) {
-    const int lane = threadIdx.x & 63;
-    // the pivots of the next block are loaded while this one is composed
-    int raw = lane < 32 && lane < J ? piv[lane] : 0;
-    for (int k0 = 0; k0 < J; k0 += 32) {
-        const int w = J - k0 < 32 ? J - k0 : 32;
-        int pk = -1;                                 // pivot of k0 + lane, relative to k0
-        if (lane < w) {
-            pk = raw - 1 - piv_base - k0;
-            if (pk < lane || pk >= R - k0) pk = lane;
+// A run of row interchanges (step c swaps rows c and p_c, c increasing,
+// p_c >= c) is sequential by definition, but its result has a closed form
+// that a workgroup evaluates in parallel.  Step c only touches rows c and
+// p_c >= c, so row c is final after step c and receives what row p_c held
+// just before it.  Let g(j) be what row j holds just before step j: the
+// content that the last earlier step i < j with p_i = j moved there, which
+// is g(i), or j itself if there is no such step.  Then
+//   row c (in the run)     ends with g(i) for the last i < c with p_i = p_c,
+//                          or p_c if there is none;
+//   row y below the run    ends with g(i) for the last i with p_i = y.
+// The steps are sorted by (p_c, c) (bitonic, in LDS), which lines up each
+// step with the previous one of the same target; g follows chains of
+// strictly decreasing rows and is resolved by pointer jumping.  Rows are
+// relative to the run's first; pivot c is piv[c] - 1 - base relative to it,
+// and a value outside [c, R) means no interchange.
+constexpr int CW = 1024;                     // steps per composition (threads)
+
+struct ComposeLds {
+    unsigned long long key[CW];              // (target << 32) | step, sorted
+    int pred[CW];                            // last earlier step of the same target
+    int g[CW];                               // chain links, then g(row)
+};
+
+// Thread c gets in blk the row whose old contents end in row c (c < min(J,
+// R); c itself if unchanged), and, if it holds the last step into a row y
+// below the run (y >= min(J, R)), ty = y and tsrc = the row whose old
+// contents end there (else ty = -1).  All CW threads call it.
+__device__ void wg_compose(const int *__restrict__ piv, int J, int R, int base, ComposeLds &L,
+                           int &blk, int &ty, int &tsrc) {
+    const int c = threadIdx.x;
+    const int Jr = J < R ? J : R;
+    int p = c;
+    if (c < Jr) {
+        p = piv[c] - 1 - base;
+        if (p < c || p >= R) p = c;
+    }
+    L.key[c] = c < Jr ? ((unsigned long long)(unsigned)p << 32) | (unsigned)c : ~0ull;
+    L.g[c] = c;
+    __syncthreads();
+    for (int size = 2; size <= CW; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int o = c ^ stride;
+            if (o > c) {
+                const unsigned long long x = L.key[c], y = L.key[o];
+                if ((x > y) == ((c & size) == 0)) {
+                    L.key[c] = y;
+                    L.key[o] = x;
+                }
+            }
+            __syncthreads();
         }
-        raw = lane < 32 && k0 + 32 + lane < J ? piv[k0 + 32 + lane] : 0;
-        int srow, content;
-        const int nslot = wave_compose32(pk, w, srow, content);
-        int v = 0;
-        if (lane < nslot) v = pm[k0 + content];
-        wave_sync_mem();
-        if (lane < nslot) pm[k0 + srow] = v;
-        wave_sync_mem();
+    // sorted position c: step i into target t
+    int t = -1, i = -1, prev = -1;
+    bool last = false;
+    if (c < Jr) {
+        const unsigned long long kc = L.key[c];
+        t = (int)(kc >> 32);
+        i = (int)(kc & 0xffffffffull);
+        if (c > 0 && (int)(L.key[c - 1] >> 32) == t) prev = (int)(L.key[c - 1] & 0xffffffffull);
+        last = c == Jr - 1 || (int)(L.key[c + 1] >> 32) != t;
+        L.pred[i] = prev;
+        // the last step before step t into row t (steps into t are <= t)
+        if (last && t < Jr) L.g[t] = i < t ? i : (prev >= 0 ? prev : t);
+    }
+    __syncthreads();
+    // chains are at most CW rows long: ten rounds of pointer jumping
+    for (int r = 0; (1 << r) < CW; ++r) {
+        const int nn = c < Jr ? L.g[L.g[c]] : c;
+        __syncthreads();
+        if (c < Jr) L.g[c] = nn;
+        __syncthreads();
+    }
+    blk = c;
+    if (c < Jr) {
+        const int pr = L.pred[c];
+        blk = pr >= 0 ? L.g[pr] : p;
+    }
+    ty = -1;
+    tsrc = 0;
+    if (last && t >= Jr) {
+        ty = t;
+        tsrc = L.g[i];
     }
 }
 
@@ -68,71 +114,52 @@ constexpr int SW_SLOTS = 2 * SW_MAX;         // rows a call can change
 constexpr int SW_TILE = 4096;                // elements per workgroup pass
 
 size_t laswp_plan_bytes(int nrows) {
-    return align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int)) +
-           (nrows > PERM_LDS_MAX ? align256((size_t)nrows * sizeof(int)) : 0);
+    (void)nrows;
+    return align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int));
 }
 
-// Only the rows a move can touch are visited: the J rows of the block and
-// the pivot targets below it (not all R rows: the permutation array is
-// initialised and scanned there alone).
-__global__ __launch_bounds__(64) void k_swap_plan(const int *__restrict__ ipiv, int k1, int k2,
-                                                  int nrows, int row0, int *__restrict__ plan,
-                                                  int *__restrict__ gperm) {
-    __shared__ int lp[PERM_LDS_MAX];
-    const int lane = threadIdx.x;
+// The plan: the run's rows that change, in order, then the rows below it
+// that change, in increasing order.
+__global__ __launch_bounds__(CW) void k_swap_plan(const int *__restrict__ ipiv, int k1, int k2,
+                                                  int nrows, int row0, int *__restrict__ plan) {
+    static_assert(SW_MAX <= CW, "one call's interchanges fit one composition");
+    __shared__ ComposeLds L;
+    __shared__ int wsum[2][CW / 64];
     const int R = nrows - k1;
     const int J = k2 - k1;
     const int Jr = J < R ? J : R;
-    const int base = row0 + k1;                  // global row of relative row 0
-    int *pm = R <= PERM_LDS_MAX ? lp : gperm;
-    for (int r = lane; r < Jr; r += 64) pm[r] = r;
-    for (int k = lane; k < J; k += 64) {
-        const int p = ipiv[k1 + k] - 1 - base;
-        if (p >= Jr && p < R) pm[p] = p;
+    int blk, ty, tsrc;
+    wg_compose(ipiv + k1, J, R, row0 + k1, L, blk, ty, tsrc);
+    const int c = threadIdx.x, lane = c & 63, w = c >> 6;
+    const bool f1 = c < Jr && blk != c, f2 = ty >= 0;
+    const unsigned long long m1 = __ballot(f1), m2 = __ballot(f2);
+    if (lane == 0) {
+        wsum[0][w] = __popcll(m1);
+        wsum[1][w] = __popcll(m2);
     }
-    wave_sync_mem();
-    compose_interchanges(pm, R, J, ipiv + k1, base);
-    int count = 0;
-    // rows of the block
-    for (int r0 = 0; r0 < Jr; r0 += 64) {
-        const int r = r0 + lane;
-        const int src = r < Jr ? pm[r] : r;
-        const bool ch = r < Jr && src != r;
-        const unsigned long long m = __ballot(ch);
-        if (ch) {
-            const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
-            plan[1 + pos] = k1 + r;
-            plan[1 + SW_SLOTS + pos] = k1 + src;
+    __syncthreads();
+    int o1 = 0, o2 = 0, n1 = 0, n2 = 0;
+    for (int x = 0; x < CW / 64; ++x) {
+        const int a = wsum[0][x], b = wsum[1][x];
+        if (x < w) {
+            o1 += a;
+            o2 += b;
         }
-        count += __popcll(m);
+        n1 += a;
+        n2 += b;
     }
-    // targets below the block, each once: the lowest lane of a chunk holding
-    // it, and a listed target is reset to itself so later chunks skip it
-    for (int c0 = 0; c0 < J; c0 += 64) {
-        const int k = c0 + lane;
-        int p = -1;
-        if (k < J) {
-            p = ipiv[k1 + k] - 1 - base;
-            if (p < Jr || p >= R) p = -1;
-        }
-        bool first = p >= 0 && pm[p] != p;
-        for (int l2 = 0; l2 < 64; ++l2) {
-            const int p2 = __builtin_amdgcn_readlane(p, l2);
-            if (l2 < lane && p2 == p) first = false;
-        }
-        const int src = first ? pm[p] : 0;
-        const unsigned long long m = __ballot(first);
-        if (first) {
-            const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
-            plan[1 + pos] = k1 + p;
-            plan[1 + SW_SLOTS + pos] = k1 + src;
-        }
-        count += __popcll(m);
-        wave_sync_mem();
-        if (first) pm[p] = p;
-        wave_sync_mem();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (f1) {
+        const int pos = o1 + __popcll(m1 & below);
+        plan[1 + pos] = k1 + c;
+        plan[1 + SW_SLOTS + pos] = k1 + blk;
     }
-    if (lane == 0) plan[0] = count;
+    if (f2) {
+        const int pos = n1 + o2 + __popcll(m2 & below);
+        plan[1 + pos] = k1 + ty;
+        plan[1 + SW_SLOTS + pos] = k1 + tsrc;
+    }
+    if (c == 0) plan[0] = n1 + n2;
 }
 
 __global__ __launch_bounds__(256) void k_swap_apply(double *__restrict__ A, long long lda,
@@ -225,10 +252,8 @@ int launch_laswp(double *A, long long lda, int nrows, int ncols_left, int col_ri
         set_error("more than %d interchanges in one call", SW_MAX);
         return EMU_ERR_UNSUPPORTED;
     }
-    int *gperm = reinterpret_cast<int *>(reinterpret_cast<char *>(plan) +
-                                         align256((size_t)(1 + 2 * SW_SLOTS) * sizeof(int)));
-    hipLaunchKernelGGL(k_swap_plan, dim3(1), dim3(64), 0, stream, ipiv, k1, k2, nrows, row0,
-                       plan, gperm);
+    hipLaunchKernelGGL(k_swap_plan, dim3(1), dim3(CW), 0, stream, ipiv, k1, k2, nrows, row0,
+                       plan);
     if (perm) hipLaunchKernelGGL(k_perm_apply, dim3(1), dim3(1024), 0, stream, perm, plan);
     return launch_laswp_apply(A, lda, nrows, ncols_left, col_right, ncols_right, k1, k2, plan,
                               stream);
@@ -250,18 +275,31 @@ int launch_laswp_apply(double *A, long long lda, int nrows, int ncols_left, int 
 
 // ---------------------------------------------------------------- getrs
 // The row interchanges of the whole factorization composed into one gather
-// permutation (in LDS when it fits).
-__global__ __launch_bounds__(64) void k_perm_from_ipiv(const int *__restrict__ ipiv, int n,
+// permutation (in LDS when it fits), CW interchanges at a time.
+__global__ __launch_bounds__(CW) void k_perm_from_ipiv(const int *__restrict__ ipiv, int n,
                                                        int *__restrict__ perm) {
     __shared__ int lp[PERM_LDS_MAX];
-    const int lane = threadIdx.x;
+    __shared__ ComposeLds L;
+    const int c = threadIdx.x;
     const bool in_lds = n <= PERM_LDS_MAX;
     int *pm = in_lds ? lp : perm;
-    for (int i = lane; i < n; i += 64) pm[i] = i;
-    wave_sync_mem();
-    compose_interchanges(pm, n, n, ipiv, 0);
+    for (int i = c; i < n; i += CW) pm[i] = i;
+    __syncthreads();
+    // pivots kb .. kb + J act on rows kb.. (relative rows of pm + kb)
+    for (int kb = 0; kb < n; kb += CW) {
+        const int J = n - kb < CW ? n - kb : CW;
+        int blk, ty, tsrc;
+        wg_compose(ipiv + kb, J, n - kb, kb, L, blk, ty, tsrc);
+        const bool f1 = c < J && blk != c;
+        const int v1 = f1 ? pm[kb + blk] : 0;
+        const int v2 = ty >= 0 ? pm[kb + tsrc] : 0;
+        __syncthreads();
+        if (f1) pm[kb + c] = v1;
+        if (ty >= 0) pm[kb + ty] = v2;
+        __syncthreads();
+    }
     if (in_lds)
-        for (int i = lane; i < n; i += 64) perm[i] = lp[i];
+        for (int i = c; i < n; i += CW) perm[i] = lp[i];
 }
 
 // X (n x nrhs, scratch, leading dimension n) <- P B
@@ -568,7 +606,7 @@ int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ip
     char *base = reinterpret_cast<char *>(perm_ws);
     double *X = reinterpret_cast<double *>(base + align256((size_t)n * sizeof(int)));
     if (!perm_ready && !perm_ext)
-        hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(64), 0, stream, ipiv, n, perm_ws);
+        hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(CW), 0, stream, ipiv, n, perm_ws);
     dim3 gcol((n + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_gather_rows, gcol, dim3(256), 0, stream, B, ldb, n, perm, X);
     if (nrhs <= PT_RHS && status) {
