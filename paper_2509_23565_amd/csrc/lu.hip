@@ -102,7 +102,7 @@ constexpr int PERM_LDS_MAX = 32768;
 // ---------------------------------------------------------------- laswp
 // The interchanges ipiv[k1..k2) (1-based global rows; A's first row is
 // global row row0) are applied to columns [0, ncols_left) and
-// [col_right, col_right + ncols_right) of rows [k1, nrows).  A one-wave
+// [col_right, col_right + ncols_right) of rows [k1, nrows).  A one-workgroup
 // kernel composes them (above) and lists the rows that change as a plan:
 // plan[0] = count, then each row (relative to A) and the row whose old
 // values it receives.  The apply kernel reads the plan and moves, for its
