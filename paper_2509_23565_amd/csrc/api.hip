@@ -929,6 +929,8 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     off += align256(refine_partial_bytes(n, nrhs));
     const size_t o_stats = off;
     off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
+    const size_t o_inv = off;
+    off += tri_inv_bytes(n);
     const size_t o_sub = off;
     // refinement falls back up to nine slices (or from a larger start up to
     // the library's largest count)
@@ -950,6 +952,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
     double *part = reinterpret_cast<double *>(ws + o_part);
     double *normA = reinterpret_cast<double *>(ws + o_stats);
     double *stats = normA + 1;
+    double *inv = reinterpret_cast<double *>(ws + o_inv);
     char *subws = ws + o_sub;
 
     EMU_TRY(launch_norm_inf(A, lda, n, part, normA, st));
@@ -972,9 +975,12 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
             return EMU_ERR_PANEL_WAIT;
         }
         if (hinfo > 0) return 0;       // exactly singular U: nothing to refine
+        // the solves multiply each diagonal block by its inverse (rounding
+        // differs from substitution; the refinement corrects it)
+        EMU_TRY(launch_tri_inv(LU, n, n, inv, st));
         EMU_TRY(launch_copy_mat(B, ldb, X, ldx, n, nrhs, st));
         EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, X, ldx, reinterpret_cast<int *>(subws), st,
-                             false, dev->status, perm));
+                             false, dev->status, perm, inv));
         double prev = -1.0;
         bool fallback = false;
         for (int it = 0;; ++it) {
@@ -1005,7 +1011,7 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
             }
             prev = eta;
             EMU_TRY(launch_getrs(n, nrhs, LU, n, ipiv, R, n, reinterpret_cast<int *>(subws), st,
-                                 true, dev->status, perm));
+                                 true, dev->status, perm, inv));
             EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
             ++total_iters;
         }

@@ -302,11 +302,16 @@ int launch_trsm_llnu(const double *L, long long ldl, int jb, double *B,
 // reuses it (same factors) instead of composing it again; perm_ext gives
 // the permutation itself (the factorization tracked it).
 // status: the device status word; with it (and at most four right-hand
-// sides) each sweep runs as one persistent launch.
+// sides) each sweep runs as one persistent launch, which with inv (the
+// inverted diagonal blocks of launch_tri_inv) multiplies each block by its
+// inverse instead of resolving it by substitution.
 int launch_getrs(int n, int nrhs, const double *LU, long long lda,
                  const int *ipiv, double *B, long long ldb, int *perm_ws,
                  hipStream_t stream, bool perm_ready = false, int *status = nullptr,
-                 const int *perm_ext = nullptr);
+                 const int *perm_ext = nullptr, const double *inv = nullptr);
+// Inverses of the 64 x 64 diagonal blocks of L (unit lower) and U.
+size_t tri_inv_bytes(int n);
+int launch_tri_inv(const double *LU, long long lda, int n, double *inv, hipStream_t stream);
 // Scratch bytes of launch_getrs.
 size_t getrs_ws_bytes(int n, int nrhs);
 

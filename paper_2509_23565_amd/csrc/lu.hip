@@ -456,6 +456,75 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double *__restrict__ L
     x[i] = b;
 }
 
+// ------------------------------------------ inverted diagonal blocks
+// For block b of the precision form's solves: L_bb^-1 (unit lower) at
+// inv + 2 b 64^2 and U_bb^-1 at inv + (2 b + 1) 64^2, column-major 64 x 64,
+// zero outside the block's nb x nb part.  One wave per block; lane j
+// computes column j of each inverse by substitution on the unit vector
+// (its entries in LDS, column j only read and written by lane j).
+size_t tri_inv_bytes(int n) {
+    return align256((size_t)((n + TRSV_NB - 1) / TRSV_NB) * 2 * TRSV_NB * TRSV_NB *
+                    sizeof(double));
+}
+
+__global__ __launch_bounds__(64) void k_tri_inv(const double *__restrict__ LU, long long lda,
+                                                int n, double *__restrict__ inv) {
+    __shared__ double Ds[TRSV_NB * TRSV_NB];        // the block, column-major
+    __shared__ double Xs[TRSV_NB * TRSV_NB];        // entry i of column j at i 64 + j
+    const int j = threadIdx.x;
+    const int b = blockIdx.x;
+    const int r0 = b * TRSV_NB;
+    const int nb = n - r0 < TRSV_NB ? n - r0 : TRSV_NB;
+    for (int k = 0; k < TRSV_NB; ++k)
+        Ds[k * TRSV_NB + j] =
+            (k < nb && j < nb) ? LU[r0 + j + (long long)(r0 + k) * lda] : 0.0;
+    __syncthreads();
+    double *Li = inv + (size_t)(2 * b) * TRSV_NB * TRSV_NB;
+    double *Ui = Li + TRSV_NB * TRSV_NB;
+    // L^-1 e_j: x_i = 0 (i < j), 1 (i = j), -sum_{k = j}^{i - 1} l_ik x_k
+    for (int i = 0; i < TRSV_NB; ++i) {
+        double x = 0.0;
+        if (j < nb && i < nb && i >= j) {
+            if (i == j) {
+                x = 1.0;
+            } else {
+                double sum = 0.0;
+#pragma unroll 8
+                for (int k = j; k < i; ++k) sum = sum + Ds[k * TRSV_NB + i] * Xs[k * TRSV_NB + j];
+                x = -sum;
+            }
+        }
+        Xs[i * TRSV_NB + j] = x;
+    }
+    for (int i = 0; i < TRSV_NB; ++i) Li[j * TRSV_NB + i] = Xs[i * TRSV_NB + j];
+    // U^-1 e_j: x_i = 0 (i > j), 1 / u_jj (i = j),
+    // -(sum_{k = i + 1}^{j} u_ik x_k) / u_ii (i < j)
+    for (int i = TRSV_NB - 1; i >= 0; --i) {
+        double x = 0.0;
+        if (j < nb && i < nb && i <= j) {
+            if (i == j) {
+                x = 1.0 / Ds[j * TRSV_NB + j];
+            } else {
+                double sum = 0.0;
+#pragma unroll 8
+                for (int k = i + 1; k <= j; ++k)
+                    sum = sum + Ds[k * TRSV_NB + i] * Xs[k * TRSV_NB + j];
+                x = -sum / Ds[i * TRSV_NB + i];
+            }
+        }
+        Xs[i * TRSV_NB + j] = x;
+    }
+    for (int i = 0; i < TRSV_NB; ++i) Ui[j * TRSV_NB + i] = Xs[i * TRSV_NB + j];
+}
+
+int launch_tri_inv(const double *LU, long long lda, int n, double *inv, hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_tri_inv, dim3((n + TRSV_NB - 1) / TRSV_NB), dim3(64), 0, stream, LU,
+                       lda, n, inv);
+    EMU_TRY_HIP(hipGetLastError());
+    return 0;
+}
+
 // ------------------------------------------- persistent triangular solves
 // One launch per sweep for up to PT_RHS right-hand sides: one workgroup per
 // 64-row block, one wave per right-hand side.  A workgroup takes its place
@@ -472,6 +541,10 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double *__restrict__ L
 // in the column-by-column substitution.  The wait is bounded: a wave that
 // exceeds PT_SPIN_LIMIT polls raises EMU_STATUS_SOLVE_WAIT and the abort
 // flag, and the waves still waiting leave; the solution is then invalid.
+// INV (the precision form): the diagonal block is not resolved by its
+// 64-step chain but multiplied by its inverse (k_tri_inv), 64 independent
+// products per lane; the solution then differs from substitution in
+// rounding, which the refinement corrects.
 constexpr int PT_RHS = 4;
 constexpr int PT_SPIN_LIMIT = 1 << 21;
 constexpr int PT_WORDS = 2 * TRSV_NB;                 // words per block and rhs
@@ -480,11 +553,11 @@ __device__ __forceinline__ unsigned long long pt_load(const unsigned long long *
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool FWD>
+template <bool FWD, bool INV>
 __global__ __launch_bounds__(64 * PT_RHS) void k_trsv_persist(
     const double *__restrict__ LU, long long lda, int n, int nrhs, double *__restrict__ X,
     unsigned long long *__restrict__ words, int *__restrict__ ctr, int *__restrict__ status,
-    unsigned tag) {
+    unsigned tag, const double *__restrict__ inv) {
     extern __shared__ double Dsh[];                   // TRSV_NB^2 doubles per wave
     __shared__ int s_q;
     const int t = threadIdx.x, lane = t & 63;
@@ -500,12 +573,19 @@ __global__ __launch_bounds__(64 * PT_RHS) void k_trsv_persist(
     const int i = r0 + lane;
     double *x = X + (long long)r * n;
     double *Ds = Dsh + (size_t)r * TRSV_NB * TRSV_NB;
-    // the diagonal block into LDS (lane i reads row i of every column)
+    // the diagonal block (INV: its inverse) into LDS (lane i reads row i of
+    // every column)
     {
         double col[TRSV_NB];
+        if constexpr (INV) {
+            const double *iv = inv + ((size_t)2 * blk + (FWD ? 0 : 1)) * TRSV_NB * TRSV_NB;
 #pragma unroll
-        for (int k = 0; k < TRSV_NB; ++k)
-            col[k] = (k < nb && lane < nb) ? LU[i + (long long)(r0 + k) * lda] : 0.0;
+            for (int k = 0; k < TRSV_NB; ++k) col[k] = iv[k * TRSV_NB + lane];
+        } else {
+#pragma unroll
+            for (int k = 0; k < TRSV_NB; ++k)
+                col[k] = (k < nb && lane < nb) ? LU[i + (long long)(r0 + k) * lda] : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < TRSV_NB; ++k) Ds[k * TRSV_NB + lane] = col[k];
     }
@@ -563,7 +643,17 @@ __global__ __launch_bounds__(64 * PT_RHS) void k_trsv_persist(
             }
         }
     }
-    if constexpr (FWD) {
+    if constexpr (INV) {
+        // entries outside the block's nb x nb part are zero, and so is acc
+        // in the lanes past nb
+        double y = 0.0;
+#pragma unroll 16
+        for (int k = 0; k < TRSV_NB; ++k) {
+            const double ak = lane_bcast(acc, k);
+            y = y + Ds[k * TRSV_NB + lane] * ak;
+        }
+        acc = y;
+    } else if constexpr (FWD) {
         for (int k = 0; k < nb - 1; ++k) {
             const double xk = lane_bcast(acc, k);
             if (lane > k && lane < nb) acc = acc - Ds[k * TRSV_NB + lane] * xk;
@@ -600,7 +690,7 @@ size_t getrs_ws_bytes(int n, int nrhs) {
 
 int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ipiv,
                  double *B, long long ldb, int *perm_ws, hipStream_t stream, bool perm_ready,
-                 int *status, const int *perm_ext) {
+                 int *status, const int *perm_ext, const double *inv) {
     if (n <= 0 || nrhs <= 0) return 0;
     const int *perm = perm_ext ? perm_ext : perm_ws;
     char *base = reinterpret_cast<char *>(perm_ws);
@@ -623,19 +713,27 @@ int launch_getrs(int n, int nrhs, const double *LU, long long lda, const int *ip
         // up to PT_RHS diagonal blocks of dynamic LDS (128 KB): allowed once
         static const hipError_t attr = [] {
             const int mx = PT_RHS * TRSV_NB * TRSV_NB * (int)sizeof(double);
-            hipError_t e = hipFuncSetAttribute(
-                reinterpret_cast<const void *>(&k_trsv_persist<true>),
-                hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trsv_persist<false>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+            const void *fns[4] = {reinterpret_cast<const void *>(&k_trsv_persist<true, false>),
+                                  reinterpret_cast<const void *>(&k_trsv_persist<false, false>),
+                                  reinterpret_cast<const void *>(&k_trsv_persist<true, true>),
+                                  reinterpret_cast<const void *>(&k_trsv_persist<false, true>)};
+            hipError_t e = hipSuccess;
+            for (int f = 0; f < 4 && e == hipSuccess; ++f)
+                e = hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize, mx);
             return e;
         }();
         if (attr != hipSuccess) return fail_hip(attr, "hipFuncSetAttribute");
-        hipLaunchKernelGGL(k_trsv_persist<true>, dim3(nblk), dim3(64 * nrhs), lds, stream, LU,
-                           lda, n, nrhs, X, words, ctr, status, 1u);
-        hipLaunchKernelGGL(k_trsv_persist<false>, dim3(nblk), dim3(64 * nrhs), lds, stream,
-                           LU, lda, n, nrhs, X, words, ctr + 2, status, 2u);
+        if (inv) {
+            hipLaunchKernelGGL((k_trsv_persist<true, true>), dim3(nblk), dim3(64 * nrhs), lds,
+                               stream, LU, lda, n, nrhs, X, words, ctr, status, 1u, inv);
+            hipLaunchKernelGGL((k_trsv_persist<false, true>), dim3(nblk), dim3(64 * nrhs), lds,
+                               stream, LU, lda, n, nrhs, X, words, ctr + 2, status, 2u, inv);
+        } else {
+            hipLaunchKernelGGL((k_trsv_persist<true, false>), dim3(nblk), dim3(64 * nrhs), lds,
+                               stream, LU, lda, n, nrhs, X, words, ctr, status, 1u, inv);
+            hipLaunchKernelGGL((k_trsv_persist<false, false>), dim3(nblk), dim3(64 * nrhs), lds,
+                               stream, LU, lda, n, nrhs, X, words, ctr + 2, status, 2u, inv);
+        }
         hipLaunchKernelGGL(k_copy_cols, gcol, dim3(256), 0, stream, X, n, B, ldb);
         EMU_TRY_HIP(hipGetLastError());
         return 0;
