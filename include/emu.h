@@ -345,6 +345,10 @@ int emu_set_param(const char *key, long long value);
  *      Otherwise, if eta did not fall below half its previous value, or
  *      `maxiter` corrections were applied, or eta is NaN: fall back (step 3);
  *      else X += getrs(R).
+ *   The solves (up to four right-hand sides) multiply each 64 x 64 diagonal
+ *   block of L and U by its inverse, computed once per factorization, so X
+ *   differs from emu_dgetrs's substitution in rounding; the refinement
+ *   corrects it.
  *   3. Fallback: refactor with s = min(s + 2, s_cap) and restart at step 1's
  *      solve, where s_cap = 9 for a start nslices <= 9 and EMU_MAX_SLICES
  *      above (beyond nine slices the update is already below the FP64 panel's
@@ -369,7 +373,9 @@ int emu_dgesv_ir(int n, int nrhs, const double *A, int lda, const double *B, int
  * repeat R = B - A X, eta = max over columns of ||R||_inf /
  * (||A||_inf ||X||_inf + ||B||_inf); stop at eta <= tol; else, unless eta
  * failed to halve or `maxiter` corrections were applied (then
- * EMU_ERR_NOT_CONVERGED), X += getrs(R).  *iters, *berr on the HOST.
+ * EMU_ERR_NOT_CONVERGED), X += getrs(R), with the inverted diagonal blocks
+ * of emu_dgesv_ir's solves (computed once per call, before the first
+ * correction).  *iters, *berr on the HOST.
  * Argument numbers: n=1 nrhs=2 A=3 lda=4 LU=5 ldlu=6 ipiv=7 B=8 ldb=9 X=10
  * ldx=11 tol=12 maxiter=13 iters=14 berr=15.
  */

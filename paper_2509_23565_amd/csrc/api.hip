@@ -1054,6 +1054,8 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
     off += align256(refine_partial_bytes(n, nrhs));
     const size_t o_stats = off;
     off += align256((size_t)(1 + 3 * nrhs) * sizeof(double));
+    const size_t o_inv = off;
+    off += tri_inv_bytes(n);
     const size_t o_sub = off;
     off += getrs_scratch_bytes(n, nrhs);
     Call call;
@@ -1065,6 +1067,7 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
     double *part = reinterpret_cast<double *>(ws + o_part);
     double *normA = reinterpret_cast<double *>(ws + o_stats);
     double *stats = normA + 1;
+    double *inv = reinterpret_cast<double *>(ws + o_inv);
     EMU_TRY(launch_norm_inf(A, lda, n, part, normA, st));
     std::vector<double> hstats(3 * (size_t)nrhs);
     double hnorm = 0.0, prev = -1.0;
@@ -1088,8 +1091,9 @@ int emu_refine(int n, int nrhs, const double *A, int lda, const double *LU, int 
             return EMU_ERR_NOT_CONVERGED;
         }
         prev = eta;
+        if (it == 0) EMU_TRY(launch_tri_inv(LU, ldlu, n, inv, st));
         EMU_TRY(launch_getrs(n, nrhs, LU, ldlu, ipiv, R, n, reinterpret_cast<int *>(ws + o_sub),
-                             st, it > 0, dev->status));
+                             st, it > 0, dev->status, nullptr, inv));
         EMU_TRY(launch_add_cols(X, ldx, R, n, n, nrhs, st));
     }
 }
