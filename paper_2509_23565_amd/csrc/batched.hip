@@ -359,7 +359,7 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
                 for (int u = 0; u < 16; ++u) {
                     const int k = kc + u;
                     if (k < kb - 1) {
-                        const double xk = __shfl(b, k, 64);
+                        const double xk = lane_read_f64(b, k);
                         if (lane > k && lane < kb) b = b - lrow[u] * xk;
                     }
                 }
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(1024) void k_bgetrs(const BSys *__restrict__ sys) {
                     const int k = kc + u;
                     if (k < kb) {
                         if (lane == k) b = b / urow[u];
-                        const double xk = __shfl(b, k, 64);
+                        const double xk = lane_read_f64(b, k);
                         if (lane < k) b = b - urow[u] * xk;
                     }
                 }

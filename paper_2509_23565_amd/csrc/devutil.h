@@ -107,6 +107,16 @@ __device__ __forceinline__ void block_key_best(long long &k, int &i, long long *
     key_best<NWAVES>(k, i);
 }
 
+// v of lane k (k wave-uniform) through two lane reads into scalar
+// registers: a few cycles, where a shuffle (ds_bpermute) waits on LDS.
+__device__ __forceinline__ double lane_read_f64(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
 // Composition of w <= 32 row interchanges k <-> p_k (k = 0..w-1 in order,
 // p_k >= k; rows relative to the first) by one wave: lane k holds pk = p_k
 // (any value for lanes >= w).  The rows they touch, at most 2w, get a lane

@@ -895,7 +895,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol_leaf(double *__restrict__ P
 #pragma unroll
         for (int c = 0; c < LEAF_W; ++c) {
             if (c < nd) {
-                const double a = uniform_f64(__shfl(d[c], c));
+                const double a = lane_read_f64(d[c], c);
                 if (!(a > 0.0) && first < 0) first = c;
                 const double l = sqrt(a);
                 const double r = 1.0 / l;
@@ -905,7 +905,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol_leaf(double *__restrict__ P
 #pragma unroll
                 for (int j = c + 1; j < LEAF_W; ++j) {
                     if (j < nd) {
-                        const double ljc = __shfl(d[c], j);
+                        const double ljc = lane_read_f64(d[c], j);
                         if (lane >= j) d[j] = d[j] - d[c] * ljc;
                     }
                 }
