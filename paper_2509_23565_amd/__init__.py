@@ -352,16 +352,25 @@ def dgesv_ir(A, B, X=None, nb=64, nslices=3, tol=1e-15, maxiter=10):
 
 
 class _Batch:
-    """Host arrays (sizes, device pointers) of a list of column-major tensors."""
+    """Host arrays (sizes, device pointers) of a list of column-major tensors
+    (the checks of _mat, in one pass over the list: a batch holds thousands)."""
 
     def __init__(self, mats, name):
-        n = len(mats)
-        self.ptr = (ctypes.c_void_p * n)()
-        self.ld = (ctypes.c_int * n)()
+        f64 = _torch().float64
+        ptrs, lds = [], []
         for i, t in enumerate(mats):
-            p, ld = _mat(t, f"{name}[{i}]")
-            self.ptr[i] = p
-            self.ld[i] = ld
+            if t.dtype is not f64 or not t.is_cuda or t.dim() != 2:
+                raise EmuError(f"{name}[{i}]: expected a 2-D float64 CUDA tensor")
+            rows, cols = t.shape
+            s0, s1 = t.stride()
+            if cols > 1 and rows > 0 and s0 != 1:
+                raise EmuError(f"{name}[{i}]: must be column-major (stride(0) == 1)")
+            ptrs.append(t.data_ptr())
+            ld = s1 if cols > 1 else rows
+            lds.append(ld if ld > 1 else 1)
+        n = len(mats)
+        self.ptr = (ctypes.c_void_p * n)(*ptrs)
+        self.ld = (ctypes.c_int * n)(*lds)
 
 
 def _pivot_views(torch, sizes, dev):
@@ -400,8 +409,17 @@ def dgesv_batched_ir(As, Bs, Xs=None, nb=32, nslices=3, tol=1e-15, maxiter=10):
     torch = _torch()
     count = len(As)
     if Xs is None:
-        Xs = [torch.empty((b.shape[1], b.shape[0]), dtype=torch.float64, device=b.device).t()
-              for b in Bs]
+        # one allocation, a column-major view per system
+        shapes = [(int(b.shape[0]), int(b.shape[1])) for b in Bs]
+        offs, tot = [], 0
+        for r, c in shapes:
+            offs.append(tot)
+            tot += r * c
+        Xs = []
+        if shapes:
+            flat = torch.empty(max(tot, 1), dtype=torch.float64, device=Bs[0].device)
+            Xs = [torch.as_strided(flat, (r, c), (1, max(r, 1)), o)
+                  for (r, c), o in zip(shapes, offs)]
     n = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
     nrhs = (ctypes.c_int * count)(*[int(b.shape[1]) for b in Bs])
     a = _Batch(As, "A")
