@@ -401,6 +401,27 @@ def test_refinement_reaches_1e15(n, phi, s, nrhs):
     assert np.abs(X - Xo).max() <= 1e-12 * np.abs(Xo).max()
 
 
+@pytest.mark.parametrize("nrhs", [1, 4, 5])
+def test_precision_form_first_solve(nrhs):
+    # with a tolerance every first solve meets, the precision form returns its
+    # first solve: up to four right-hand sides it multiplies each diagonal
+    # block by its inverse (ragged last block here: 1000 = 15 * 64 + 40), so
+    # it agrees with the oracle's substitution on the same factors to
+    # rounding; five take the substitution itself, bit for bit
+    n, s = 1000, 6
+    A = matgen.phi_matrix(n, n, 1.0, seed=27)
+    B = matgen.uniform(n, nrhs, seed=28)
+    Xg, inf = emu.dgesv_ir(emu.colmajor(A), emu.colmajor(B), nb=64, nslices=s, tol=1e300)
+    assert inf["rc"] == 0 and inf["iters"] == 0 and inf["s_final"] == s
+    LU, piv, info = O.getrf(A, nb=64, s=s)
+    Xo = O.getrs(LU, piv, B)
+    X = _host(Xg)
+    if nrhs <= 4:
+        assert np.abs(X - Xo).max() <= 1e-11 * np.abs(Xo).max()
+    else:
+        assert _same_bits(X, Xo)
+
+
 def test_refinement_fallback_paths_match_oracle():
     A = matgen.phi_matrix(400, 400, 1.0, seed=23)
     B = matgen.uniform(400, 1, seed=24)
