@@ -799,18 +799,27 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
         EMU_TRY_HIP(hipGetLastError());
         return 0;
     }
-    const int G = (rows + LF_ROWS - 1) / LF_ROWS;
+    // 256-thread workgroups (one wave per SIMD, 1024 rows each) while at most
+    // LF_MAX_G of them cover the leaf, else 512-thread ones
+    const bool narrow = rows <= LF_MAX_G * (LF_ROWS / 2);
+    const int NTg = narrow ? LF_THREADS / 2 : LF_THREADS;
+    const int G = (rows + NTg * LF_R - 1) / (NTg * LF_R);
     if (G > LF_MAX_G) {
         set_error("panel of %d rows above %d", rows, LF_MAX_G * LF_ROWS);
         return EMU_ERR_UNSUPPORTED;
     }
     unsigned base = pr.arrivals;
+    const void *fn = narrow ? reinterpret_cast<const void *>(&k_leaf<true, LF_THREADS / 2>)
+                            : reinterpret_cast<const void *>(&k_leaf<true, LF_THREADS>);
     if (g_leaf_cooperative) {
         void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
-        EMU_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_leaf<true, LF_THREADS>),
-                                               dim3(G), dim3(LF_THREADS), args, 0, st));
+        EMU_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NTg), args, 0, st));
+    } else if (narrow) {
+        hipLaunchKernelGGL((k_leaf<true, LF_THREADS / 2>), dim3(G), dim3(NTg), 0, st, P, lda,
+                           rows, w, ipiv, grow0, info, x, base, ncl, ncr);
+        EMU_TRY_HIP(hipGetLastError());
     } else {
-        hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G), dim3(LF_THREADS), 0, st, P, lda,
+        hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G), dim3(NTg), 0, st, P, lda,
                            rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
     }
