@@ -26,7 +26,8 @@
 //     copy of row c) into a double-buffered LDS slot, so after the barrier
 //     every wave picks the winner and reads both rows without a second
 //     round.  Leaves taller than 2048 rows run as one launch of up to 32
-//     workgroups that exchange their candidates the same way through global
+//     workgroups (256 threads and 1024 rows each up to 32768 rows, else 512
+//     threads and 2048 rows) that exchange their candidates the same way through global
 //     memory, with one grid-wide wait per column: every wave reads a share
 //     of all workgroups' records, then a workgroup barrier (bounded: a wait
 //     that exceeds its bound aborts the leaf, sets info to EMU_INFO_ABORTED
