@@ -35,6 +35,7 @@
 #include "common.h"
 #include "devutil.h"
 
+#include <atomic>
 #include <float.h>
 
 namespace emu {
@@ -46,17 +47,31 @@ constexpr int LF_R = 4;                        // rows per thread
 constexpr int LF_ROWS = LF_THREADS * LF_R;     // rows per workgroup
 constexpr int LF_MAX_G = 32;                   // workgroups of one leaf (65536 rows)
 constexpr int LF_SPIN_LIMIT = 1 << 20;         // polls of one grid-wide wait
+constexpr int LF_XCDS = 8;                     // XCDs that workgroups are dealt over in turn
+constexpr int LF_XCD_MAX_G = 16;              // leaves of at most this many workgroups on one XCD
 
 // Cross-workgroup exchange of a multi-workgroup leaf (global scratch).
 // Per column and workgroup one record of 64-bit words, each holding a
 // 32-bit payload in its low half and the column's tag in its high half, so
 // every word is validated on its own and one read of the records follows
 // the last write (no separate flag to poll).  Words: [0] pivot key high,
-// [1] key low, [2] its row, [3] unused, [4 + 2j], [5 + 2j] low and high
-// half of element j of that row, [36 + 2j], [37 + 2j] the same for row c
-// (workgroup 0 only, which owns it).  Double-buffered by column parity;
-// tags count the columns of the panel from 1 (the words are zeroed once
-// per panel).
+// [1] key low, [2] its row, [3] the XCD of the workgroup, [4 + 2j],
+// [5 + 2j] low and high half of element j of that row, [36 + 2j], [37 + 2j]
+// the same for row c (workgroup 0 only, which owns it).  Double-buffered by
+// column parity; tags number the columns of all panels of the process from
+// 1 (the words are zeroed once per panel).
+//
+// Where the exchange runs: the dispatcher deals workgroups over the XCDs in
+// turn (block b to XCD b mod 8), so a leaf of at most 16 workgroups is
+// launched with 8 blocks per workgroup and only blocks 0, 8, 16, ... work,
+// all on one XCD.  The records' device-scope loads are served by that XCD's
+// L2 for lines written there, so from the second column on (once the first
+// column's records have shown every workgroup on one XCD) the records are
+// written with plain stores into that L2 instead of through to memory: a
+// round trip of about 1500 instead of 2900 shader-clock ticks.  Leaves on
+// several XCDs, and larger ones, keep device-scope stores.  Larger leaves
+// stay spread out: 17-32 workgroups on one XCD made the n = 32768 LU 11%
+// slower.
 constexpr int RW = 68;              // words per record
 constexpr int RW_MAIN = 36;         // words every workgroup publishes
 struct LeafX {
@@ -64,7 +79,15 @@ struct LeafX {
     int *abort;                     // set by a workgroup whose wait exceeded the bound
     int *status;                    // device status word (EMU_STATUS_PANEL_WAIT)
     int nopiv;                      // no interchanges: row c is the pivot of column c
+    int xs;                         // launch stride: workgroup g is block g xs (1 or LF_XCDS)
 };
+
+// The XCD this wave runs on.
+__device__ __forceinline__ unsigned xcc_id() {
+    unsigned id;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(id));
+    return id;
+}
 
 __device__ __forceinline__ void st_relaxed(double *p, double v) {
     __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
@@ -93,6 +116,8 @@ struct LeafLds {
     double xrow[2][LEAF_W];
     double grow[2][LF_MAX_G][LEAF_W];   // multi-workgroup: every record's row
     unsigned gkey[2][LF_MAX_G][3];      // and its key (high, low) and row
+    unsigned gxcc[LF_MAX_G];            // XCD of each workgroup (first column's records)
+    int l2x;                            // all on one XCD: plain record stores
     double xr[2][LEAF_W];
     int abort;
     int piv[LEAF_W];          // pivot row (leaf coordinates) of each column
@@ -245,7 +270,8 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         for (int j = 0; j < LEAF_W; ++j) pr[j] = row_elem(e0, e1, wr, j);
         xr = L.xrow[buf];
     } else {
-        const int G = (int)gridDim.x;
+        const int G = (int)gridDim.x / x.xs;
+        const bool l2x = L.l2x != 0;
         const unsigned long long tag = (unsigned long long)(base + (unsigned)c + 1u) << 32;
         if (wid == 0) {
             const long long wkv = (long long)(((unsigned long long)(unsigned)
@@ -265,14 +291,19 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                 } else if (e == 2) {
                     pl = (unsigned)wi;
                 } else if (e == 3) {
-                    pl = 0u;
+                    pl = xcc_id();
                 } else {
                     const int j = (e - 4) % 32 / 2, hi = e & 1;
                     const double d = e < RW_MAIN ? wrow[j] : L.xrow[buf][j];
                     const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
                     pl = hi ? (unsigned)(bits >> 32) : (unsigned)bits;
                 }
-                __hip_atomic_store(mine + e, tag | pl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (l2x)
+                    __hip_atomic_store(mine + e, tag | pl, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    __hip_atomic_store(mine + e, tag | pl, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         // collect: every wave reads its share of the records' words (64-word
@@ -313,7 +344,9 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
                         const int sl = e / RW_MAIN, wo = e % RW_MAIN;
                         if (wo < 3)
                             L.gkey[buf][sl][wo] = pl;
-                        else if (wo >= 4)
+                        else if (wo == 3)
+                            L.gxcc[sl] = pl;
+                        else
                             grow_w[sl * 2 * LEAF_W + (wo - 4)] = pl;
                     } else {
                         xr_w[e - RW_MAIN * G] = pl;
@@ -340,6 +373,14 @@ __device__ __forceinline__ bool leaf_col(double (&v)[LF_R][LEAF_W], LeafLds &L, 
         }
         __syncthreads();
         if (L.abort) return false;
+        // after the launch's first column: when every workgroup runs on one
+        // XCD (the same finding in every workgroup), the later columns'
+        // records are written into that XCD's L2
+        if (c == 0 && t == 0 && x.xs > 1) {
+            int same = 1;
+            for (int s2 = 1; s2 < G; ++s2) same &= L.gxcc[s2] == L.gxcc[0];
+            L.l2x = same;
+        }
         // the grid's winner from the staged keys (every wave, same result)
         {
             const int l = lane & (LF_MAX_G - 1);
@@ -536,11 +577,13 @@ __global__ __launch_bounds__(NT) void k_leaf(double *__restrict__ P, long long l
                                                      int ncl, int ncr) {
     __shared__ LeafLds L;
     const int t = threadIdx.x;
-    const int g = MULTI ? (int)blockIdx.x : 0;
+    if (MULTI && blockIdx.x % x.xs != 0) return;    // a slot on another XCD
+    const int g = MULTI ? (int)blockIdx.x / x.xs : 0;
     const int base_row = g * (NT * LF_R);
     if (t == 0) {
         L.abort = 0;
         L.zc = w;
+        L.l2x = 0;
     }
     double v[LF_R][LEAF_W];
 #pragma unroll
@@ -571,7 +614,8 @@ __global__ __launch_bounds__(NT) void k_leaf(double *__restrict__ P, long long l
         if (t < w) ipiv[t] = grow0 + L.piv[t] + 1;
         if (t == 0 && L.zc < w && *info == 0) *info = grow0 + L.zc + 1;
     }
-    if (ncl + ncr > 0) leaf_panel_swaps<NT>(P, lda, w, ncl, ncr, L, g, MULTI ? (int)gridDim.x : 1);
+    if (ncl + ncr > 0) leaf_panel_swaps<NT>(P, lda, w, ncl, ncr, L, g,
+                                                MULTI ? (int)gridDim.x / x.xs : 1);
 }
 
 // --------------------------------------------- order-preserving FP64 tiles
@@ -762,6 +806,7 @@ static LeafX leaf_x(char *ws, int *status) {
     x.abort = reinterpret_cast<int *>(x.rec + 2 * LF_MAX_G * RW);
     x.status = status;
     x.nopiv = 0;
+    x.xs = 1;
     return x;
 }
 
@@ -813,15 +858,18 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
     const void *fn = narrow ? reinterpret_cast<const void *>(&k_leaf<true, LF_THREADS / 2>)
                             : reinterpret_cast<const void *>(&k_leaf<true, LF_THREADS>);
     if (g_leaf_cooperative) {
+        x.xs = 1;
         void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
         EMU_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NTg), args, 0, st));
     } else if (narrow) {
-        hipLaunchKernelGGL((k_leaf<true, LF_THREADS / 2>), dim3(G), dim3(NTg), 0, st, P, lda,
-                           rows, w, ipiv, grow0, info, x, base, ncl, ncr);
+        x.xs = G <= LF_XCD_MAX_G ? LF_XCDS : 1;
+        hipLaunchKernelGGL((k_leaf<true, LF_THREADS / 2>), dim3(G * x.xs), dim3(NTg), 0, st,
+                           P, lda, rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
     } else {
-        hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G), dim3(NTg), 0, st, P, lda,
-                           rows, w, ipiv, grow0, info, x, base, ncl, ncr);
+        x.xs = G <= LF_XCD_MAX_G ? LF_XCDS : 1;
+        hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G * x.xs), dim3(NTg), 0, st,
+                           P, lda, rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
     }
     pr.arrivals += (unsigned)w;
@@ -850,9 +898,20 @@ static int panel_rec(double *A, long long lda, int m_rows, int pw, int c0, int w
     return 0;
 }
 
+// Record tags continue over all panels of the process (never 0, the value of
+// a zeroed word), so no record word left from an earlier panel, wherever it
+// is cached, carries a tag a later wait looks for.
+static std::atomic<unsigned> g_leaf_tags{0u};
+static unsigned leaf_tag_base(int cols) {
+    for (;;) {
+        const unsigned s = g_leaf_tags.fetch_add((unsigned)cols + 1u);
+        if (s <= 0xFFFFFFFFu - (unsigned)cols - 1u) return s;
+    }
+}
+
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0, int *info,
                  char *ws, int *status, hipStream_t stream, bool pivot) {
-    PanelRun pr{ws, status, 0u, pivot};
+    PanelRun pr{ws, status, rows > LF_ROWS ? leaf_tag_base(jb) : 0u, pivot};
     if (rows > LF_ROWS) {
         // record words (tag 0: not yet written) and the abort flag start at
         // zero (a fill kernel, not a memset)
