@@ -1351,12 +1351,13 @@ int emu_dgetrf_adaptive(int m, int n, double *A, int lda, int *ipiv, int *info, 
     auto panel = [&](int j0) -> int {
         const int jb = nb < mn - j0 ? nb : mn - j0;
         return launch_panel(A + j0 + (long long)j0 * ld, ld, m - j0, jb, ipiv + j0, j0, info,
-                            pws, dev->status, st);
+                            pws, dev->status, st, true, false);
     };
     // The grouped launches are persistent (a grid of resident workgroups
     // walks the tile list); on the side stream they take three quarters of
     // the compute units, so that the next panel's kernels, which run
-    // meanwhile, find free ones.
+    // meanwhile, find free ones.  Those are a quarter of every XCD, too few
+    // for a leaf gathered on one XCD: the panels keep their leaves spread.
     auto gemms = [&](int part, int nt, hipStream_t sx) -> int {
         GemmArgs *pp = dprob + (size_t)part * 9 * nt0;
         int *pr = dpre + (size_t)part * 9 * (nt0 + 1);

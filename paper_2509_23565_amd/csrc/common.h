@@ -260,13 +260,15 @@ int launch_fill_int(int *p, int v, int count, hipStream_t stream);
 // Panel factorization (recursive, see panel.hip) of the rows x jb block at
 // A (global row/column row0); ws: panel_scratch_bytes(rows) bytes; status:
 // the device status word (EMU_STATUS_PANEL_WAIT on an aborted tall leaf);
-// pivot = false: no interchanges (ipiv receives the identity).
+// pivot = false: no interchanges (ipiv receives the identity); one_xcd =
+// false: leaves of several workgroups stay spread over the XCDs (for callers
+// whose concurrent kernels keep compute units of every XCD occupied).
 size_t panel_scratch_bytes(int rows);
 // Launch multi-workgroup panel leaves cooperatively (process-wide switch).
 void set_leaf_cooperative(int on);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
                  int row0, int *info, char *ws, int *status, hipStream_t stream,
-                 bool pivot = true);
+                 bool pivot = true, bool one_xcd = true);
 // Lower Cholesky of the rows x jb panel at A (its top jb x jb block on the
 // diagonal; global column col0), FP64; *info receives the first column
 // (1-based, global) whose pivot is not positive, if it is still 0.

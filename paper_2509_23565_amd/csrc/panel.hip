@@ -818,6 +818,7 @@ struct PanelRun {
     int *status;
     unsigned arrivals;
     bool pivot;
+    bool one_xcd;                   // leaves of at most LF_XCD_MAX_G workgroups on one XCD
 };
 
 // Multi-workgroup leaves are plain launches unless this is set.  Their
@@ -862,12 +863,12 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
         void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
         EMU_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NTg), args, 0, st));
     } else if (narrow) {
-        x.xs = G <= LF_XCD_MAX_G ? LF_XCDS : 1;
+        x.xs = pr.one_xcd && G <= LF_XCD_MAX_G ? LF_XCDS : 1;
         hipLaunchKernelGGL((k_leaf<true, LF_THREADS / 2>), dim3(G * x.xs), dim3(NTg), 0, st,
                            P, lda, rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
     } else {
-        x.xs = G <= LF_XCD_MAX_G ? LF_XCDS : 1;
+        x.xs = pr.one_xcd && G <= LF_XCD_MAX_G ? LF_XCDS : 1;
         hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G * x.xs), dim3(NTg), 0, st,
                            P, lda, rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
@@ -910,8 +911,8 @@ static unsigned leaf_tag_base(int cols) {
 }
 
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv, int row0, int *info,
-                 char *ws, int *status, hipStream_t stream, bool pivot) {
-    PanelRun pr{ws, status, rows > LF_ROWS ? leaf_tag_base(jb) : 0u, pivot};
+                 char *ws, int *status, hipStream_t stream, bool pivot, bool one_xcd) {
+    PanelRun pr{ws, status, rows > LF_ROWS ? leaf_tag_base(jb) : 0u, pivot, one_xcd};
     if (rows > LF_ROWS) {
         // record words (tag 0: not yet written) and the abort flag start at
         // zero (a fill kernel, not a memset)
