@@ -256,10 +256,16 @@ def test_getrf_lookahead_changes_no_bit(m, n, nb, s):
     assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
 
 
-def test_getrf_cooperative_leaves_change_no_bit():
+@pytest.mark.parametrize("m,n,nb,s", [(6000, 700, 128, 3), (16384, 96, 32, 3),
+                                      (17000, 64, 32, 3)])
+def test_getrf_cooperative_leaves_change_no_bit(m, n, nb, s):
     # tall leaves (several workgroups) launched cooperatively against the
-    # plain launch; both with the look-ahead running beside them
-    m, n, nb, s = 6000, 700, 128, 3
+    # plain launch; both with the look-ahead running beside them.  The
+    # plain launch gathers leaves of at most 16 workgroups (16384 rows) on
+    # one XCD and exchanges their records with plain stores from the
+    # second column on; the cooperative one spreads them and uses
+    # device-scope stores throughout; 17000 rows: 17 workgroups, spread in
+    # both.  The tall-skinny cases also match the oracle bit for bit.
     A = emu.colmajor(matgen.phi_matrix(m, n, 1.0, seed=23))
     A0 = A.clone()
     try:
@@ -272,6 +278,12 @@ def test_getrf_cooperative_leaves_change_no_bit():
     assert emu.status() == 0
     assert torch.equal(ip0, ip1) and torch.equal(inf0, inf1)
     assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
+    if n < 128:
+        LU, piv, inf = O.getrf(np.asfortranarray(matgen.phi_matrix(m, n, 1.0, seed=23)),
+                               nb=nb, s=s)
+        assert int(_host(inf1)[0]) == inf
+        assert np.array_equal(_host(ip1), piv)
+        assert _same_bits(_host(A), LU)
 
 
 def _same_or_both_nan(a, b):
