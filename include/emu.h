@@ -327,6 +327,14 @@ int emu_dgetrs(int n, int nrhs, const double *LU, int lda, const int *ipiv,
  *   hipLaunchCooperativeKernel instead of a plain launch.  The factors are
  *   identical either way; the plain launch avoids the cooperative launch's
  *   fixed cost.
+ *   "leaf_one_xcd" (0 or 1, default 1): plain launches of
+ *   such leaves with at most 16 workgroups (at most 16384 rows) place all
+ *   of them on one XCD, where their exchange of pivot candidates is about
+ *   twice as fast; they then need 16 compute units of that XCD at once.
+ *   Callers that keep part of every XCD busy for long stretches beside the
+ *   factorization (persistent kernels on other streams) should set 0, or
+ *   the leaves' bounded waits may run out (EMU_STATUS_PANEL_WAIT).
+ *   emu_dgetrf_adaptive spreads its leaves regardless.  Factors identical.
  * Returns -1 for an unknown key, -2 for an invalid value.
  */
 int emu_set_param(const char *key, long long value);

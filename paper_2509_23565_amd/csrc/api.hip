@@ -854,6 +854,11 @@ int emu_set_param(const char *key, long long value) {
         set_leaf_cooperative((int)value);
         return 0;
     }
+    if (std::strcmp(key, "leaf_one_xcd") == 0) {
+        if (value != 0 && value != 1) return -2;
+        set_leaf_one_xcd((int)value);
+        return 0;
+    }
     if (std::strcmp(key, "batched_tile") == 0) {
         if (value != 0 && value != 1) return -2;
         set_batched_tile((int)value);

@@ -264,8 +264,10 @@ int launch_fill_int(int *p, int v, int count, hipStream_t stream);
 // false: leaves of several workgroups stay spread over the XCDs (for callers
 // whose concurrent kernels keep compute units of every XCD occupied).
 size_t panel_scratch_bytes(int rows);
-// Launch multi-workgroup panel leaves cooperatively (process-wide switch).
+// Launch multi-workgroup panel leaves cooperatively (calling thread's switch).
 void set_leaf_cooperative(int on);
+// Gather leaves of at most 16 workgroups on one XCD (calling thread's switch, default on).
+void set_leaf_one_xcd(int on);
 int launch_panel(double *A, long long lda, int rows, int jb, int *ipiv,
                  int row0, int *info, char *ws, int *status, hipStream_t stream,
                  bool pivot = true, bool one_xcd = true);

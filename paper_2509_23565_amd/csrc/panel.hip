@@ -827,8 +827,15 @@ struct PanelRun {
 // without them, so a workgroup that waits for one not yet started waits at
 // most that long, well inside the bounded wait.  A cooperative launch gives
 // the same guarantee at a cost of tens of microseconds per launch.
-static bool g_leaf_cooperative = false;
+static thread_local bool g_leaf_cooperative = false;
 void set_leaf_cooperative(int on) { g_leaf_cooperative = on != 0; }
+
+// Leaves of at most LF_XCD_MAX_G workgroups gathered on one XCD unless this
+// is cleared: they then need that many compute units of one XCD at once,
+// which kernels that hold part of every XCD for their whole run (persistent
+// launches on other streams) can withhold until they end.
+static thread_local bool g_leaf_one_xcd = true;
+void set_leaf_one_xcd(int on) { g_leaf_one_xcd = on != 0; }
 
 static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0, int *info,
                 int ncl, int ncr, PanelRun &pr, hipStream_t st) {
@@ -863,12 +870,12 @@ static int leaf(double *P, long long lda, int rows, int w, int *ipiv, int grow0,
         void *args[] = {&P, &lda, &rows, &w, &ipiv, &grow0, &info, &x, &base, &ncl, &ncr};
         EMU_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NTg), args, 0, st));
     } else if (narrow) {
-        x.xs = pr.one_xcd && G <= LF_XCD_MAX_G ? LF_XCDS : 1;
+        x.xs = pr.one_xcd && g_leaf_one_xcd && G <= LF_XCD_MAX_G ? LF_XCDS : 1;
         hipLaunchKernelGGL((k_leaf<true, LF_THREADS / 2>), dim3(G * x.xs), dim3(NTg), 0, st,
                            P, lda, rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());
     } else {
-        x.xs = pr.one_xcd && G <= LF_XCD_MAX_G ? LF_XCDS : 1;
+        x.xs = pr.one_xcd && g_leaf_one_xcd && G <= LF_XCD_MAX_G ? LF_XCDS : 1;
         hipLaunchKernelGGL((k_leaf<true, LF_THREADS>), dim3(G * x.xs), dim3(NTg), 0, st,
                            P, lda, rows, w, ipiv, grow0, info, x, base, ncl, ncr);
         EMU_TRY_HIP(hipGetLastError());

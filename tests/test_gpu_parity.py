@@ -263,9 +263,10 @@ def test_getrf_cooperative_leaves_change_no_bit(m, n, nb, s):
     # plain launch; both with the look-ahead running beside them.  The
     # plain launch gathers leaves of at most 16 workgroups (16384 rows) on
     # one XCD and exchanges their records with plain stores from the
-    # second column on; the cooperative one spreads them and uses
-    # device-scope stores throughout; 17000 rows: 17 workgroups, spread in
-    # both.  The tall-skinny cases also match the oracle bit for bit.
+    # second column on; the cooperative one, and the plain one with
+    # leaf_one_xcd = 0, spread them and use device-scope stores throughout;
+    # 17000 rows: 17 workgroups, spread in all three.  The tall-skinny cases
+    # also match the oracle bit for bit.
     A = emu.colmajor(matgen.phi_matrix(m, n, 1.0, seed=23))
     A0 = A.clone()
     try:
@@ -278,6 +279,16 @@ def test_getrf_cooperative_leaves_change_no_bit(m, n, nb, s):
     assert emu.status() == 0
     assert torch.equal(ip0, ip1) and torch.equal(inf0, inf1)
     assert torch.equal(A0.view(torch.int64), A.view(torch.int64))
+    # plain launches kept spread over the XCDs
+    A2 = emu.colmajor(matgen.phi_matrix(m, n, 1.0, seed=23))
+    try:
+        emu.set_param("leaf_one_xcd", 0)
+        ip2, inf2 = emu.dgetrf(A2, nb=nb, nslices=s)
+    finally:
+        emu.set_param("leaf_one_xcd", 1)
+    assert emu.status() == 0
+    assert torch.equal(ip2, ip1) and torch.equal(inf2, inf1)
+    assert torch.equal(A2.view(torch.int64), A.view(torch.int64))
     if n < 128:
         LU, piv, inf = O.getrf(np.asfortranarray(matgen.phi_matrix(m, n, 1.0, seed=23)),
                                nb=nb, s=s)

@@ -57,10 +57,12 @@ def test_dgemm_argument_errors(args, code):
 
 
 def test_dgemm_unsupported_slice_count():
-    # 1..16 slices are accepted (on a machine without a GPU the call then
-    # fails in the runtime, 1001); all-pairs thresholds stop at s = 5
+    # 1..16 slices are accepted: with m = 0 the call returns 0 after its
+    # argument and support checks, before any device work (the dummy
+    # pointers must never reach a kernel); all-pairs thresholds stop at s = 5
     for s in (10, 12, 16):
-        assert emu.emu_dgemm(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, s) not in (-12, 1003)
+        assert emu.emu_dgemm(0, 4, 4, 1.0, _p(), 1, _p(), 4, 0.0, _p(), 1, s) == 0
+    assert emu.emu_dgemm(0, 4, 4, 1.0, _p(), 1, _p(), 4, 0.0, _p(), 1, 17) == -12
     assert emu.emu_dgemm_t(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 7, 14) == 1003
     assert emu.emu_dgemm_t(4, 4, 4, 1.0, _p(), 4, _p(), 4, 0.0, _p(), 4, 3, 7) == -13
 
@@ -77,7 +79,7 @@ def test_lu_argument_errors():
     assert emu.emu_dgetrs(4, -1, _p(), 4, _p(), _p(), 4) == -2
     assert emu.emu_dgetrs(4, 1, _p(), 4, _p(), _p(), 2) == -7
     assert emu.emu_status(None) == -1
-    for key in ("lu_pivot", "lu_update", "gemm_map"):
+    for key in ("lu_pivot", "lu_update", "gemm_map", "leaf_cooperative", "leaf_one_xcd"):
         assert emu.emu_set_param(key.encode(), 2) == -2
 
 
