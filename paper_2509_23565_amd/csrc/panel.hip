@@ -810,9 +810,9 @@ static LeafX leaf_x(char *ws, int *status) {
     return x;
 }
 
-// One panel factorization: scratch, status word, and the columns the
-// multi-workgroup leaves of this panel have finished so far (record sequence
-// numbers continue from there; they are zeroed once per panel).
+// One panel factorization: scratch, status word, and the record tag base:
+// the panel's first tag (from leaf_tag_base) plus the columns its
+// multi-workgroup leaves have finished so far.
 struct PanelRun {
     char *ws;
     int *status;
